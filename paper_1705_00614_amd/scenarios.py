@@ -1,0 +1,160 @@
+"""Seeded synthetic inputs for the shallow-water solver.
+
+This module only draws inputs (terrain, roughness, initial water, inlet and
+hydrograph parameters); it holds none of the scheme's arithmetic, so both the
+GPU library and the CPU oracle used by the tests can take their inputs from
+it.  The real inputs of arXiv 1705.00614 (the Volga-Akhtuba digital terrain
+model, hydrographs and gauge records, Sec. 2.2 and Sec. 5) are not available;
+these generators stand in for them with the shapes the paper describes:
+floodplain relief of a few metres cut by a deep meandering river bed, 25-50 m
+cells, depths from centimetres to tens of metres, a large inflow from a
+hydraulic structure, and a water/land ratio between a few and ~60 %.
+
+Every scenario is a dict with keys
+    nx, ny, h              grid and cell size [m]
+    b, n_manning           (ny, nx) float64 bed elevation [m] and Manning n
+    solid                  (ny, nx) uint8 closed-gate mask or None
+    H0, Qx0, Qy0           (ny, nx) float64 initial depth and unit discharge
+    params                 dict of physical and numerical constants
+Random numbers come from NumPy's PCG64 generator seeded explicitly.
+"""
+import math
+
+import numpy as np
+
+G = 9.81
+# Wind drag coefficient C_a rho_a / rho with C_a = 1.3e-3, rho_a = 1.225,
+# rho = 1000 (typical open-water values; the paper names the factors only).
+WIND_KAPPA = 1.3e-3 * 1.225 / 1000.0
+# Coriolis parameter 2 Omega sin(phi) at about 48.7 N (Volgograd region).
+F_COR = 2.0 * 7.2921e-5 * math.sin(math.radians(48.7))
+
+
+def base_params(**over):
+    p = dict(g=G, courant=0.4, eps=1e-4, tau_max=0.0, tau_min=0.0, nu=0.0,
+             f_cor=0.0, wind_x=0.0, wind_y=0.0, wind_kappa=0.0, h_wind=0.1,
+             limiter=0, inlet=None, q_base=0.0, q_peak=0.0, t_peak=0.0,
+             sigma_t=0.0, precision=32)
+    p.update(over)
+    return p
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def fbm(ny, nx, hurst, seed, relief):
+    """Fractional-Brownian relief by spectral synthesis: white noise, Fourier
+    amplitudes scaled by |k|^-(hurst+1) with the mean mode removed, inverse
+    transform, then scaled to [0, relief] metres."""
+    noise = _rng(seed).standard_normal((ny, nx))
+    spec = np.fft.rfft2(noise)
+    ky = np.fft.fftfreq(ny)[:, None]
+    kx = np.fft.rfftfreq(nx)[None, :]
+    k = np.sqrt(kx * kx + ky * ky)
+    amp = np.zeros_like(k)
+    amp[k > 0] = k[k > 0] ** (-(hurst + 1.0))
+    z = np.fft.irfft2(spec * amp, s=(ny, nx))
+    z -= z.min()
+    z *= relief / max(z.max(), 1e-30)
+    return z
+
+
+def _centreline(n, h, rng):
+    """Meandering river centre y_c(x) = L/2 + sum_k A_k sin(2 pi x/lambda_k + phi_k)."""
+    L = n * h
+    A = (rng.uniform(0.10, 0.20) * L, rng.uniform(0.02, 0.05) * L)
+    lam = (rng.uniform(0.25, 0.50) * L, rng.uniform(0.08, 0.15) * L)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=2)
+    x = (np.arange(n) + 0.5) * h
+    yc = 0.5 * L + sum(A[k] * np.sin(2 * math.pi * x / lam[k] + phi[k]) for k in range(2))
+    dyc = sum(A[k] * 2 * math.pi / lam[k] * np.cos(2 * math.pi * x / lam[k] + phi[k])
+              for k in range(2))
+    return yc, dyc
+
+
+def floodplain_terrain(n, h=25.0, seed=0, relief=15.0, hurst=0.8,
+                       channel_depth=8.0, channel_half_width=100.0):
+    """fBm floodplain with a carved meandering channel draining in +x.
+
+    Returns (b, n_manning, channel_mask, yc) with the channel bed at the
+    running minimum (downstream) of the relief along the centre line minus
+    channel_depth."""
+    rng = _rng(seed)
+    z = fbm(n, n, hurst, rng.integers(2**63), relief)
+    yc, dyc = _centreline(n, h, rng)
+    y = (np.arange(n) + 0.5) * h
+    dist = np.abs(y[:, None] - yc[None, :]) / np.sqrt(1.0 + dyc[None, :] ** 2)
+    chan = dist <= channel_half_width
+    jc = np.clip(np.floor(yc / h).astype(int), 0, n - 1)
+    zc = z[jc, np.arange(n)]
+    bed = np.minimum.accumulate(zc) - channel_depth
+    b = np.where(chan, np.minimum(z, bed[None, :]), z)
+    nm = np.where(chan, 0.03, 0.05)
+    return b, nm, chan, yc
+
+
+def floodplain(n=4096, h=25.0, seed=0, steps=10000, q_peak=3.0e4, t_peak=3600.0,
+               sigma_t=1200.0, inlet_cells=40, fill=4.0, precision=32):
+    """Synthetic floodplain flood: dry floodplain, channel filled to `fill`
+    metres, Gaussian inflow over an inlet_cells^2 inlet on the channel at its
+    upstream end, walls all round, wind, Coriolis, turbulent viscosity."""
+    b, nm, chan, yc = floodplain_terrain(n, h, seed)
+    H0 = np.where(chan, fill, 0.0)
+    ni = min(inlet_cells, n)
+    jc = int(yc[min(ni // 2, n - 1)] / h)
+    j0 = int(np.clip(jc - ni // 2, 0, n - ni))
+    prm = base_params(tau_max=2.0, nu=0.5, f_cor=F_COR, wind_x=5.0, wind_y=2.0,
+                      wind_kappa=WIND_KAPPA, inlet=(0, j0, ni, ni), q_base=0.0,
+                      q_peak=q_peak, t_peak=t_peak, sigma_t=sigma_t, precision=precision)
+    return dict(name="floodplain-%d" % n, nx=n, ny=n, h=h, b=b, n_manning=nm, solid=None,
+                H0=H0, Qx0=np.zeros_like(b), Qy0=np.zeros_like(b), params=prm, steps=steps)
+
+
+def floodplain_wet(n=4096, h=25.0, seed=0, percentile=60.0, precision=32):
+    """Fully wet control on the same terrain: still water with its level at
+    the given percentile of the bed, so that about that share of cells is wet."""
+    sc = floodplain(n, h, seed, precision=precision)
+    eta0 = float(np.percentile(sc["b"], percentile))
+    sc["H0"] = np.maximum(eta0 - sc["b"], 0.0)
+    sc["name"] = "floodplain-wet-%d" % n
+    return sc
+
+
+def dam_break(nx=256, ny=256, h=1.0, x_dam=128.0, h_left=2.0, h_right=0.5,
+              precision=64):
+    """Idealised dam break on a flat frictionless bed, water at rest."""
+    x = (np.arange(nx) + 0.5) * h
+    H0 = np.where(x < x_dam, h_left, h_right)[None, :].repeat(ny, axis=0)
+    z = np.zeros((ny, nx))
+    return dict(name="dam-break-%dx%d" % (nx, ny), nx=nx, ny=ny, h=h, b=z.copy(),
+                n_manning=z.copy(), solid=None, H0=H0.astype(np.float64),
+                Qx0=z.copy(), Qy0=z.copy(), params=base_params(precision=precision),
+                steps=200)
+
+
+def lake_at_rest(n=64, h=10.0, seed=3, relief=8.0, eta0=5.0, precision=64):
+    """Still lake over rough fBm relief whose peaks rise above the surface."""
+    b = fbm(n, n, 0.8, seed, relief)
+    H0 = np.maximum(eta0 - b, 0.0)
+    z = np.zeros_like(b)
+    return dict(name="lake-%d" % n, nx=n, ny=n, h=h, b=b, n_manning=np.full_like(b, 0.03),
+                solid=None, H0=H0, Qx0=z.copy(), Qy0=z.copy(),
+                params=base_params(precision=precision, nu=0.5), steps=1000)
+
+
+def random_state(nx, ny, h=5.0, seed=0, wet_frac=0.6, precision=32, **prm):
+    """Rough random wet/dry state with random velocities (stencil stress test)."""
+    rng = _rng(seed)
+    b = fbm(ny, nx, 0.7, rng.integers(2**63), 4.0)
+    eta0 = float(np.quantile(b, wet_frac))
+    H0 = np.maximum(eta0 - b, 0.0) * rng.uniform(0.7, 1.3, size=b.shape)
+    wet = H0 > 1e-3
+    Qx0 = np.where(wet, H0 * rng.normal(0.0, 0.5, size=b.shape), 0.0)
+    Qy0 = np.where(wet, H0 * rng.normal(0.0, 0.5, size=b.shape), 0.0)
+    nm = rng.uniform(0.02, 0.06, size=b.shape)
+    p = base_params(precision=precision, nu=0.5, f_cor=F_COR, wind_x=5.0, wind_y=-3.0,
+                    wind_kappa=WIND_KAPPA, tau_max=1.0)
+    p.update(prm)
+    return dict(name="random-%dx%d" % (nx, ny), nx=nx, ny=ny, h=h, b=b, n_manning=nm,
+                solid=None, H0=H0, Qx0=Qx0, Qy0=Qy0, params=p, steps=200)
