@@ -1,0 +1,141 @@
+/*
+ * swe.h -- C ABI of the MI355X (gfx950) CSPH-TVD shallow-water library
+ * (libswe_hip.so).
+ *
+ * The library advances the Saint-Venant equations of arXiv 1705.00614
+ * (Sec. 2.1, Eqs. 1-4: continuity with sources sigma, momentum with the
+ * free-surface gradient, Manning bottom friction, turbulent viscosity,
+ * Coriolis and wind forces) with the four-stage CSPH-TVD step of Sec. 2.3:
+ *   I   forces at t_n and the CFL time step tau_n,
+ *   II  Lagrangian predictor-corrector of the cell-centred particles,
+ *   III TVD reconstruction and approximate-Riemann mass and momentum fluxes
+ *       through the Euler-cell faces,
+ *   IV  final update with the particles put back at the cell centres,
+ * skipping tiles without water (Sec. 3, kernels K1 and K8).  All of it runs
+ * in hand-written HIP kernels on the GPU; the host only launches them.
+ *
+ * Conventions
+ *   - Host arrays are FP64, row-major with x fastest: cell (i, j) at index
+ *     j*nx + i, centre at ((i+1/2) dx, (j+1/2) dx).  The caller owns every
+ *     array and the params struct; swe_create copies what it needs and keeps
+ *     no caller pointer.
+ *   - The handle is owned by the library until swe_destroy.  One handle is
+ *     used by one host thread at a time; all its GPU work is ordered on the
+ *     stream given at creation (the caller's hipStream_t, e.g. torch's
+ *     current stream; NULL means a stream the library creates).
+ *   - The state lives in device memory (HBM) between calls; only the get/set
+ *     calls and the scalar queries copy to or from the host.
+ *   - Errors: functions returning int give 0 or a negative SWE_E* code;
+ *     swe_create returns NULL; the message is in swe_last_error().  After a
+ *     device-side error (non-finite state, time-step collapse) the handle
+ *     stops advancing until swe_set_state installs a new state.
+ *   - Domain edges are reflective walls.  A closed gate (solid cell) is a
+ *     permanently dry cell whose bed is far above any water level.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_OK            0
+#define SWE_EINVAL      (-1)   /* invalid argument */
+#define SWE_ENOMEM      (-2)   /* device or host allocation failed */
+#define SWE_EHIP        (-3)   /* a HIP runtime call failed */
+#define SWE_ENONFINITE  (-4)   /* the state became NaN or infinite */
+#define SWE_EDTCOLLAPSE (-5)   /* the CFL time step fell below dt_min */
+
+typedef struct swe_s swe_t;
+
+typedef struct {
+    int    precision;    /* 32: FP32 stencil, 64: FP64 stencil.  Volume,
+                            time and the hydrograph integral are FP64 always. */
+    double g;            /* gravitational acceleration [m/s^2] */
+    double cfl;          /* Courant number K, 0 < K < 1 (Sec. 2.3) */
+    double eps;          /* wet threshold: a cell is wet iff H > eps [m] */
+    double dt_max;       /* upper bound of tau [s]; <= 0: none */
+    double dt_min;       /* a CFL step below this is SWE_EDTCOLLAPSE [s] */
+    double nu;           /* turbulent viscosity [m^2/s] */
+    double f_coriolis;   /* 2 Omega sin(latitude) [1/s] */
+    double wind_x, wind_y; /* wind velocity W [m/s] */
+    double wind_kappa;   /* C_a rho_a / rho of the wind force */
+    double h_wind;       /* depth floor of the wind force [m] */
+    int    limiter;      /* 0 minmod, 1 van Leer, 2 monotonised central */
+    int    skip_dry;     /* 1: skip tiles without water (results identical) */
+    int    tile_x, tile_y; /* tile shape; 0,0 = default for the precision */
+    int    inlet_i0, inlet_j0, inlet_ni, inlet_nj; /* source rectangle; ni or
+                            nj = 0: no source.  Must lie inside the grid and
+                            contain no closed gate. */
+    double q_base, q_peak, t_peak, sigma_t; /* Gaussian hydrograph
+                            Q(t) = q_base + (q_peak-q_base) exp(-(t-t_peak)^2/(2 sigma_t^2))
+                            [m^3/s], [s]; spread evenly over the inlet cells */
+    const uint8_t* solid;  /* nx*ny closed-gate mask or NULL (copied) */
+    const double* H0;      /* nx*ny initial depth >= 0, or NULL: dry */
+    const double* Qx0;     /* nx*ny initial unit discharge H*Ux or NULL */
+    const double* Qy0;     /* nx*ny initial unit discharge H*Uy or NULL */
+    void*  stream;         /* hipStream_t owned by the caller, or NULL */
+} swe_params;
+
+/* Create a solver on an nx x ny grid of cell size dx [m] with bed elevation
+ * b [m] and Manning coefficient n_M (both nx*ny, host FP64; n_M may be NULL
+ * for no friction).  Allocates the state in device memory, uploads the
+ * inputs, and computes the wet tiles and the first time step from layer 0.
+ * Returns NULL on error (see swe_last_error). */
+swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
+                  const swe_params* p);
+
+/* Advance one CSPH-TVD step (Sec. 2.3 stages I-IV).  Synchronises the
+ * stream.  Returns 0 or SWE_E*. */
+int    swe_step(swe_t* s);
+
+/* Advance nsteps steps: device-side time step, no host round trip inside,
+ * steps replayed from a captured hipGraph.  Synchronises at the end.  Stops
+ * advancing at the first device error and returns it. */
+int    swe_run(swe_t* s, long nsteps);
+
+/* Water volume dx^2 * sum(H) [m^3], reduced on the GPU in FP64 in a fixed
+ * order; NaN on error. */
+double swe_mass(swe_t* s);
+
+/* Free the handle and its device memory.  NULL-safe. */
+void   swe_destroy(swe_t* s);
+
+/* Copy the current state to host FP64 arrays (nx*ny each; any may be NULL). */
+int    swe_get_state(swe_t* s, double* H, double* Qx, double* Qy);
+
+/* Install a new state (H >= 0; Qx, Qy may be NULL for rest), e.g. a
+ * checkpoint.  Clears a device error and recomputes the wet tiles and the
+ * next time step.  Time, step count, inflow and ledger are kept. */
+int    swe_set_state(swe_t* s, const double* H, const double* Qx, const double* Qy);
+
+double swe_time(swe_t* s);     /* simulated time [s] (FP64) */
+double swe_last_dt(swe_t* s);  /* time step of the last completed step [s] */
+double swe_next_dt(swe_t* s);  /* time step the next step will take [s] */
+double swe_ledger(swe_t* s);   /* volume added by clamping negative depths [m^3] */
+double swe_inflow(swe_t* s);   /* volume delivered by the hydrograph [m^3] (FP64) */
+long   swe_steps(swe_t* s);    /* completed steps */
+
+/* Work counters since creation: processed tile-steps, processed in-domain
+ * cell-steps and tile count of the grid.  Any pointer may be NULL. */
+int    swe_work(swe_t* s, long long* tile_steps, long long* cell_steps,
+                int* ntiles, int* tile_x, int* tile_y);
+
+/* Tiles the next step will process (row-major tile indices, unordered),
+ * at most cap entries; returns the count or SWE_E*. */
+int    swe_active_tiles(swe_t* s, int* out, int cap);
+
+/* nsteps steps launched one by one with a HIP event pair around each step
+ * kernel on the handle's stream; *kernel_ms receives the summed kernel time
+ * [ms].  For measurement. */
+int    swe_run_timed(swe_t* s, long nsteps, double* kernel_ms);
+
+/* Message of the last error on this host thread ("" if none). */
+const char* swe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -345,9 +345,13 @@ static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
 /* Time step from layer n (Sec. 2.3, stage I):
  *   U_s = max(|Ux|, |Uy|) + sqrt(g H),
  *   U_p = max(|Ux + sgn(Fx) sqrt(h|Fx|)|, |Uy + sgn(Fy) sqrt(h|Fy|)|),
- * F the non-pressure force of Eq. (4) with friction at U^n, maximum over wet
- * cells, tau = min(tau_max, K h / max(U_s, U_p), h^2/(4 nu)); a bound whose
- * divisor is zero is left out. */
+ * maximum over wet cells, tau = min(tau_max, K h / max(U_s, U_p),
+ * h^2/(4 nu)); a bound whose divisor is zero is left out.  Reading: F is the
+ * explicitly integrated part of the Eq. (4) force (viscosity, Coriolis,
+ * wind).  Friction enters the step through a point-implicit factor that can
+ * only slow a particle down, never reverse it, so it sets no explicit limit;
+ * counting it would let films just above eps (friction ~ H^(-4/3)) dictate
+ * the time step. */
 static double cfl_tau(orc_sim* s)
 {
     const orc_params* p = &s->p;
@@ -359,9 +363,6 @@ static double cfl_tau(orc_sim* s)
             double ux = s->Ux[c], uy = s->Uy[c];
             double fx, fy;
             soft_forces(s, c, s->Ux, s->Uy, &fx, &fy);
-            double lam = s->lam0[c] * sqrt(ux * ux + uy * uy);
-            fx -= lam * ux;
-            fy -= lam * uy;
             double us = fmax(fabs(ux), fabs(uy)) + sqrt(p->g * s->H[c]);
             double upx = fabs(ux + sgn(fx) * sqrt(s->h * fabs(fx)));
             double upy = fabs(uy + sgn(fy) * sqrt(s->h * fabs(fy)));

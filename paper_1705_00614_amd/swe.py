@@ -1,0 +1,246 @@
+"""Python binding of libswe_hip.so (argument marshalling only).
+
+Every step of the CSPH-TVD path runs in the library's HIP kernels on the GPU;
+this module converts NumPy arrays to the C ABI of ``include/swe.h`` and back.
+PyTorch is used, when present, only to hand the library the caller's current
+HIP stream.  There is no CPU fallback: if the library is missing, importing
+the binding raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe_hip.so")
+
+SWE_OK, SWE_EINVAL, SWE_ENOMEM, SWE_EHIP, SWE_ENONFINITE, SWE_EDTCOLLAPSE = 0, -1, -2, -3, -4, -5
+_ERRNAME = {-1: "SWE_EINVAL", -2: "SWE_ENOMEM", -3: "SWE_EHIP", -4: "SWE_ENONFINITE",
+            -5: "SWE_EDTCOLLAPSE"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class SweParams(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int), ("g", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("eps", ctypes.c_double), ("dt_max", ctypes.c_double), ("dt_min", ctypes.c_double),
+        ("nu", ctypes.c_double), ("f_coriolis", ctypes.c_double),
+        ("wind_x", ctypes.c_double), ("wind_y", ctypes.c_double),
+        ("wind_kappa", ctypes.c_double), ("h_wind", ctypes.c_double),
+        ("limiter", ctypes.c_int), ("skip_dry", ctypes.c_int),
+        ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+        ("inlet_i0", ctypes.c_int), ("inlet_j0", ctypes.c_int),
+        ("inlet_ni", ctypes.c_int), ("inlet_nj", ctypes.c_int),
+        ("q_base", ctypes.c_double), ("q_peak", ctypes.c_double),
+        ("t_peak", ctypes.c_double), ("sigma_t", ctypes.c_double),
+        ("solid", ctypes.POINTER(ctypes.c_uint8)), ("H0", _dp), ("Qx0", _dp), ("Qy0", _dp),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+# Every function declared in include/swe.h, with its ctypes signature.
+EXPORTS = {
+    "swe_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
+                                     ctypes.POINTER(SweParams)]),
+    "swe_step": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
+    "swe_mass": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_destroy": (None, [ctypes.c_void_p]),
+    "swe_get_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "swe_set_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "swe_time": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_last_dt": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_next_dt": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_ledger": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
+    "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
+    "swe_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "swe_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "swe_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
+    "swe_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libswe_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch is imported first so that the process holds a single HIP
+        # runtime (torch's) and torch's streams are valid handles for it
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libswe_hip.so is not built (run paper_1705_00614_amd/build.py); "
+                              "there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return load().swe_last_error().decode()
+
+
+class SweError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_ERRNAME.get(code, code), msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise SweError(rc, last_error())
+    return rc
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def current_stream():
+    """The caller's current HIP stream from torch, or None (library stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+def make_params(prm, skip_dry=True, tile=(0, 0), stream=None):
+    inlet = prm.get("inlet") or (0, 0, 0, 0)
+    p = SweParams()
+    p.precision = int(prm.get("precision", 32))
+    p.g = prm["g"]
+    p.cfl = prm["courant"]
+    p.eps = prm["eps"]
+    p.dt_max = prm.get("tau_max", 0.0)
+    p.dt_min = prm.get("tau_min", 0.0)
+    p.nu = prm.get("nu", 0.0)
+    p.f_coriolis = prm.get("f_cor", 0.0)
+    p.wind_x = prm.get("wind_x", 0.0)
+    p.wind_y = prm.get("wind_y", 0.0)
+    p.wind_kappa = prm.get("wind_kappa", 0.0)
+    p.h_wind = prm.get("h_wind", 0.1)
+    p.limiter = int(prm.get("limiter", 0))
+    p.skip_dry = int(bool(skip_dry))
+    p.tile_x, p.tile_y = int(tile[0]), int(tile[1])
+    p.inlet_i0, p.inlet_j0, p.inlet_ni, p.inlet_nj = (int(v) for v in inlet)
+    p.q_base = prm.get("q_base", 0.0)
+    p.q_peak = prm.get("q_peak", 0.0)
+    p.t_peak = prm.get("t_peak", 0.0)
+    p.sigma_t = prm.get("sigma_t", 0.0)
+    p.stream = stream
+    return p
+
+
+class Solver:
+    """A GPU solver handle built from a scenario dict (keys nx, ny, h, b,
+    n_manning, solid, H0, Qx0, Qy0, params)."""
+
+    def __init__(self, sc, skip_dry=True, tile=(0, 0), precision=None, stream="torch"):
+        L = load()
+        self.nx, self.ny, self.h = int(sc["nx"]), int(sc["ny"]), float(sc["h"])
+        shp = (self.ny, self.nx)
+        prm = dict(sc["params"])
+        if precision is not None:
+            prm["precision"] = precision
+        st = current_stream() if stream == "torch" else stream
+        p = make_params(prm, skip_dry, tile, st)
+        b = _f64(sc["b"], shp)
+        nm = _f64(sc.get("n_manning"), shp)
+        H0, Qx0, Qy0 = (_f64(sc.get(k), shp) for k in ("H0", "Qx0", "Qy0"))
+        solid = sc.get("solid")
+        solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+        p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
+        self._h = L.swe_create(self.nx, self.ny, self.h, _ptr(b), _ptr(nm), ctypes.byref(p))
+        if not self._h:
+            raise SweError(SWE_EINVAL, last_error())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self):
+        return _check(load().swe_step(self._h))
+
+    def run(self, n):
+        return _check(load().swe_run(self._h, int(n)))
+
+    def run_rc(self, n):
+        return load().swe_run(self._h, int(n))
+
+    def run_timed(self, n):
+        ms = ctypes.c_double(0.0)
+        _check(load().swe_run_timed(self._h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def mass(self):
+        return load().swe_mass(self._h)
+
+    def time(self):
+        return load().swe_time(self._h)
+
+    def last_dt(self):
+        return load().swe_last_dt(self._h)
+
+    def next_dt(self):
+        return load().swe_next_dt(self._h)
+
+    def ledger(self):
+        return load().swe_ledger(self._h)
+
+    def inflow(self):
+        return load().swe_inflow(self._h)
+
+    def steps(self):
+        return load().swe_steps(self._h)
+
+    def state(self):
+        shp = (self.ny, self.nx)
+        H, Qx, Qy = (np.empty(shp) for _ in range(3))
+        _check(load().swe_get_state(self._h, _ptr(H), _ptr(Qx), _ptr(Qy)))
+        return H, Qx, Qy
+
+    def set_state(self, H, Qx=None, Qy=None):
+        shp = (self.ny, self.nx)
+        H, Qx, Qy = (_f64(a, shp) for a in (H, Qx, Qy))
+        return _check(load().swe_set_state(self._h, _ptr(H), _ptr(Qx), _ptr(Qy)))
+
+    def work(self):
+        t, c = ctypes.c_longlong(), ctypes.c_longlong()
+        n, tx, ty = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().swe_work(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(n),
+                               ctypes.byref(tx), ctypes.byref(ty)))
+        return dict(tile_steps=t.value, cell_steps=c.value, ntiles=n.value, tile=(tx.value, ty.value))
+
+    def active_tiles(self):
+        n = self.work()["ntiles"]
+        buf = (ctypes.c_int * max(n, 1))()
+        cnt = load().swe_active_tiles(self._h, buf, n)
+        if cnt < 0:
+            _check(cnt)
+        return np.sort(np.array(buf[:cnt], dtype=np.int64))

@@ -427,14 +427,19 @@ def test_time_step_formula_on_hand_built_states():
     assert abs(sim.next_tau() - K * h / math.sqrt(g * 4.0)) < 1e-14
     sim = orc.OracleSim(_uniform(4, 4, h, 4.0, ux=3.0, uy=-1.0), periodic=True)
     assert abs(sim.next_tau() - K * h / (3.0 + math.sqrt(g * 4.0))) < 1e-14
-    # friction force F = -c|U|U/H^(4/3) enters U_p = |U + sgn(F) sqrt(h|F|)|
+    # friction is point-implicit and does not limit the step, even on a film
     nM = 0.2
     sim = orc.OracleSim(_uniform(4, 4, h, 0.04, ux=-2.0, n_manning=np.full((4, 4), nM)),
                         periodic=True)
-    F = g * nM * nM * 2.0 * 2.0 / 0.04 ** (4 / 3)        # positive (opposes ux < 0)
-    up = abs(-2.0 + math.sqrt(h * F))
-    us = 2.0 + math.sqrt(g * 0.04)
-    assert abs(sim.next_tau() - K * h / max(up, us)) < 1e-13
+    assert abs(sim.next_tau() - K * h / (2.0 + math.sqrt(g * 0.04))) < 1e-14
+    # wind force F = kappa (W-U)|W-U|/max(H, h_w) enters U_p = |U + sgn(F) sqrt(h|F|)|
+    kap, W = 0.05, 30.0
+    sim = orc.OracleSim(_uniform(4, 4, h, 0.5, ux=0.5, wind_x=W, wind_kappa=kap), periodic=True)
+    F = kap * (W - 0.5) ** 2 / 0.5
+    up = 0.5 + math.sqrt(h * F)
+    us = 0.5 + math.sqrt(g * 0.5)
+    assert up > us
+    assert abs(sim.next_tau() - K * h / up) < 1e-13
     # viscous and tau_max caps, dry domain
     sim = orc.OracleSim(_uniform(4, 4, h, 4.0, nu=50.0), periodic=True)
     assert abs(sim.next_tau() - h * h / (4 * 50.0)) < 1e-14
