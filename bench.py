@@ -1,0 +1,146 @@
+"""Benchmark: CSPH-TVD steps of the 4096^2 synthetic floodplain on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload floodplain|wet]
+                [--no-cpu] [--cpu-steps S]
+
+One step = one CSPH-TVD time step (arXiv 1705.00614, Sec. 2.3 stages I-IV:
+forces and CFL time step, Lagrangian predictor-corrector, TVD Riemann fluxes,
+final update, plus the wet-tile bookkeeping of K1) over the whole grid, with
+the inputs resident in HBM.  W untimed steps advance the flood, then exactly
+K steps are timed, bracketed by torch.cuda.synchronize() and HIP events on
+the stream the library launches on.  Prints ONE JSON line.
+
+value        active-cell updates per second: in-domain cells of the tiles the
+             step kernel processes (the dry-tile skip removes the rest)
+roofline     the step kernel: algorithmic bytes (32 B per processed FP32 cell:
+             reads H, Qx, Qy, b, c_f; writes H, Qx, Qy) per launch over its
+             mean launch duration, from per-launch HIP events over the timed
+             steps, against the 8 TB/s HBM peak
+cpu_baseline the FP64 CPU oracle on the host, a bounded sample of the same
+             workload (its first steps from the initial state, every cell)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {32: 32, 64: 64}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9900)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", choices=["floodplain", "wet"], default="floodplain")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--tile", default="0x0")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--graph", action="store_true",
+                    help="time hipGraph replays instead of per-launch events (no roofline)")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, steps):
+    from oracle import oracle
+    t0 = time.perf_counter()
+    sim = oracle.OracleSim(sc)
+    t1 = time.perf_counter()
+    sim.run(steps)
+    t2 = time.perf_counter()
+    cells = sc["nx"] * sc["ny"] * steps
+    return {"value": cells / (t2 - t1) / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the same %dx%d workload from its initial state, FP64, every "
+                      "cell each step (the oracle has no dry-tile skip); %.1f s of CPU time, setup "
+                      "%.1f s excluded" % (steps, sc["nx"], sc["ny"], t2 - t1, t1 - t0)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(the multi-GPU decomposition is a design, not a measured path)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1705_00614_amd import scenarios as S
+    from paper_1705_00614_amd import swe
+
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    mk = S.floodplain if args.workload == "floodplain" else S.floodplain_wet
+    sc = mk(n=args.n, seed=0)
+    prec = sc["params"]["precision"]
+    stream = torch.cuda.Stream()          # default priority, not the null stream
+    with torch.cuda.stream(stream):
+        g = swe.Solver(sc, tile=tile)
+        V0 = g.mass()
+        g.run(args.warmup)
+        torch.cuda.synchronize()
+        w0, t_sim0 = g.work(), g.time()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        e0.record(stream)
+        if args.graph:
+            g.run(args.steps)
+            kernel_ms = None
+        else:
+            kernel_ms = g.run_timed(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        w1, t_sim1 = g.work(), g.time()
+        ev_ms = e0.elapsed_time(e1)
+        V, inflow, ledger = g.mass(), g.inflow(), g.ledger()
+    wall = c1 - c0
+    secs = max(ev_ms * 1e-3, 1e-12)
+    cells = w1["cell_steps"] - w0["cell_steps"]
+    tiles = w1["tile_steps"] - w0["tile_steps"]
+    grid_cells = sc["nx"] * sc["ny"] * args.steps
+    out = {
+        "metric": "Gcell-updates/s + HBM GB/s fraction; learned-coarse vs fine time at <=2% depth err",
+        "value": cells / secs / 1e9,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ev_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == 32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s %dx%d, dx=%g m, %s stencil, FP64 volume and inflow; steps %d..%d of the flood"
+                        % (sc["name"], sc["nx"], sc["ny"], sc["h"], "FP32" if prec == 32 else "FP64",
+                           args.warmup, args.warmup + args.steps),
+            "tile": list(w1["tile"]),
+            "active_tile_fraction": tiles / args.steps / w1["ntiles"],
+            "grid_cell_updates_per_s": grid_cells / secs / 1e9,
+            "simulated_seconds": t_sim1 - t_sim0,
+            "wall_seconds": wall,
+            "timing": "hipGraph replay" if args.graph else "per-launch HIP events",
+            "volume_balance_rel": abs(V - V0 - inflow - ledger) / max(V, 1e-300),
+        },
+    }
+    if kernel_ms is not None:
+        alg_bytes = BYTES_PER_CELL[prec] * cells
+        achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "swe::k_step<%s,%d,%d>" % ("float" if prec == 32 else "double",
+                                                                w1["tile"][0], w1["tile"][1]),
+                           "mean_launch_us": kernel_ms * 1e3 / args.steps,
+                           "bytes_per_launch": alg_bytes / args.steps}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -111,6 +111,10 @@ int    swe_get_state(swe_t* s, double* H, double* Qx, double* Qy);
  * next time step.  Time, step count, inflow and ledger are kept. */
 int    swe_set_state(swe_t* s, const double* H, const double* Qx, const double* Qy);
 
+/* Set the simulated clock (restoring a checkpoint together with
+ * swe_set_state); recomputes the next hydrograph volume.  t finite. */
+int    swe_set_time(swe_t* s, double t);
+
 double swe_time(swe_t* s);     /* simulated time [s] (FP64) */
 double swe_last_dt(swe_t* s);  /* time step of the last completed step [s] */
 double swe_next_dt(swe_t* s);  /* time step the next step will take [s] */

@@ -269,9 +269,16 @@ orc_sim* orc_create(int nx, int ny, double h, const double* b,
 /* ------------------------------------------------------------------ */
 
 /* Pressure gradient G = grad(eta*) at every interior wet cell (SPH stage,
- * Sec. 2.3).  Reading for a dry neighbour m of a wet cell c: it contributes
- * eta*_m = min(eta_c, max(b_m, b_c)), i.e. a dry bank above the surface exerts
- * no push and a dry cell below the own bed counts as the own bed. */
+ * Sec. 2.3).  Reading of the level eta*_m that a neighbour m shows to a wet
+ * cell c, after the hydrostatic-reconstruction principle behind the paper's
+ * regularisation-free wet/dry fronts: a neighbour pushes with at most its own
+ * depth above c's surface and never from below c's bed,
+ *     eta*_m = max(b_c, min(eta_m, eta_c + H_m)),
+ * with H_m = 0, eta_m = b_m for a dry neighbour (which gives
+ * min(eta_c, max(b_m, b_c)): a dry bank above the surface exerts no push, a
+ * dry cell below the own bed counts as the own bed).  Over a flat bed and in
+ * a lake at rest eta*_m = eta_m; a film on a high bank pushes with its film
+ * depth only, so the force is continuous as the film crosses eps. */
 static void pressure_gradient(orc_sim* s)
 {
     const double al = sph_alpha(), be = sph_beta(), ih = 1.0 / s->h;
@@ -280,13 +287,15 @@ static void pressure_gradient(orc_sim* s)
         for (int i = 0; i < s->nx; ++i) {
             long c = P(s, i, j);
             if (!s->wet[c]) { s->Gx[c] = s->Gy[c] = 0.0; continue; }
+            const double ec = s->eta[c], bc = s->b[c];
             double e[9];
             int q = 0;
             for (int dj = -1; dj <= 1; ++dj)
                 for (int di = -1; di <= 1; ++di) {
                     long m = c + dj * px + di;
-                    if (s->wet[m]) e[q] = s->eta[m];
-                    else e[q] = fmin(s->eta[c], fmax(s->b[m], s->b[c]));
+                    double Hm = s->wet[m] ? s->H[m] : 0.0;
+                    double em = s->wet[m] ? s->eta[m] : s->b[m];
+                    e[q] = fmax(bc, fmin(em, ec + Hm));
                     ++q;
                 }
             /* e[0]=SW e[1]=S e[2]=SE e[3]=W e[4]=C e[5]=E e[6]=NW e[7]=N e[8]=NE */

@@ -521,6 +521,19 @@ int swe_set_state(swe_t* s, const double* H, const double* Qx, const double* Qy)
     return set_state_impl(s, H, Qx, Qy, s->solid.empty() ? nullptr : s->solid.data());
 }
 
+int swe_set_time(swe_t* s, double t) {
+    if (!s || !std::isfinite(t)) { set_err("swe_set_time: invalid arguments"); return SWE_EINVAL; }
+    Ctrl c;
+    int rc = sync_ctrl(s, &c);
+    if (rc) return rc;
+    char* cb = (char*)s->ctrl;
+    HIPCHK(hipMemcpyAsync(cb + offsetof(Ctrl, t), &t, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    // the next source volume depends on the clock: recompute the layer scalars
+    s->launched = c.step;
+    return prepare(s);
+}
+
 double swe_mass(swe_t* s) {
     if (!s) return NAN;
     hipLaunchKernelGGL(swe::k_sum_tiles, dim3(1), dim3(1024), 0, s->stream, s->mass, s->ntiles, s->scalar);

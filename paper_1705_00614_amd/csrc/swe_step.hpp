@@ -345,9 +345,14 @@ __global__ __launch_bounds__(NT) void k_step(Args<real> a) {
             real e[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
+                // level a neighbour shows: it pushes with at most its own depth
+                // above the own surface and never from below the own bed (a dry
+                // neighbour has depth 0 and level = its bed)
                 const int m = s + (q / 3 - 1) * W + (q % 3 - 1);
-                const real Hm = A0[m], bm = A1[m];
-                e[q] = WET[m] ? Hm + bm : rmin(ec, rmax(bm, bc));
+                const bool wm = WET[m];
+                const real Hm = wm ? A0[m] : real(0);
+                const real em = wm ? A0[m] + A1[m] : A1[m];
+                e[q] = rmax(bc, rmin(em, ec + Hm));
             }
             // e: 0 SW 1 S 2 SE 3 W 4 C 5 E 6 NW 7 N 8 NE
             const real Gx = (al * (e[5] - e[3]) + be * ((e[8] - e[6]) + (e[2] - e[0]))) * a.ih;

@@ -49,6 +49,7 @@ EXPORTS = {
     "swe_destroy": (None, [ctypes.c_void_p]),
     "swe_get_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_set_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "swe_set_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "swe_time": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_last_dt": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_next_dt": (ctypes.c_double, [ctypes.c_void_p]),
@@ -229,6 +230,9 @@ class Solver:
         shp = (self.ny, self.nx)
         H, Qx, Qy = (_f64(a, shp) for a in (H, Qx, Qy))
         return _check(load().swe_set_state(self._h, _ptr(H), _ptr(Qx), _ptr(Qy)))
+
+    def set_time(self, t):
+        return _check(load().swe_set_time(self._h, float(t)))
 
     def work(self):
         t, c = ctypes.c_longlong(), ctypes.c_longlong()

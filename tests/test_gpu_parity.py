@@ -1,0 +1,312 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 stencil -- relative L1 <= 1e-10 (the same arithmetic up to
+rounding order); FP32 stencil -- relative L1 in H and HU <= 1e-4 after 200
+steps and relative volume drift <= 1e-6.  Invariance tests (dry-tile skipping,
+tile shapes, graph replay, checkpoint/resume, run-to-run) are bitwise.
+Paper: arXiv 1705.00614, Sec. 2.1 (Eqs. 1-4), Sec. 2.3, Sec. 3 (K1, K8).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1705_00614_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+swe = pytest.importorskip("paper_1705_00614_amd.swe")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu] %s" % request.node.nodeid, flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def rel_l1(a, b):
+    den = np.abs(b).sum()
+    return np.abs(a - b).sum() / (den if den > 0 else 1.0)
+
+
+def compare(sc, steps, prec, tol_H, tol_Q, tile=(0, 0), skip=True):
+    sc = dict(sc)
+    sc["params"] = dict(sc["params"], precision=prec)
+    o = orc.OracleSim(sc)
+    g = swe.Solver(sc, skip_dry=skip, tile=tile)
+    m0 = g.mass()
+    o.run(steps)
+    g.run(steps)
+    H, Qx, Qy = g.state()
+    Ho, Qxo, Qyo = o.state()
+    eH = rel_l1(H, Ho)
+    eQ = (np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum()) / max(np.abs(Qxo).sum() + np.abs(Qyo).sum(), 1e-300)
+    assert g.steps() == steps
+    assert abs(g.time() - o.time()) <= max(tol_H, 1e-12) * o.time() + 1e-12
+    assert eH <= tol_H, eH
+    assert eQ <= tol_Q, eQ
+    V = g.mass()
+    drift = abs(V - m0 - g.inflow() - g.ledger()) / max(V, 1e-300)
+    return g, o, drift
+
+
+# ------------------------------------------------------------------ C1 and friends
+
+def test_dam_break_fp64_matches_oracle():
+    g, o, drift = compare(S.dam_break(precision=64), 200, 64, 1e-10, 1e-10)
+    assert drift < 1e-13
+    # Stoker middle depth reached
+    assert abs(g.state()[0][128, 150] - 1.1035) < 2e-3
+
+
+def test_dam_break_fp32_matches_oracle():
+    g, o, drift = compare(S.dam_break(precision=32), 200, 32, 1e-4, 1e-4)
+    assert drift < 1e-6
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_floodplain_fp32_200_steps(n):
+    g, o, drift = compare(S.floodplain(n=n, seed=1), 200, 32, 1e-4, 1e-4)
+    assert drift <= 1e-6
+
+
+def test_floodplain_fp64_200_steps():
+    g, o, drift = compare(S.floodplain(n=128, seed=2, precision=64), 200, 64, 1e-10, 1e-10)
+    assert drift < 1e-12
+
+
+@pytest.mark.parametrize("lim", [0, 1, 2])
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+def test_random_state_all_forces_all_limiters(lim, prec, tol):
+    sc = S.random_state(70, 45, seed=5 + lim, limiter=lim)
+    compare(sc, 60, prec, tol, tol)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (5, 7), (33, 17), (77, 45)])
+def test_ragged_and_tiny_grids_fp64(shape):
+    nx, ny = shape
+    sc = S.random_state(nx, ny, seed=nx * 31 + ny)
+    compare(sc, 25, 64, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("tile", [(32, 32), (64, 16), (32, 16), (16, 16)])
+def test_every_tile_shape_fp32_matches_oracle(tile):
+    sc = S.random_state(90, 70, seed=9)
+    compare(sc, 40, 32, 1e-4, 1e-4, tile=tile)
+
+
+def test_gates_fp64_match_oracle_and_stay_dry():
+    sc = S.dam_break(nx=64, ny=24, h=1.0, precision=64)
+    solid = np.zeros((24, 64), np.uint8)
+    solid[:, 40] = 1
+    solid[10:14, 40] = 0          # an open gate in a closed wall
+    solid[3, 20] = solid[17, 25] = 1
+    sc["solid"] = solid
+    g, o, drift = compare(sc, 120, 64, 1e-10, 1e-10)
+    assert np.all(g.state()[0][solid == 1] == 0.0)
+
+
+def test_lake_at_rest_fp32_stays_still():
+    sc = S.lake_at_rest(n=96, precision=32)
+    g = swe.Solver(sc)
+    g.run(1000)
+    H, Qx, Qy = g.state()
+    wet = H > 1e-4
+    assert np.abs((H + sc["b"].astype(np.float32) - 5.0)[wet]).max() <= 1e-5
+    assert (np.hypot(Qx, Qy)[wet] / H[wet]).max() <= 1e-4
+
+
+def test_all_dry_domain_uses_dt_max_and_changes_nothing():
+    sc = S.floodplain(n=64, seed=3)
+    sc["H0"] = np.zeros_like(sc["H0"])
+    sc["params"] = dict(sc["params"], inlet=None)
+    g = swe.Solver(sc)
+    assert g.active_tiles().size == 0
+    g.run(10)
+    assert abs(g.time() - 20.0) < 1e-12 and g.next_dt() == 2.0
+    assert np.all(g.state()[0] == 0.0) and g.mass() == 0.0
+
+
+# ------------------------------------------------------------------ invariances (bitwise)
+
+def _final_state(sc, steps, **kw):
+    g = swe.Solver(sc, **kw)
+    g.run(steps)
+    return g.state(), g.time()
+
+
+def test_skip_dry_is_bitwise_identical():
+    sc = S.floodplain(n=192, seed=4)
+    (a, ta) = _final_state(sc, 150, skip_dry=True)
+    (b, tb) = _final_state(sc, 150, skip_dry=False)
+    assert ta == tb
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_tile_shapes_are_bitwise_identical():
+    sc = S.floodplain(n=160, seed=6)
+    ref, tr = _final_state(sc, 80, tile=(32, 32))
+    for tile in [(64, 16), (32, 16), (16, 16)]:
+        st, t = _final_state(sc, 80, tile=tile)
+        assert t == tr
+        for x, y in zip(st, ref):
+            assert np.array_equal(x, y), tile
+
+
+def test_graph_replay_equals_single_steps_and_reruns():
+    sc = S.floodplain(n=128, seed=7)
+    g1 = swe.Solver(sc)
+    g1.run(96)                       # graph replays
+    g2 = swe.Solver(sc)
+    for _ in range(96):
+        g2.step()                    # one launch per step
+    g3 = swe.Solver(sc)
+    g3.run_timed(96)                 # event-timed launches
+    s1, s2, s3 = g1.state(), g2.state(), g3.state()
+    for x, y, z in zip(s1, s2, s3):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    assert g1.time() == g2.time() == g3.time()
+    assert g1.mass() == g2.mass()
+
+
+def test_checkpoint_resume_is_bitwise():
+    sc = S.floodplain(n=128, seed=8)
+    g = swe.Solver(sc)
+    g.run(37)
+    ck = g.state()
+    t_ck = g.time()
+    g.run(50)
+    final = g.state()
+    r = swe.Solver(sc)
+    r.set_state(*ck)
+    r.set_time(t_ck)
+    r.run(50)
+    for x, y in zip(r.state(), final):
+        assert np.array_equal(x, y)
+    # restoring on the same handle works too
+    g.set_state(*ck)
+    g.set_time(t_ck)
+    g.run(50)
+    for x, y in zip(g.state(), final):
+        assert np.array_equal(x, y)
+
+
+def test_active_tiles_follow_the_k1_rule_fp64():
+    """Tiles processed at step n+1 are exactly the K1-active tiles of layers
+    n+1 and n (a tile that just dried is processed once more so that both
+    state buffers hold its final layer)."""
+    sc = S.floodplain(n=200, seed=5, precision=64)
+    g = swe.Solver(sc, tile=(16, 16))
+    o = orc.OracleSim(sc)
+    tx = ty = 16
+    p = sc["params"]["inlet"]
+    src = np.zeros((200, 200), bool)
+    src[p[1]:p[1] + p[3], p[0]:p[0] + p[2]] = True
+    prev = None
+    for k in range(30):
+        own, ring = orc.tile_flags(o.state()[0], tx, ty, 1e-4, src)
+        act = np.flatnonzero((own | ring).ravel())
+        expect = act if prev is None else np.union1d(act, prev)
+        assert np.array_equal(g.active_tiles(), expect), k
+        prev = act
+        o.step()
+        g.step()
+    assert 0 < len(prev) < own.size
+
+
+# ------------------------------------------------------------------ FP64 accumulators
+
+def test_volume_sum_is_fp64_accurate():
+    sc = S.floodplain(n=256, seed=9)
+    g = swe.Solver(sc)
+    g.run(100)
+    H = g.state()[0]
+    exact = math.fsum(H.ravel().tolist()) * sc["h"] ** 2
+    assert abs(g.mass() - exact) <= 1e-13 * exact
+
+
+def test_inflow_integral_is_fp64_accurate():
+    sc = S.floodplain(n=128, seed=10)
+    g = swe.Solver(sc)
+    g.run(300)
+    p = sc["params"]
+    t = g.time()
+    k = 1.0 / (p["sigma_t"] * math.sqrt(2.0))
+    exact = p["q_base"] * t + (p["q_peak"] - p["q_base"]) * p["sigma_t"] * math.sqrt(math.pi / 2) * (
+        math.erf((t - p["t_peak"]) * k) - math.erf((0.0 - p["t_peak"]) * k))
+    assert abs(g.inflow() - exact) <= 1e-11 * exact
+
+
+# ------------------------------------------------------------------ errors (host-forced)
+
+def test_invalid_arguments_are_rejected():
+    sc = S.dam_break(nx=16, ny=8)
+    bad = [dict(nx=0), dict(h=0.0), dict(h=-1.0)]
+    for b in bad:
+        s2 = dict(sc, **b)
+        if s2["nx"] == 0:
+            s2["b"] = np.zeros((8, 0))
+            s2["H0"] = s2["Qx0"] = s2["Qy0"] = s2["n_manning"] = None
+        with pytest.raises((swe.SweError, ValueError)):
+            swe.Solver(s2)
+    for prm in [dict(courant=1.5), dict(eps=0.0), dict(precision=16), dict(limiter=7),
+                dict(inlet=(10, 0, 10, 2))]:
+        s2 = dict(sc, params=dict(sc["params"], **prm))
+        with pytest.raises(swe.SweError):
+            swe.Solver(s2)
+    with pytest.raises(swe.SweError):
+        swe.Solver(sc, tile=(7, 9))
+    H = sc["H0"].copy()
+    H[0, 0] = -1.0
+    with pytest.raises(swe.SweError):
+        swe.Solver(dict(sc, H0=H))
+    swe.load().swe_destroy(None)
+
+
+def test_nonfinite_state_is_reported_and_recoverable():
+    sc = S.dam_break(nx=32, ny=32, precision=32)
+    g = swe.Solver(sc)
+    H = sc["H0"].copy()
+    H[10, 10] = 3.0e38                    # overflows FP32 in the first step
+    g.set_state(H)
+    assert g.run_rc(5) == swe.SWE_ENONFINITE
+    assert g.run_rc(1) == swe.SWE_ENONFINITE  # the handle stays stopped
+    g.set_state(sc["H0"])
+    g.run(5)
+    assert np.isfinite(g.state()[0]).all()
+
+
+def test_dt_collapse_is_reported():
+    sc = S.dam_break(nx=32, ny=32)
+    sc["params"] = dict(sc["params"], tau_min=10.0)
+    g = swe.Solver(sc)
+    assert g.run_rc(3) == swe.SWE_EDTCOLLAPSE
+    assert g.steps() == 0
+
+
+# ------------------------------------------------------------------ full size
+
+def test_full_size_floodplain_first_steps_match_oracle():
+    """The 4096^2 floodplain in the launch configuration the benchmark times
+    (FP32, skipping on, default tile): first steps against the oracle on the
+    whole grid, then a long run against the volume balance."""
+    sc = S.floodplain(n=4096, seed=0)
+    g = swe.Solver(sc)
+    o = orc.OracleSim(sc)
+    m0 = g.mass()
+    assert abs(m0 - o.mass()) <= 1e-6 * o.mass()
+    o.run(3)
+    g.run(3)
+    H, Qx, Qy = g.state()
+    Ho, Qxo, Qyo = o.state()
+    assert rel_l1(H, Ho) <= 1e-4
+    assert (np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum()) / (np.abs(Qxo).sum() + np.abs(Qyo).sum()) <= 1e-4
+    del o
+    g.run(997)
+    V = g.mass()
+    assert abs(V - m0 - g.inflow() - g.ledger()) <= 1e-6 * V
+    assert g.work()["tile_steps"] < 0.2 * 1000 * g.work()["ntiles"]
