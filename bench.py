@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--graph", action="store_true",
                     help="time hipGraph replays instead of per-launch events (no roofline)")
     return ap.parse_args()

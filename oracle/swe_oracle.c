@@ -546,12 +546,14 @@ static void fluxes(orc_sim* s)
 
 /* H' = Ht + tau/h (net inflow through the 4 faces), H = max(H', 0) with the
  * clamp booked in the ledger; Q = Qt + tau/h (net momentum inflow) where
- * H > eps, else 0 (K8 fragment: dev_h, dev_hv; reading of their bodies). */
-static void final_update(orc_sim* s, double tau)
+ * H > eps, else 0 (K8 fragment: dev_h, dev_hv; reading of their bodies).
+ * Returns 1 if any updated value was NaN or infinite before the clamps. */
+static int final_update(orc_sim* s, double tau)
 {
     const double r = tau / s->h, eps = s->p.eps, h2 = s->h * s->h;
     const int nx = s->nx;
     double ledger = 0.0;
+    int bad = 0;
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < nx; ++i) {
             long c = P(s, i, j);
@@ -560,6 +562,7 @@ static void final_update(orc_sim* s, double tau)
             double Hn = s->Ht[c] + r * ((s->FxH[fw] - s->FxH[fe]) + (s->FyH[fs] - s->FyH[fn]));
             double qx = s->Qtx[c] + r * ((s->FxQn[fw] - s->FxQn[fe]) + (s->FyQt[fs] - s->FyQt[fn]));
             double qy = s->Qty[c] + r * ((s->FxQt[fw] - s->FxQt[fe]) + (s->FyQn[fs] - s->FyQn[fn]));
+            if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) bad = 1;
             double Hc = fmax(Hn, 0.0);
             ledger += h2 * (Hc - Hn);
             int w = Hc > eps;
@@ -568,6 +571,7 @@ static void final_update(orc_sim* s, double tau)
             s->Qy[c] = w ? qy : 0.0;
         }
     s->ledger += ledger;
+    return bad;
 }
 
 /* ------------------------------------------------------------------ */
@@ -614,12 +618,12 @@ static int step_with(orc_sim* s, double tau)
     }
     post_lagrangian(s, sdepth);
     fluxes(s);
-    final_update(s, tau);
+    int bad = final_update(s, tau);
     s->t += tau;
     s->inflow += dV;
     s->tau_last = tau;
     s->steps++;
-    return finite_state(s) ? 0 : ORC_ENONFINITE;
+    return (!bad && finite_state(s)) ? 0 : ORC_ENONFINITE;
 }
 
 int orc_step(orc_sim* s)

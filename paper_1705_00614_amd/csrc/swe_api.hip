@@ -44,17 +44,17 @@ void set_hip_err(const char* where, hipError_t e) {
 constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even)
 
 struct Launcher {
-    int tx, ty, nt, precision;
+    int tx, ty, nt, precision, limiter;
     hipError_t (*step)(const void* args, int grid, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
     hipError_t (*prepare_finish)(const void* args, hipStream_t st);
     int (*occupancy)(int* blocks);
 };
 
-template <typename real, int TX, int TY, int NT>
+template <typename real, int TX, int TY, int NT, int LIM>
 hipError_t launch_step(const void* args, int grid, hipStream_t st) {
     const Args<real>& a = *static_cast<const Args<real>*>(args);
-    hipLaunchKernelGGL((swe::k_step<real, TX, TY, NT>), dim3(grid), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM>), dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 template <typename real, int TX, int TY, int NT>
@@ -69,29 +69,31 @@ hipError_t launch_prepare_finish(const void* args, hipStream_t st) {
     hipLaunchKernelGGL((swe::k_prepare_finish<real>), dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
 }
-template <typename real, int TX, int TY, int NT>
+template <typename real, int TX, int TY, int NT, int LIM>
 int occupancy(int* blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT>, NT, 0) ==
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT, LIM>, NT, 0) ==
                    hipSuccess ? 0 : -1;
 }
 
-#define LAUNCHER(real, TX, TY, NT, P)                                                    \
-    Launcher{TX, TY, NT, P, launch_step<real, TX, TY, NT>, launch_prepare<real, TX, TY, NT>, \
-             launch_prepare_finish<real>, occupancy<real, TX, TY, NT>}
+#define LAUNCHER(real, TX, TY, NT, P, LIM)                                                       \
+    Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM>, launch_prepare<real, TX, TY, NT>, \
+             launch_prepare_finish<real>, occupancy<real, TX, TY, NT, LIM>}
+#define LAUNCHERS(real, TX, TY, NT, P) \
+    LAUNCHER(real, TX, TY, NT, P, 0), LAUNCHER(real, TX, TY, NT, P, 1), LAUNCHER(real, TX, TY, NT, P, 2)
 
-// Tile shapes compiled in; the first of each precision is its default.
+// Tile shapes compiled in, each with the three limiters; the first shape of
+// each precision is its default.
 const Launcher kLaunchers[] = {
-    LAUNCHER(float, 32, 32, 512, 32),
-    LAUNCHER(float, 64, 16, 512, 32),
-    LAUNCHER(float, 32, 16, 256, 32),
-    LAUNCHER(float, 16, 16, 256, 32),
-    LAUNCHER(double, 16, 16, 256, 64),
-    LAUNCHER(double, 32, 16, 256, 64),
+    LAUNCHERS(float, 32, 32, 512, 32),
+    LAUNCHERS(float, 64, 16, 512, 32),
+    LAUNCHERS(float, 16, 16, 256, 32),
+    LAUNCHERS(double, 16, 16, 256, 64),
+    LAUNCHERS(double, 32, 16, 256, 64),
 };
 
-const Launcher* find_launcher(int precision, int tx, int ty) {
+const Launcher* find_launcher(int precision, int tx, int ty, int limiter) {
     for (const Launcher& l : kLaunchers) {
-        if (l.precision != precision) continue;
+        if (l.precision != precision || l.limiter != limiter) continue;
         if ((tx == 0 && ty == 0) || (l.tx == tx && l.ty == ty)) return &l;
     }
     return nullptr;
@@ -327,7 +329,7 @@ swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
         !std::isfinite(p->dt_max)) {
         set_err("swe_create: invalid physical or numerical parameter"); return nullptr;
     }
-    const Launcher* L = find_launcher(p->precision, p->tile_x, p->tile_y);
+    const Launcher* L = find_launcher(p->precision, p->tile_x, p->tile_y, p->limiter);
     if (!L) { set_err("swe_create: tile shape not available for this precision"); return nullptr; }
     const size_t n = (size_t)nx * ny;
     for (size_t i = 0; i < n; ++i) {

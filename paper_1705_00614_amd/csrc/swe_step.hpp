@@ -13,11 +13,18 @@
 //           Manning factor) and the predictor U^{n+1/2} on tile + 4
 //   P2      forces at t_{n+1/2}, corrector U^L, sources, post-Lagrangian
 //           state on tile + 3
-//   FX, FY  limited reconstruction and hydrostatic Rusanov fluxes through the
-//           x faces, then the y faces, of tile + 1
-//   final   H, Q at t_{n+1} on tile + 1 (written to HBM for the tile)
+//   FX      limited reconstruction and hydrostatic Rusanov fluxes through the
+//           x faces of tile + 1
+//   FY      the same through the y faces, fused with the final update of
+//           tile + 1 (written to HBM for the tile)
 //   epi     CFL speed of layer n+1 on the tile (needs the ring of tile + 1),
 //           wet bits, FP64 volume and clamp partials
+//
+// Work layout: in P1, P2 and FX a thread owns a run of 4 cells along x, in FY
+// a run of 4 cells along y, so neighbour values and limited slopes are loaded
+// and computed once per run instead of once per use.  Lanes of a wave stride
+// LDS rows (row pitch odd) or columns, which keeps LDS accesses free of bank
+// conflicts.  Wet/dry decisions are selects, not branches.
 //
 // The tile list of the next step is built by the workgroups themselves
 // (atomic de-duplicated append), and the last workgroup to finish turns the
@@ -31,6 +38,7 @@
 namespace swe {
 
 constexpr int HALO = 5;
+constexpr int RUN = 4;
 constexpr double GATE_BED = 1.0e6;
 
 // Device-resident control block of a simulation.
@@ -76,21 +84,24 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-    // x^(-4/3) for x > 0 via the hardware base-2 logarithm and exponential
-    static __device__ __forceinline__ float pow_m43(float x) {
-        return __builtin_amdgcn_exp2f(-1.33333333f * __builtin_amdgcn_logf(x));
+    // c_f / H^(4/3) for H > 0 via the hardware base-2 logarithm and exponential
+    static __device__ __forceinline__ float friction(float cf, float H) {
+        return cf * __builtin_amdgcn_exp2f(-1.33333333f * __builtin_amdgcn_logf(H));
     }
 };
 template <> struct Mth<double> {
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-    static __device__ __forceinline__ double pow_m43(double x) { return 1.0 / (x * ::cbrt(x)); }
+    static __device__ __forceinline__ double friction(double cf, double H) { return cf / (H * ::cbrt(H)); }
 };
 
 template <typename real> __device__ __forceinline__ real rmax(real a, real b) { return a > b ? a : b; }
 template <typename real> __device__ __forceinline__ real rmin(real a, real b) { return a < b ? a : b; }
 template <typename real> __device__ __forceinline__ real rabs(real a) { return a < real(0) ? -a : a; }
+// false for NaN and +-inf (compare against the largest finite value)
+__device__ __forceinline__ bool finite(float a) { return rabs(a) <= 3.40282347e38f; }
+__device__ __forceinline__ bool finite(double a) { return rabs(a) <= 1.7976931348623157e308; }
 
 // Reflect a global index into [0, n) about the end faces; flips counts the
 // reflections (odd: the velocity component normal to that wall changes sign).
@@ -117,48 +128,53 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 
 // ---------------------------------------------------------------- limiter, Riemann
 
-template <typename real>
-__device__ __forceinline__ real limit(int kind, real a, real b) {
-    if (a * b <= real(0)) return real(0);
-    if (kind == 1) return Mth<real>::div(real(2) * a * b, a + b);
-    if (kind == 2) {
-        real m = rmin(rmin(real(2) * rabs(a), real(2) * rabs(b)), real(0.5) * rabs(a + b));
-        return a > real(0) ? m : -m;
+// Limited slope from the backward and forward differences (0 minmod,
+// 1 van Leer, 2 monotonised central).
+template <typename real, int LIM>
+__device__ __forceinline__ real limit(real a, real b) {
+    const bool same = a * b > real(0);
+    real m;
+    if constexpr (LIM == 1) {
+        m = Mth<real>::div(real(2) * a * b, a + b);
+    } else if constexpr (LIM == 2) {
+        const real mm = rmin(rmin(real(2) * rabs(a), real(2) * rabs(b)), real(0.5) * rabs(a + b));
+        m = a > real(0) ? mm : -mm;
+    } else {
+        m = rabs(a) < rabs(b) ? a : b;
     }
-    return rabs(a) < rabs(b) ? a : b;
+    return same ? m : real(0);
 }
 
 template <typename real> struct Face { real H, eta, un, ut; };
 
-// Limited reconstruction on the face of cell c on side `side` (+1: towards
-// c+d, -1: towards c-d) from the post-Lagrangian LDS fields.
-template <typename real>
-__device__ __forceinline__ Face<real> recon(int c, int d, real side, int lim, real eps,
-                                            const real* sHt, const real* sEt, const real* sBed,
-                                            const real* un, const real* ut) {
-    Face<real> f;
-    const real Hc = sHt[c];
-    if (!(Hc > eps)) {
-        f.H = real(0); f.eta = sBed[c]; f.un = real(0); f.ut = real(0);
-        return f;
-    }
-    const int m = c - d, q = c + d;
-    const real Hm = sHt[m], Hq = sHt[q];
-    const real ec = sEt[c];
-    const real sH = limit(lim, Hc - Hm, Hq - Hc);
-    const real sE = limit(lim, ec - sEt[m], sEt[q] - ec);
-    const bool wm = Hm > eps, wq = Hq > eps;
-    const real unc = un[c], utc = ut[c];
-    const real sN = limit(lim, wm ? unc - un[m] : real(0), wq ? un[q] - unc : real(0));
-    const real sT = limit(lim, wm ? utc - ut[m] : real(0), wq ? ut[q] - utc : real(0));
-    const real hs = real(0.5) * side;
-    f.H = rmax(real(0), Hc + hs * sH);
-    f.eta = ec + hs * sE;
-    f.un = unc + hs * sN;
-    f.ut = utc + hs * sT;
-    return f;
+// Post-Lagrangian values of one cell for reconstruction along one axis.
+template <typename real> struct Cell { real H, b, un, ut; };
+
+// Limited reconstruction of cell c on its low (towards m) and high (towards
+// q) faces.  A dry cell (H_t <= eps) shows H = 0, U = 0, eta = b; a dry
+// neighbour contributes a zero velocity difference; face depth >= 0.
+template <typename real, int LIM>
+__device__ __forceinline__ void recon(real eps, const Cell<real>& m, const Cell<real>& c,
+                                      const Cell<real>& q, Face<real>& lo, Face<real>& hi) {
+    const real em = m.H + m.b, ec = c.H + c.b, eq = q.H + q.b;   // eta_t = H_t + b
+    const real sH = limit<real, LIM>(c.H - m.H, q.H - c.H);
+    const real sE = limit<real, LIM>(ec - em, eq - ec);
+    const bool wm = m.H > eps, wq = q.H > eps, wc = c.H > eps;
+    const real sN = limit<real, LIM>(wm ? c.un - m.un : real(0), wq ? q.un - c.un : real(0));
+    const real sT = limit<real, LIM>(wm ? c.ut - m.ut : real(0), wq ? q.ut - c.ut : real(0));
+    const real hH = real(0.5) * sH, hE = real(0.5) * sE, hN = real(0.5) * sN, hT = real(0.5) * sT;
+    hi.H = wc ? rmax(real(0), c.H + hH) : real(0);
+    lo.H = wc ? rmax(real(0), c.H - hH) : real(0);
+    hi.eta = wc ? ec + hE : c.b;
+    lo.eta = wc ? ec - hE : c.b;
+    hi.un = wc ? c.un + hN : real(0);
+    lo.un = wc ? c.un - hN : real(0);
+    hi.ut = wc ? c.ut + hT : real(0);
+    lo.ut = wc ? c.ut - hT : real(0);
 }
 
+// Hydrostatic reconstruction over b* = max(bL, bR) and the Rusanov flux of
+// mass, normal and tangential momentum; L is the lower-index side.
 template <typename real>
 __device__ __forceinline__ void riemann(real g, const Face<real>& L, const Face<real>& R,
                                         real& FH, real& Fn, real& Ft) {
@@ -173,19 +189,23 @@ __device__ __forceinline__ void riemann(real g, const Face<real>& L, const Face<
 
 // ---------------------------------------------------------------- forces
 
-// Viscosity over wet face neighbours + Coriolis + wind at cell s for the
-// velocity field (ux, uy); H is the cell's depth at layer n.
-template <typename real, int W>
-__device__ __forceinline__ void soft_forces(const Args<real>& a, int s, const real* ux, const real* uy,
-                                            const uint8_t* wet, real H, real& fx, real& fy) {
-    const real uxc = ux[s], uyc = uy[s];
+// Velocities of the four face neighbours (order W, E, S, N) and whether each
+// is wet.
+template <typename real> struct Nb4 { real ux[4], uy[4]; bool w[4]; };
+
+// Viscosity over wet face neighbours + Coriolis + wind at a cell with depth
+// H (layer n) and velocity (uxc, uyc).
+template <typename real>
+__device__ __forceinline__ void soft_forces(const Args<real>& a, real H, real uxc, real uyc,
+                                            const Nb4<real>& nb, real& fx, real& fy) {
     real vx = real(0), vy = real(0);
-    if (wet[s - 1]) { vx += ux[s - 1] - uxc; vy += uy[s - 1] - uyc; }
-    if (wet[s + 1]) { vx += ux[s + 1] - uxc; vy += uy[s + 1] - uyc; }
-    if (wet[s - W]) { vx += ux[s - W] - uxc; vy += uy[s - W] - uyc; }
-    if (wet[s + W]) { vx += ux[s + W] - uxc; vy += uy[s + W] - uyc; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        vx += nb.w[k] ? nb.ux[k] - uxc : real(0);
+        vy += nb.w[k] ? nb.uy[k] - uyc : real(0);
+    }
     const real dx = a.wx - uxc, dy = a.wy - uyc;
-    const real k = a.kw * Mth<real>::sqrt(dx * dx + dy * dy) * Mth<real>::rcp(rmax(H, a.hw));
+    const real k = Mth<real>::div(a.kw * Mth<real>::sqrt(dx * dx + dy * dy), rmax(H, a.hw));
     fx = a.nuh2 * vx + a.fcor * uyc + k * dx;
     fy = a.nuh2 * vy - a.fcor * uxc + k * dy;
 }
@@ -247,47 +267,400 @@ __device__ __forceinline__ void enqueue(int tile, int gen, int* stamp, int* list
     if (atomicMax(&stamp[tile], gen) < gen) list[atomicAdd(count, 1)] = tile;
 }
 
+template <typename real>
+__device__ __forceinline__ bool is_src(const Args<real>& a, int gx, int gy) {
+    return (unsigned)(gx - a.i0) < (unsigned)a.ni && (unsigned)(gy - a.j0) < (unsigned)a.nj;
+}
+
+// ---------------------------------------------------------------- LDS of a tile
+
+// Row pitch is odd so that lanes walking down a column hit distinct banks.
+template <int TX, int TY>
+struct Geo {
+    static constexpr int W = (TX + 2 * HALO) | 1;
+    static constexpr int H = TY + 2 * HALO;
+    static constexpr int N = W * H;
+    static __device__ __forceinline__ int at(int x, int y) { return (y + HALO) * W + x + HALO; }
+};
+
+// Ten arrays in one layout, reused across the stages:
+//   H   H^n            -> x-flux F_t (y-momentum)
+//   B   b
+//   UX  Ux^n           -> H_t
+//   UY  Uy^n           -> Ux_t
+//   HX  Ux^{n+1/2}     -> x-flux F_H
+//   HY  Uy^{n+1/2}     -> x-flux F_n (x-momentum)
+//   GX  G_x            -> Qx_t -> Ux^{n+1}
+//   GY  G_y            -> Qy_t -> Uy^{n+1}
+//   LM  c_f/H^(4/3)    -> Uy_t
+//   NH  H^{n+1}
+template <typename real, int TX, int TY>
+struct Lds {
+    real H[Geo<TX, TY>::N], B[Geo<TX, TY>::N], UX[Geo<TX, TY>::N], UY[Geo<TX, TY>::N];
+    real HX[Geo<TX, TY>::N], HY[Geo<TX, TY>::N], GX[Geo<TX, TY>::N], GY[Geo<TX, TY>::N];
+    real LM[Geo<TX, TY>::N], NH[Geo<TX, TY>::N];
+};
+
+// Copy mirror images into the positions of [x0, x1) x [y0, y1) (tile
+// coordinates) that lie outside the domain.  Bit q of sgx / sgy marks array
+// q as the x / y component of a vector (its sign flips across that wall).
+template <typename real, int TX, int TY, int NT>
+__device__ void fill_ghosts(int tx0, int ty0, int nx, int ny, int x0, int x1, int y0, int y1,
+                            real* f0, real* f1, real* f2, int sgx, int sgy) {
+    using G = Geo<TX, TY>;
+    const int w = x1 - x0, n = w * (y1 - y0);
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const int x = x0 + k % w, y = y0 + k / w;
+        const int gx = tx0 + x, gy = ty0 + y;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) continue;
+        int fx = 0, fy = 0;
+        const int mx = mirror(gx, nx, fx) - tx0, my = mirror(gy, ny, fy) - ty0;
+        const int s = G::at(x, y), m = G::at(mx, my);
+        real* fs[3] = {f0, f1, f2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (!fs[q]) continue;
+            const bool neg = (((sgx >> q) & 1) && (fx & 1)) != (((sgy >> q) & 1) && (fy & 1));
+            const real v = fs[q][m];
+            fs[q][s] = neg ? -v : v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- one tile
+
+// bits: 1 own wet, 2 W edge, 4 E edge, 8 S edge, 16 N edge (layer n+1),
+// 32 ring wet (layer n+1), 64 K1-active at layer n
+template <typename real, int TX, int TY, int NT, int LIM, bool EDGE>
+__device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, int ty0,
+                          real tau, real sdep, real& vmax, bool& bad, double& msum, double& lsum,
+                          int& bits) {
+    using G = Geo<TX, TY>;
+    constexpr int W = G::W;
+    const int tid = threadIdx.x, nx = a.nx, ny = a.ny;
+    const real eps = a.eps, half_tau = real(0.5) * tau, r = tau * a.ih;
+    // normalised cubic-B-spline SPH gradient weights (smoothing length h):
+    // al = 1/(12 sqrt2 - 14), be = (3 sqrt2 - 4)/(12 sqrt2 - 14), 2 al + 4 be = 1
+    const real al = real(0.33663655161388173), be = real(0.08168172419305914);
+    auto inside = [&](int x, int y) {
+        if constexpr (!EDGE) return true;
+        const int gx = tx0 + x, gy = ty0 + y;
+        return gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    };
+
+    // ---- load tile + 5
+    {
+        constexpr int RW = TX + 2 * HALO, NL = RW * G::H;
+        int act = 0;
+        for (int k = tid; k < NL; k += NT) {
+            const int x = k % RW - HALO, y = k / RW - HALO;
+            int gx = tx0 + x, gy = ty0 + y, fx = 0, fy = 0;
+            if constexpr (EDGE) { gx = mirror(gx, nx, fx); gy = mirror(gy, ny, fy); }
+            const long gi = (long)gy * nx + gx;
+            const real H = a.Hi[gi];
+            real qx = a.Qxi[gi], qy = a.Qyi[gi];
+            if constexpr (EDGE) { if (fx & 1) qx = -qx; if (fy & 1) qy = -qy; }
+            const bool w = H > eps;
+            const int s = G::at(x, y);
+            L.H[s] = H;
+            L.B[s] = a.bed[gi];
+            L.UX[s] = w ? Mth<real>::div(qx, H) : real(0);
+            L.UY[s] = w ? Mth<real>::div(qy, H) : real(0);
+            // K1 rule at layer n: own cells and outer face neighbours (no corners)
+            const bool own = x >= 0 && x < TX && y >= 0 && y < TY;
+            const bool ring = ((x == -1 || x == TX) && y >= 0 && y < TY) || ((y == -1 || y == TY) && x >= 0 && x < TX);
+            if ((own || ring) && inside(x, y) && (w || is_src(a, tx0 + x, ty0 + y))) act = 1;
+        }
+        if (__syncthreads_or(act)) bits |= 64;
+    }
+
+    // ---- P1: forces at t_n and predictor on tile + 4, runs of 4 along x
+    {
+        constexpr int NRW = (TX + 8) / RUN, NRH = TY + 8, NR = NRW * NRH;
+        for (int k = tid; k < NR; k += NT) {
+            const int y = k % NRH - 4, x0 = (k / NRH) * RUN - 4;
+            // 3 x 6 patch of effective depth and level: a dry cell shows depth 0
+            // and its bed as level
+            real He[3][RUN + 2], Le[3][RUN + 2], Bc[RUN + 2];
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int i = 0; i < RUN + 2; ++i) {
+                    const int s = G::at(x0 - 1 + i, y - 1 + j);
+                    const real H = L.H[s], b = L.B[s];
+                    const bool w = H > eps;
+                    He[j][i] = w ? H : real(0);
+                    Le[j][i] = b + He[j][i];
+                    if (j == 1) { Bc[i] = b; if (i >= 1 && i <= RUN) any |= w; }
+                }
+            if (!__any(any)) continue;   // the whole wave is dry here
+            real ux[RUN + 2], uy[RUN + 2], uxs[RUN], uys[RUN], uxn[RUN], uyn[RUN];
+#pragma unroll
+            for (int i = 0; i < RUN + 2; ++i) {
+                const int s = G::at(x0 - 1 + i, y);
+                ux[i] = L.UX[s]; uy[i] = L.UY[s];
+            }
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                const int ss = G::at(x0 + i, y - 1), sn = G::at(x0 + i, y + 1);
+                uxs[i] = L.UX[ss]; uys[i] = L.UY[ss];
+                uxn[i] = L.UX[sn]; uyn[i] = L.UY[sn];
+            }
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                const int c = i + 1;
+                const real Hc = He[1][c], bc = Bc[c], ec = Le[1][c];
+                const bool wc = Hc > real(0);
+                real e[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        e[j][d] = rmax(bc, rmin(Le[j][c - 1 + d], ec + He[j][c - 1 + d]));
+                // e[j][d]: j = 0 south row, 2 north row; d = 0 west column, 2 east
+                const real Gx = (al * (e[1][2] - e[1][0]) + be * ((e[2][2] - e[2][0]) + (e[0][2] - e[0][0]))) * a.ih;
+                const real Gy = (al * (e[2][1] - e[0][1]) + be * ((e[2][2] - e[0][2]) + (e[2][0] - e[0][0]))) * a.ih;
+                const int gx = tx0 + x0 + i, gy = ty0 + y;
+                const bool ins = inside(x0 + i, y);
+                const real cf = ins ? a.cf[(long)gy * nx + gx] : real(0);
+                const real lam0 = Mth<real>::friction(cf, wc ? Hc : real(1));
+                Nb4<real> nb;
+                nb.ux[0] = ux[c - 1]; nb.uy[0] = uy[c - 1]; nb.w[0] = He[1][c - 1] > real(0);
+                nb.ux[1] = ux[c + 1]; nb.uy[1] = uy[c + 1]; nb.w[1] = He[1][c + 1] > real(0);
+                nb.ux[2] = uxs[i]; nb.uy[2] = uys[i]; nb.w[2] = He[0][c] > real(0);
+                nb.ux[3] = uxn[i]; nb.uy[3] = uyn[i]; nb.w[3] = He[2][c] > real(0);
+                real fx, fy;
+                soft_forces(a, Hc, ux[c], uy[c], nb, fx, fy);
+                const real ax = -a.g * Gx + fx, ay = -a.g * Gy + fy;
+                const real lam = lam0 * Mth<real>::sqrt(ux[c] * ux[c] + uy[c] * uy[c]);
+                const real d = real(1) + half_tau * lam;
+                const int s = G::at(x0 + i, y);
+                if (ins) {
+                    L.HX[s] = wc ? Mth<real>::div(ux[c] + half_tau * ax, d) : real(0);
+                    L.HY[s] = wc ? Mth<real>::div(uy[c] + half_tau * ay, d) : real(0);
+                    L.GX[s] = Gx;
+                    L.GY[s] = Gy;
+                    L.LM[s] = lam0;
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (EDGE) {
+            fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -4, TX + 4, -4, TY + 4, L.HX, L.HY, nullptr,
+                                          /*sgx*/ 1, /*sgy*/ 2);
+            __syncthreads();
+        }
+    }
+
+    // ---- P2: forces at t_{n+1/2}, corrector, sources on tile + 3
+    {
+        constexpr int NRW = (TX + 8) / RUN, NRH = TY + 6, NR = NRW * NRH;
+        for (int k = tid; k < NR; k += NT) {
+            const int y = k % NRH - 3, x0 = (k / NRH) * RUN - 4;
+            real hx[RUN + 2], hy[RUN + 2], Hr[RUN + 2];
+            bool wr[RUN + 2];
+#pragma unroll
+            for (int i = 0; i < RUN + 2; ++i) {
+                const int s = G::at(x0 - 1 + i, y);
+                hx[i] = L.HX[s]; hy[i] = L.HY[s]; Hr[i] = L.H[s]; wr[i] = Hr[i] > eps;
+            }
+            real hxs[RUN], hys[RUN], hxn[RUN], hyn[RUN];
+            bool ws[RUN], wn[RUN];
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                const int ss = G::at(x0 + i, y - 1), sn = G::at(x0 + i, y + 1);
+                hxs[i] = L.HX[ss]; hys[i] = L.HY[ss]; ws[i] = L.H[ss] > eps;
+                hxn[i] = L.HX[sn]; hyn[i] = L.HY[sn]; wn[i] = L.H[sn] > eps;
+            }
+            real out[RUN][5];
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                const int c = i + 1, x = x0 + i;
+                const int s = G::at(x, y);
+                const real Hc = Hr[c];
+                const bool wc = wr[c];
+                const real ux = L.UX[s], uy = L.UY[s], gxv = L.GX[s], gyv = L.GY[s], lam0 = L.LM[s];
+                Nb4<real> nb;
+                nb.ux[0] = hx[c - 1]; nb.uy[0] = hy[c - 1]; nb.w[0] = wr[c - 1];
+                nb.ux[1] = hx[c + 1]; nb.uy[1] = hy[c + 1]; nb.w[1] = wr[c + 1];
+                nb.ux[2] = hxs[i]; nb.uy[2] = hys[i]; nb.w[2] = ws[i];
+                nb.ux[3] = hxn[i]; nb.uy[3] = hyn[i]; nb.w[3] = wn[i];
+                real fx, fy;
+                soft_forces(a, Hc, hx[c], hy[c], nb, fx, fy);
+                const real ax = -a.g * gxv + fx, ay = -a.g * gyv + fy;
+                const real lam = lam0 * Mth<real>::sqrt(hx[c] * hx[c] + hy[c] * hy[c]);
+                const real d = real(1) + tau * lam;
+                const real qx = wc ? Hc * Mth<real>::div(ux + tau * ax, d) : real(0);
+                const real qy = wc ? Hc * Mth<real>::div(uy + tau * ay, d) : real(0);
+                const real Ht = is_src(a, tx0 + x, ty0 + y) ? Hc + sdep : Hc;
+                const bool wt = Ht > eps;
+                out[i][0] = Ht;
+                out[i][1] = wt ? Mth<real>::div(qx, Ht) : real(0);
+                out[i][2] = wt ? Mth<real>::div(qy, Ht) : real(0);
+                out[i][3] = qx;
+                out[i][4] = qy;
+            }
+            // own-cell stores after all own-cell reads of the run
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                if (!inside(x0 + i, y)) continue;
+                const int s = G::at(x0 + i, y);
+                L.UX[s] = out[i][0];
+                L.UY[s] = out[i][1];
+                L.LM[s] = out[i][2];
+                L.GX[s] = out[i][3];
+                L.GY[s] = out[i][4];
+            }
+        }
+        __syncthreads();
+        if constexpr (EDGE) {
+            fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -3, TX + 3, -3, TY + 3, L.UX, L.UY, L.LM,
+                                          /*sgx*/ 2, /*sgy*/ 4);
+            __syncthreads();
+        }
+    }
+
+    // ---- FX: x faces of rows -1..TY, face x between cells x-1 and x
+    {
+        constexpr int NRW = (TX + 4) / RUN, NRH = TY + 2, NR = NRW * NRH;
+        for (int k = tid; k < NR; k += NT) {
+            const int y = k % NRH - 1, x0 = (k / NRH) * RUN - 1;
+            Cell<real> cl[RUN + 3];
+#pragma unroll
+            for (int i = 0; i < RUN + 3; ++i) {
+                const int s = G::at(x0 - 2 + i, y);
+                cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.UY[s]; cl[i].ut = L.LM[s];
+            }
+            Face<real> lo[RUN + 1], hi[RUN + 1];
+#pragma unroll
+            for (int i = 0; i < RUN + 1; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
+            // recon index i is cell x0 - 1 + i; face x0 + f sits between cells f and f+1
+#pragma unroll
+            for (int f = 0; f < RUN; ++f) {
+                real FH, Fn, Ft;
+                riemann<real>(a.g, hi[f], lo[f + 1], FH, Fn, Ft);
+                const int s = G::at(x0 + f, y);
+                L.HX[s] = FH; L.HY[s] = Fn; L.H[s] = Ft;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- FY + final update: columns -1..TX, runs of 4 cells along y
+    {
+        constexpr int NC = TX + 2, NRY = (TY + 2 + RUN - 1) / RUN, NR = NC * NRY;
+        for (int k = tid; k < NR; k += NT) {
+            const int x = k % NC - 1, y0 = (k / NC) * RUN - 1;
+            Cell<real> cl[RUN + 4];
+#pragma unroll
+            for (int i = 0; i < RUN + 4; ++i) {
+                const int s = G::at(x, y0 - 2 + i);
+                cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.LM[s]; cl[i].ut = L.UY[s];
+            }
+            Face<real> lo[RUN + 2], hi[RUN + 2];
+#pragma unroll
+            for (int i = 0; i < RUN + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
+            // recon index i is cell y0 - 1 + i; face y0 + f between cells f and f+1
+            real FH[RUN + 1], Fn[RUN + 1], Ft[RUN + 1];
+#pragma unroll
+            for (int f = 0; f < RUN + 1; ++f) riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+                const int y = y0 + i;
+                if (y > TY || !inside(x, y)) continue;
+                const int s = G::at(x, y);
+                const real dxH = L.HX[s] - L.HX[s + 1];
+                const real dxQx = L.HY[s] - L.HY[s + 1];
+                const real dxQy = L.H[s] - L.H[s + 1];
+                const real Hn = cl[i + 2].H + r * (dxH + (FH[i] - FH[i + 1]));
+                const real qx = L.GX[s] + r * (dxQx + (Ft[i] - Ft[i + 1]));
+                const real qy = L.GY[s] + r * (dxQy + (Fn[i] - Fn[i + 1]));
+                const real Hc = rmax(Hn, real(0));
+                const bool w = Hc > eps;
+                const real qxo = w ? qx : real(0), qyo = w ? qy : real(0);
+                L.NH[s] = Hc;
+                L.GX[s] = w ? Mth<real>::div(qxo, Hc) : real(0);
+                L.GY[s] = w ? Mth<real>::div(qyo, Hc) : real(0);
+                if (x >= 0 && x < TX && y >= 0 && y < TY) {
+                    const long gi = (long)(ty0 + y) * nx + tx0 + x;
+                    a.Ho[gi] = Hc;
+                    a.Qxo[gi] = qxo;
+                    a.Qyo[gi] = qyo;
+                    msum += (double)Hc;
+                    lsum += (double)(Hc - Hn);
+                    bad |= !finite(Hn) || !finite(qx) || !finite(qy);
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (EDGE) {
+            fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -1, TX + 1, -1, TY + 1, L.NH, L.GX, L.GY,
+                                          /*sgx*/ 2, /*sgy*/ 4);
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue: CFL speed of layer n+1 on the tile, K1 bits of layer n+1
+    {
+        constexpr int NT_CELLS = TX * TY, NRING = 2 * (TX + TY);
+        int own = 0, eW = 0, eE = 0, eS = 0, eN = 0, rg = 0;
+        for (int k = tid; k < NT_CELLS + NRING; k += NT) {
+            int x, y;
+            if (k < NT_CELLS) {
+                x = k % TX; y = k / TX;
+            } else {
+                const int q = k - NT_CELLS;   // ring: S row, N row, W column, E column
+                if (q < TX) { x = q; y = -1; }
+                else if (q < 2 * TX) { x = q - TX; y = TY; }
+                else if (q < 2 * TX + TY) { x = -1; y = q - 2 * TX; }
+                else { x = TX; y = q - 2 * TX - TY; }
+            }
+            if (!inside(x, y)) continue;
+            const int s = G::at(x, y);
+            const real H = L.NH[s];
+            const bool w = H > eps;
+            const bool ws = w || is_src(a, tx0 + x, ty0 + y);
+            if (k >= NT_CELLS) { rg |= ws; continue; }
+            if (ws) {
+                own = 1;
+                eW |= x == 0; eE |= x == TX - 1; eS |= y == 0; eN |= y == TY - 1;
+            }
+            if (w) {
+                Nb4<real> nb;
+                const int sn[4] = {s - 1, s + 1, s - W, s + W};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    nb.ux[q] = L.GX[sn[q]]; nb.uy[q] = L.GY[sn[q]]; nb.w[q] = L.NH[sn[q]] > eps;
+                }
+                const real ux = L.GX[s], uy = L.GY[s];
+                real fx, fy;
+                soft_forces(a, H, ux, uy, nb, fx, fy);
+                vmax = rmax(vmax, cfl_speed(a, H, ux, uy, fx, fy));
+            }
+        }
+        bits |= own | (eW << 1) | (eE << 2) | (eS << 3) | (eN << 4) | (rg << 5);
+    }
+}
+
 // ---------------------------------------------------------------- step kernel
 
-template <typename real, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_step(Args<real> a) {
-    constexpr int W = TX + 2 * HALO, HH = TY + 2 * HALO, N = W * HH;
-    constexpr int W4 = TX + 8, N4 = W4 * (TY + 8);
-    constexpr int W3 = TX + 6, N3 = W3 * (TY + 6);
-    constexpr int W1 = TX + 2, N1 = W1 * (TY + 2);
-    constexpr int M1 = (N1 + NT - 1) / NT;   // R1 cells per thread
+template <typename real, int TX, int TY, int NT, int LIM>
+__global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
-
-    // LDS, all arrays share the halo-5 layout: cell (lx, ly) at (ly+5)*W + lx+5
-    __shared__ real A0[N];   // H^n             -> eta_t
-    __shared__ real A1[N];   // b               -> H^{n+1}
-    __shared__ real A2[N];   // Ux^n            -> H_t
-    __shared__ real A3[N];   // Uy^n            -> Ux_t
-    __shared__ real A4[N];   // Ux^{n+1/2}      -> flux F_H
-    __shared__ real A5[N];   // Uy^{n+1/2}      -> flux F normal
-    __shared__ real A6[N];   // G_x             -> Qx_t -> Ux^{n+1}
-    __shared__ real A7[N];   // G_y             -> Qy_t -> Uy^{n+1}
-    __shared__ real A8[N];   // c_f/H^(4/3)     -> flux F tangential
-    __shared__ real A9[N];   // Uy_t
-    __shared__ uint8_t WET[N];
+    __shared__ Lds<real, TX, TY> L;
     __shared__ double red_d[2][NWAVE];
     __shared__ int red_i[NWAVE];
     __shared__ int s_last;
 
     Ctrl* const ctrl = a.ctrl;
     if (ctrl->err_gate) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int count = a.skip ? ctrl->count[a.slot] : a.ntiles;
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
-    const real half_tau = real(0.5) * tau;
-    const real r = tau * a.ih;
     const int gen = (int)ctrl->step + 2;
     const int nx = a.nx, ny = a.ny;
-    const real eps = a.eps;
-    // normalised cubic-B-spline SPH gradient weights (smoothing length h):
-    // al = 1/(12 sqrt2 - 14), be = (3 sqrt2 - 4)/(12 sqrt2 - 14), 2 al + 4 be = 1
-    const real al = real(0.33663655161388173), be = real(0.08168172419305914);
 
     real vmax = real(0);
     bool bad = false;
@@ -298,264 +671,14 @@ __global__ __launch_bounds__(NT) void k_step(Args<real> a) {
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
-        __syncthreads();   // LDS of the previous tile is free
-
-        // ---- load tile + 5 (mirror images outside the domain)
-        int act_n = 0;
-        for (int k = tid; k < N; k += NT) {
-            const int lx = k % W - HALO, ly = k / W - HALO;
-            int fx = 0, fy = 0;
-            const int gx = mirror(tx0 + lx, nx, fx), gy = mirror(ty0 + ly, ny, fy);
-            const long gi = (long)gy * nx + gx;
-            const real H = a.Hi[gi];
-            real qx = a.Qxi[gi], qy = a.Qyi[gi];
-            if (fx & 1) qx = -qx;
-            if (fy & 1) qy = -qy;
-            const bool w = H > eps;
-            const real iH = w ? Mth<real>::rcp(H) : real(0);
-            A0[k] = H;
-            A1[k] = a.bed[gi];
-            A2[k] = qx * iH;
-            A3[k] = qy * iH;
-            WET[k] = (uint8_t)w;
-            // K1 rule at layer n: own cells and outer face neighbours (no corners)
-            const bool in_tile = lx >= 0 && lx < TX && ly >= 0 && ly < TY;
-            const bool ring = ((lx == -1 || lx == TX) && ly >= 0 && ly < TY) ||
-                              ((ly == -1 || ly == TY) && lx >= 0 && lx < TX);
-            const int gxr = tx0 + lx, gyr = ty0 + ly;
-            const bool in_dom = gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny;
-            if ((in_tile || ring) && in_dom) {
-                const bool src = (unsigned)(gxr - a.i0) < (unsigned)a.ni && (unsigned)(gyr - a.j0) < (unsigned)a.nj;
-                if (w || src) act_n = 1;
-            }
-        }
-        act_n = __syncthreads_or(act_n);
-
-        // ---- P1: forces at t_n and predictor on tile + 4
-        for (int k = tid; k < N4; k += NT) {
-            const int lx = k % W4 - 4, ly = k / W4 - 4;
-            const int gx = tx0 + lx, gy = ty0 + ly;
-            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const int s = (ly + HALO) * W + lx + HALO;
-            if (!WET[s]) {
-                A4[s] = real(0); A5[s] = real(0); A6[s] = real(0); A7[s] = real(0); A8[s] = real(0);
-                continue;
-            }
-            const real Hc = A0[s], bc = A1[s], ec = Hc + bc;
-            real e[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                // level a neighbour shows: it pushes with at most its own depth
-                // above the own surface and never from below the own bed (a dry
-                // neighbour has depth 0 and level = its bed)
-                const int m = s + (q / 3 - 1) * W + (q % 3 - 1);
-                const bool wm = WET[m];
-                const real Hm = wm ? A0[m] : real(0);
-                const real em = wm ? A0[m] + A1[m] : A1[m];
-                e[q] = rmax(bc, rmin(em, ec + Hm));
-            }
-            // e: 0 SW 1 S 2 SE 3 W 4 C 5 E 6 NW 7 N 8 NE
-            const real Gx = (al * (e[5] - e[3]) + be * ((e[8] - e[6]) + (e[2] - e[0]))) * a.ih;
-            const real Gy = (al * (e[7] - e[1]) + be * ((e[8] - e[2]) + (e[6] - e[0]))) * a.ih;
-            const long gi = (long)gy * nx + gx;
-            const real lam0 = a.cf[gi] * Mth<real>::pow_m43(Hc);
-            real fx, fy;
-            soft_forces<real, W>(a, s, A2, A3, WET, Hc, fx, fy);
-            const real ux = A2[s], uy = A3[s];
-            const real ax = -a.g * Gx + fx, ay = -a.g * Gy + fy;
-            const real lam = lam0 * Mth<real>::sqrt(ux * ux + uy * uy);
-            const real id = Mth<real>::rcp(real(1) + half_tau * lam);
-            A4[s] = (ux + half_tau * ax) * id;
-            A5[s] = (uy + half_tau * ay) * id;
-            A6[s] = Gx;
-            A7[s] = Gy;
-            A8[s] = lam0;
-        }
-        __syncthreads();
-        if (edge) {   // mirror images of U^{n+1/2} outside the domain
-            for (int k = tid; k < N4; k += NT) {
-                const int lx = k % W4 - 4, ly = k / W4 - 4;
-                const int gx = tx0 + lx, gy = ty0 + ly;
-                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) continue;
-                int fx = 0, fy = 0;
-                const int mx = mirror(gx, nx, fx) - tx0, my = mirror(gy, ny, fy) - ty0;
-                const int s = (ly + HALO) * W + lx + HALO, m = (my + HALO) * W + mx + HALO;
-                A4[s] = (fx & 1) ? -A4[m] : A4[m];
-                A5[s] = (fy & 1) ? -A5[m] : A5[m];
-            }
-            __syncthreads();
-        }
-
-        // ---- P2: forces at t_{n+1/2}, corrector, sources on tile + 3
-        for (int k = tid; k < N3; k += NT) {
-            const int lx = k % W3 - 3, ly = k / W3 - 3;
-            const int gx = tx0 + lx, gy = ty0 + ly;
-            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const int s = (ly + HALO) * W + lx + HALO;
-            const real Hc = A0[s];
-            real qx = real(0), qy = real(0);
-            if (WET[s]) {
-                real fx, fy;
-                soft_forces<real, W>(a, s, A4, A5, WET, Hc, fx, fy);
-                const real hx = A4[s], hy = A5[s];
-                const real ax = -a.g * A6[s] + fx, ay = -a.g * A7[s] + fy;
-                const real lam = A8[s] * Mth<real>::sqrt(hx * hx + hy * hy);
-                const real id = Mth<real>::rcp(real(1) + tau * lam);
-                qx = Hc * ((A2[s] + tau * ax) * id);
-                qy = Hc * ((A3[s] + tau * ay) * id);
-            }
-            const bool src = (unsigned)(gx - a.i0) < (unsigned)a.ni && (unsigned)(gy - a.j0) < (unsigned)a.nj;
-            const real Ht = src ? Hc + sdep : Hc;
-            const bool wt = Ht > eps;
-            const real iH = wt ? Mth<real>::rcp(Ht) : real(0);
-            A0[s] = Ht + A1[s];   // eta_t
-            A2[s] = Ht;
-            A3[s] = qx * iH;
-            A9[s] = qy * iH;
-            A6[s] = qx;
-            A7[s] = qy;
-        }
-        __syncthreads();
-        if (edge) {   // mirror images of the post-Lagrangian fields
-            for (int k = tid; k < N3; k += NT) {
-                const int lx = k % W3 - 3, ly = k / W3 - 3;
-                const int gx = tx0 + lx, gy = ty0 + ly;
-                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) continue;
-                int fx = 0, fy = 0;
-                const int mx = mirror(gx, nx, fx) - tx0, my = mirror(gy, ny, fy) - ty0;
-                const int s = (ly + HALO) * W + lx + HALO, m = (my + HALO) * W + mx + HALO;
-                A0[s] = A0[m];
-                A2[s] = A2[m];
-                A3[s] = (fx & 1) ? -A3[m] : A3[m];
-                A9[s] = (fy & 1) ? -A9[m] : A9[m];
-            }
-            __syncthreads();
-        }
-
-        // ---- FX: x faces of rows -1..TY, face i between cells i-1 and i
-        constexpr int NFX = (W1 + 1) * (TY + 2);
-        for (int k = tid; k < NFX; k += NT) {
-            const int lx = k % (W1 + 1) - 1, ly = k / (W1 + 1) - 1;
-            const int s = (ly + HALO) * W + lx + HALO;
-            const Face<real> L = recon<real>(s - 1, 1, real(1), a.limiter, eps, A2, A0, A1, A3, A9);
-            const Face<real> R = recon<real>(s, 1, real(-1), a.limiter, eps, A2, A0, A1, A3, A9);
-            real FH, Fn, Ft;
-            riemann<real>(a.g, L, R, FH, Fn, Ft);
-            A4[s] = FH; A5[s] = Fn; A8[s] = Ft;
-        }
-        __syncthreads();
-        real dH[M1], dQx[M1], dQy[M1];
-#pragma unroll
-        for (int m = 0; m < M1; ++m) {
-            const int k = tid + m * NT;
-            if (k < N1) {
-                const int lx = k % W1 - 1, ly = k / W1 - 1;
-                const int s = (ly + HALO) * W + lx + HALO;
-                dH[m] = A4[s] - A4[s + 1];
-                dQx[m] = A5[s] - A5[s + 1];
-                dQy[m] = A8[s] - A8[s + 1];
-            }
-        }
-        __syncthreads();
-
-        // ---- FY: y faces of columns -1..TX, face j between cells j-1 and j
-        constexpr int NFY = W1 * (TY + 3);
-        for (int k = tid; k < NFY; k += NT) {
-            const int lx = k % W1 - 1, ly = k / W1 - 1;
-            const int s = (ly + HALO) * W + lx + HALO;
-            const Face<real> L = recon<real>(s - W, W, real(1), a.limiter, eps, A2, A0, A1, A9, A3);
-            const Face<real> R = recon<real>(s, W, real(-1), a.limiter, eps, A2, A0, A1, A9, A3);
-            real FH, Fn, Ft;
-            riemann<real>(a.g, L, R, FH, Fn, Ft);
-            A4[s] = FH; A5[s] = Fn; A8[s] = Ft;
-        }
-        __syncthreads();
-
-        // ---- final update on tile + 1
         double msum = 0.0, lsum = 0.0;
-#pragma unroll
-        for (int m = 0; m < M1; ++m) {
-            const int k = tid + m * NT;
-            if (k >= N1) continue;
-            const int lx = k % W1 - 1, ly = k / W1 - 1;
-            const int gx = tx0 + lx, gy = ty0 + ly;
-            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const int s = (ly + HALO) * W + lx + HALO;
-            const real Hn = A2[s] + r * (dH[m] + (A4[s] - A4[s + W]));
-            const real qx = A6[s] + r * (dQx[m] + (A8[s] - A8[s + W]));
-            const real qy = A7[s] + r * (dQy[m] + (A5[s] - A5[s + W]));
-            const real Hc = rmax(Hn, real(0));
-            const bool w = Hc > eps;
-            const real iH = w ? Mth<real>::rcp(Hc) : real(0);
-            const real qxo = w ? qx : real(0), qyo = w ? qy : real(0);
-            A1[s] = Hc;
-            A6[s] = qxo * iH;
-            A7[s] = qyo * iH;
-            if (lx >= 0 && lx < TX && ly >= 0 && ly < TY) {
-                const long gi = (long)gy * nx + gx;
-                a.Ho[gi] = Hc;
-                a.Qxo[gi] = qxo;
-                a.Qyo[gi] = qyo;
-                msum += (double)Hc;
-                lsum += (double)(Hc - Hn);
-                bad |= !(rabs(Hc) < real(1e30)) || !(rabs(qxo) < real(1e30)) || !(rabs(qyo) < real(1e30));
-            }
-        }
-        __syncthreads();
-        if (edge) {   // mirror images of the new layer on the ring
-            for (int k = tid; k < N1; k += NT) {
-                const int lx = k % W1 - 1, ly = k / W1 - 1;
-                const int gx = tx0 + lx, gy = ty0 + ly;
-                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) continue;
-                int fx = 0, fy = 0;
-                const int mx = mirror(gx, nx, fx) - tx0, my = mirror(gy, ny, fy) - ty0;
-                const int s = (ly + HALO) * W + lx + HALO, m = (my + HALO) * W + mx + HALO;
-                A1[s] = A1[m];
-                A6[s] = (fx & 1) ? -A6[m] : A6[m];
-                A7[s] = (fy & 1) ? -A7[m] : A7[m];
-            }
-            __syncthreads();
-        }
-        // wet flags of layer n+1 on tile + 1 for the epilogue
-        for (int k = tid; k < N1; k += NT) {
-            const int lx = k % W1 - 1, ly = k / W1 - 1;
-            const int s = (ly + HALO) * W + lx + HALO;
-            WET[s] = (uint8_t)(A1[s] > eps);
-        }
-        __syncthreads();
-
-        // ---- epilogue on the tile: CFL speed of layer n+1 and flags
-        int own = 0, eW = 0, eE = 0, eS = 0, eN = 0, ringf = 0;
-        for (int k = tid; k < N1; k += NT) {
-            const int lx = k % W1 - 1, ly = k / W1 - 1;
-            const int gx = tx0 + lx, gy = ty0 + ly;
-            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const int s = (ly + HALO) * W + lx + HALO;
-            const bool w = WET[s];
-            const bool src = (unsigned)(gx - a.i0) < (unsigned)a.ni && (unsigned)(gy - a.j0) < (unsigned)a.nj;
-            const bool in_tile = lx >= 0 && lx < TX && ly >= 0 && ly < TY;
-            if (!in_tile) {   // ring cell: outer face neighbour, corners excluded
-                const bool corner = (lx < 0 || lx >= TX) && (ly < 0 || ly >= TY);
-                if (!corner && (w || src)) ringf = 1;
-                continue;
-            }
-            if (w || src) {
-                own = 1;
-                if (lx == 0) eW = 1;
-                if (lx == TX - 1) eE = 1;
-                if (ly == 0) eS = 1;
-                if (ly == TY - 1) eN = 1;
-            }
-            if (w) {
-                const real H = A1[s];
-                real fx, fy;
-                soft_forces<real, W>(a, s, A6, A7, WET, H, fx, fy);
-                vmax = rmax(vmax, cfl_speed(a, H, A6[s], A7[s], fx, fy));
-            }
-        }
+        int bits = 0;
+        __syncthreads();   // LDS of the previous tile is free
+        if (edge)
+            tile_step<real, TX, TY, NT, LIM, true>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+        else
+            tile_step<real, TX, TY, NT, LIM, false>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
         // block reductions: flags, volume and ledger partials
-        const int lane = tid & 63, wv = tid >> 6;
-        int bits = own | (eW << 1) | (eE << 2) | (eS << 3) | (eN << 4) | (ringf << 5);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         msum = wave_sum(msum);
@@ -571,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_step(Args<real> a) {
             if (a.skip) {
                 const int ti = tile % a.ntx, tj = tile / a.ntx;
                 int* cnt = &ctrl->count[a.slot ^ 1];
-                if (act_n || (bb & 1) || (bb & 32)) enqueue(tile, gen, a.stamp, a.list_out, cnt);
+                if (bb & (1 | 32 | 64)) enqueue(tile, gen, a.stamp, a.list_out, cnt);
                 if ((bb & 2) && ti > 0) enqueue(tile - 1, gen, a.stamp, a.list_out, cnt);
                 if ((bb & 4) && ti < a.ntx - 1) enqueue(tile + 1, gen, a.stamp, a.list_out, cnt);
                 if ((bb & 8) && tj > 0) enqueue(tile - a.ntx, gen, a.stamp, a.list_out, cnt);
@@ -582,10 +705,9 @@ __global__ __launch_bounds__(NT) void k_step(Args<real> a) {
 
     // ---- completion: maximum speed, error flag, last workgroup finalises
     vmax = wave_max(vmax);
-    const int lane = tid & 63, wv = tid >> 6;
     __syncthreads();
     if (lane == 0) red_d[0][wv] = (double)vmax;
-    int anybad = __syncthreads_or((int)bad);
+    const int anybad = __syncthreads_or((int)bad);
     if (tid == 0) {
         double vm = 0.0;
         for (int q = 0; q < NWAVE; ++q) vm = fmax(vm, red_d[0][q]);
@@ -621,13 +743,13 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
     constexpr int W = TX + 2, N = W * (TY + 2);
     constexpr int NWAVE = NT / 64;
     __shared__ real sH[N], sUx[N], sUy[N];
-    __shared__ uint8_t WET[N];
     __shared__ double red_d[NWAVE];
     __shared__ real red_v[NWAVE];
     __shared__ int red_i[NWAVE];
     const int tid = threadIdx.x, tile = blockIdx.x;
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
     const int nx = a.nx, ny = a.ny;
+    const real eps = a.eps;
     for (int k = tid; k < N; k += NT) {
         const int lx = k % W - 1, ly = k / W - 1;
         int fx = 0, fy = 0;
@@ -637,9 +759,10 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         real qx = a.Qxi[gi], qy = a.Qyi[gi];
         if (fx & 1) qx = -qx;
         if (fy & 1) qy = -qy;
-        const bool w = H > a.eps;
-        const real iH = w ? Mth<real>::rcp(H) : real(0);
-        sH[k] = H; sUx[k] = qx * iH; sUy[k] = qy * iH; WET[k] = (uint8_t)w;
+        const bool w = H > eps;
+        sH[k] = H;
+        sUx[k] = w ? Mth<real>::div(qx, H) : real(0);
+        sUy[k] = w ? Mth<real>::div(qy, H) : real(0);
     }
     __syncthreads();
     real vmax = real(0);
@@ -652,14 +775,18 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         const bool in_tile = lx >= 0 && lx < TX && ly >= 0 && ly < TY;
         const bool corner = (lx < 0 || lx >= TX) && (ly < 0 || ly >= TY);
         if (corner) continue;
-        const bool src = (unsigned)(gx - a.i0) < (unsigned)a.ni && (unsigned)(gy - a.j0) < (unsigned)a.nj;
-        if (WET[k] || src) act = 1;
+        const bool w = sH[k] > eps;
+        if (w || is_src(a, gx, gy)) act = 1;
         if (!in_tile) continue;
         const real H = sH[k];
         msum += (double)H;
-        if (WET[k]) {
+        if (w) {
+            Nb4<real> nb;
+            const int sn[4] = {k - 1, k + 1, k - W, k + W};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { nb.ux[q] = sUx[sn[q]]; nb.uy[q] = sUy[sn[q]]; nb.w[q] = sH[sn[q]] > eps; }
             real fx, fy;
-            soft_forces<real, W>(a, k, sUx, sUy, WET, H, fx, fy);
+            soft_forces(a, H, sUx[k], sUy[k], nb, fx, fy);
             vmax = rmax(vmax, cfl_speed(a, H, sUx[k], sUy[k], fx, fy));
         }
     }
