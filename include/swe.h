@@ -136,6 +136,47 @@ int    swe_active_tiles(swe_t* s, int* out, int cap);
  * [ms].  For measurement. */
 int    swe_run_timed(swe_t* s, long nsteps, double* kernel_ms);
 
+/* ------------------------------------------------------------------ batches
+ * A batch advances n independent scenarios together -- the paper's use case
+ * of hundreds of runs over hydrograph and hydraulic-structure settings
+ * (Sec. 1) -- with uneven grid sizes, one kernel launch per step for all of
+ * them, each scenario with its own time step, clock, hydrograph and error
+ * state.  Scenario k has an nx[k] x ny[k] grid of cell size dx[k], bed b[k],
+ * Manning n_M[k] (n_M or n_M[k] may be NULL) and parameters p[k] (closed
+ * gates through p[k].solid, initial state through p[k].H0/Qx0/Qy0; all
+ * copied).  precision, limiter and the tile shape come from p[0] and must
+ * agree; every p[k].skip_dry must be 1; the stream is p[0].stream.  A
+ * scenario computes bit for bit what a single handle with the same inputs
+ * and tile shape computes.  Returns NULL on error. */
+typedef struct swe_batch_s swe_batch_t;
+swe_batch_t* swe_batch_create(int n, const int* nx, const int* ny, const double* dx,
+                              const double* const* b, const double* const* n_M,
+                              const swe_params* p);
+
+/* Advance every scenario nsteps steps (hipGraph replay, one launch per step
+ * for the whole batch); a scenario that hits an error stops while the others
+ * continue.  Synchronises; returns 0 or the first scenario's SWE_E* code. */
+int    swe_batch_run(swe_batch_t* b, long nsteps);
+
+/* As swe_batch_run with a HIP event pair around every step kernel; the summed
+ * kernel time goes to *kernel_ms. */
+int    swe_batch_run_timed(swe_batch_t* b, long nsteps, double* kernel_ms);
+
+/* Per-scenario clock [s], FP64 volume [m^3], hydrograph volume [m^3], clamp
+ * ledger [m^3] and completed steps; arrays of n, any may be NULL. */
+int    swe_batch_query(swe_batch_t* b, double* t, double* mass, double* inflow,
+                       double* ledger, long* steps);
+
+/* Host FP64 copy of scenario k's state (nx[k]*ny[k] each; any may be NULL). */
+int    swe_batch_get_state(swe_batch_t* b, int k, double* H, double* Qx, double* Qy);
+
+/* Processed tile-steps and in-domain cell-steps of the batch, total tiles. */
+int    swe_batch_work(swe_batch_t* b, long long* tile_steps, long long* cell_steps,
+                      int* total_tiles);
+
+/* Free the batch and its device memory.  NULL-safe. */
+void   swe_batch_destroy(swe_batch_t* b);
+
 /* Message of the last error on this host thread ("" if none). */
 const char* swe_last_error(void);
 

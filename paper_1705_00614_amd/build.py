@@ -11,10 +11,11 @@ DEPS = SOURCES + [os.path.join(CSRC, "swe_step.hpp"),
                   os.path.join(os.path.dirname(HERE), "include", "swe.h")]
 
 # Packed FP32 instructions are disabled on purpose: every FP32 operation is
-# issued as a plain VALU instruction.  No implicit contraction into fused
-# multiply-adds either: every tile shape (template instantiation) then rounds
-# every cell identically, so results do not depend on the tile shape.
-HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+# issued as a plain VALU instruction.  Multiply-adds are fused only within a
+# single source expression (-ffp-contract=on, never across statements), so
+# every tile shape (template instantiation) rounds every cell identically and
+# results do not depend on the tile shape.
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function"]
 

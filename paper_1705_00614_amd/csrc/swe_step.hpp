@@ -41,6 +41,18 @@ constexpr int HALO = 5;
 constexpr int RUN = 4;
 constexpr double GATE_BED = 1.0e6;
 
+// Tile lists and completion counters.  Same-address device atomics
+// serialise (~11 ns each on this part), so nothing per workgroup goes to one
+// address: the workgroups of a step form NSEG groups, each with its own
+// completion counter and its own segment of the next tile list, every counter
+// on its own 256-byte line; per-workgroup maxima are plain stores reduced by
+// the last workgroup.
+constexpr int NSEG = 8;
+constexpr int LINE = 64;   // ints per 256-byte line
+__host__ __device__ constexpr int hot_done(int g) { return g * LINE; }          // g < NSEG; NSEG: all groups
+__host__ __device__ constexpr int hot_seg(int slot, int g) { return (NSEG + 1 + slot * NSEG + g) * LINE; }
+constexpr int HOT_INTS = (NSEG + 1 + 2 * NSEG) * LINE;
+
 // Device-resident control block of a simulation.
 struct Ctrl {
     double t;            // simulated time of the current layer
@@ -49,10 +61,9 @@ struct Ctrl {
     double sdepth;       // source depth of the next step (dV / (N_in h^2))
     double inflow;       // hydrograph volume of all completed steps
     double last_tau;     // time step of the last completed step
-    unsigned int speed32;          // max speed of the new layer (float bits)
-    unsigned int done;             // finished workgroups of the running step
-    unsigned long long speed64;    // max speed of the new layer (double bits)
-    int count[2];        // tile-list lengths
+    unsigned long long prep_speed;  // max speed of the new layer gathered by atomics (preparation
+                                    // kernel; batch step), bits of the stencil type
+    int seg_off[2][NSEG + 1];       // prefix offsets of the list segments, per list slot
     int err;             // error raised during the running step
     int err_gate;        // error as of the start of the running step
     long long step;      // completed steps
@@ -60,17 +71,31 @@ struct Ctrl {
     long long cells;     // processed in-domain cell-steps
 };
 
+// A tile-list entry packs the scenario of a batch (0 for a single grid) above
+// the tile index of that scenario's grid.
+constexpr int TILE_BITS = 20;
+__host__ __device__ constexpr int pack_entry(int sid, int tile) { return (sid << TILE_BITS) | tile; }
+__host__ __device__ constexpr int entry_sid(int e) { return e >> TILE_BITS; }
+__host__ __device__ constexpr int entry_tile(int e) { return e & ((1 << TILE_BITS) - 1); }
+
 template <typename real>
 struct Args {
     const real* Hi; const real* Qxi; const real* Qyi;   // layer n
     real* Ho; real* Qxo; real* Qyo;                     // layer n+1
     const real* bed; const real* cf;                    // static
-    Ctrl* ctrl;
-    const int* list_in; int* list_out; int slot;        // tile lists
+    Ctrl* ctrl;                                         // this grid: clock, time step, source, errors
+    Ctrl* lctrl;                                        // the tile lists (the batch's for an ensemble)
+    int sid, tile_base;                                 // scenario index; its first stamp
+    int* hot;                                           // counters, one per 256-byte line
+    int* lists;                                         // [2 slots][NSEG segments][ntiles]
+    int slot;                                           // list slot read by this step
     int* stamp;                                         // de-duplication stamps
+    real* wg_speed;                                     // per-workgroup maximum speed
+    long long* wg_cells;                                // per-workgroup processed cells
     double* mass;                                       // per-tile sum of H
     double* ledger;                                     // per-tile clamp volume
     int nx, ny, ntx, nty, ntiles, skip, limiter;
+    int list_cap;                                       // capacity of one list segment
     int i0, j0, ni, nj;                                 // inlet rectangle
     real h, ih, g, eps, nuh2, fcor, wx, wy, kw, hw;     // stencil constants
     double h_d, g_d, cfl, tau_max, tau_min, nu_d, nin_h2;
@@ -96,9 +121,14 @@ template <> struct Mth<double> {
     static __device__ __forceinline__ double friction(double cf, double H) { return cf / (H * ::cbrt(H)); }
 };
 
-template <typename real> __device__ __forceinline__ real rmax(real a, real b) { return a > b ? a : b; }
-template <typename real> __device__ __forceinline__ real rmin(real a, real b) { return a < b ? a : b; }
-template <typename real> __device__ __forceinline__ real rabs(real a) { return a < real(0) ? -a : a; }
+// fmax/fmin/fabs map to single v_max/v_min instructions and a free abs
+// operand modifier (a ternary would cost a compare and a select each)
+__device__ __forceinline__ float rmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ float rmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float rabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double rmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double rmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double rabs(double a) { return __builtin_fabs(a); }
 // false for NaN and +-inf (compare against the largest finite value)
 __device__ __forceinline__ bool finite(float a) { return rabs(a) <= 3.40282347e38f; }
 __device__ __forceinline__ bool finite(double a) { return rabs(a) <= 1.7976931348623157e308; }
@@ -193,6 +223,10 @@ __device__ __forceinline__ void riemann(real g, const Face<real>& L, const Face<
 // is wet.
 template <typename real> struct Nb4 { real ux[4], uy[4]; bool w[4]; };
 
+// 1 for wet, 0 for dry: a dry neighbour (velocity 0, finite) then adds
+// 0 * (u_m - u_c) = +-0 to the viscous sum, the same as leaving it out.
+template <typename real> __device__ __forceinline__ real mask(bool w) { return w ? real(1) : real(0); }
+
 // Viscosity over wet face neighbours + Coriolis + wind at a cell with depth
 // H (layer n) and velocity (uxc, uyc).
 template <typename real>
@@ -201,8 +235,9 @@ __device__ __forceinline__ void soft_forces(const Args<real>& a, real H, real ux
     real vx = real(0), vy = real(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        vx += nb.w[k] ? nb.ux[k] - uxc : real(0);
-        vy += nb.w[k] ? nb.uy[k] - uyc : real(0);
+        const real m = mask<real>(nb.w[k]);
+        vx += m * (nb.ux[k] - uxc);
+        vy += m * (nb.uy[k] - uyc);
     }
     const real dx = a.wx - uxc, dy = a.wy - uyc;
     const real k = Mth<real>::div(a.kw * Mth<real>::sqrt(dx * dx + dy * dy), rmax(H, a.hw));
@@ -224,14 +259,18 @@ __device__ __forceinline__ real cfl_speed(const Args<real>& a, real H, real ux, 
     return rmax(us, rmax(upx, upy));
 }
 
-__device__ __forceinline__ void atomic_max_speed(Ctrl* c, float v) {
-    atomicMax(&c->speed32, __float_as_uint(v));
+__device__ __forceinline__ void atomic_max_prep(Ctrl* c, float v) {
+    atomicMax((unsigned int*)&c->prep_speed, __float_as_uint(v));
 }
-__device__ __forceinline__ void atomic_max_speed(Ctrl* c, double v) {
-    atomicMax(&c->speed64, (unsigned long long)__double_as_longlong(v));
+__device__ __forceinline__ void atomic_max_prep(Ctrl* c, double v) {
+    atomicMax(&c->prep_speed, (unsigned long long)__double_as_longlong(v));
 }
-__device__ __forceinline__ double read_speed(const Ctrl* c, float) { return (double)__uint_as_float(c->speed32); }
-__device__ __forceinline__ double read_speed(const Ctrl* c, double) { return __longlong_as_double((long long)c->speed64); }
+__device__ __forceinline__ double prep_speed(const Ctrl* c, float) {
+    return (double)__uint_as_float(*(const unsigned int*)&c->prep_speed);
+}
+__device__ __forceinline__ double prep_speed(const Ctrl* c, double) {
+    return __longlong_as_double((long long)c->prep_speed);
+}
 
 // Inflow volume over [t, t+tau] of the Gaussian hydrograph (closed form, FP64).
 __device__ __forceinline__ double hydro_volume(double qb, double qp, double tp, double st,
@@ -244,10 +283,9 @@ __device__ __forceinline__ double hydro_volume(double qb, double qp, double tp, 
     return v;
 }
 
-// Next time step and source from the maximum speed of the new layer.
+// Next time step and source from the maximum speed S of the new layer.
 template <typename real>
-__device__ void next_step_scalars(const Args<real>& a, Ctrl* c) {
-    const double S = read_speed(c, real(0));
+__device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
     double tau = a.tau_max > 0.0 ? a.tau_max : __builtin_inf();
     if (S > 0.0) tau = fmin(tau, a.cfl * a.h_d / S);
     if (a.nu_d > 0.0) tau = fmin(tau, a.h_d * a.h_d / (4.0 * a.nu_d));
@@ -259,12 +297,42 @@ __device__ void next_step_scalars(const Args<real>& a, Ctrl* c) {
         dV = hydro_volume(a.q_base, a.q_peak, a.t_peak, a.sigma_t, c->t, tau);
     c->dV = dV;
     c->sdepth = a.nin_h2 > 0.0 ? (double)(real)(dV / a.nin_h2) : 0.0;
-    c->speed32 = 0u;
-    c->speed64 = 0ull;
 }
 
-__device__ __forceinline__ void enqueue(int tile, int gen, int* stamp, int* list, int* count) {
-    if (atomicMax(&stamp[tile], gen) < gen) list[atomicAdd(count, 1)] = tile;
+// Prefix offsets of the list segments of `slot` from their counters.
+__device__ __forceinline__ void close_segments(Ctrl* c, int* hot, int slot) {
+    int off = 0;
+    c->seg_off[slot][0] = 0;
+    for (int g = 0; g < NSEG; ++g) {
+        off += hot[hot_seg(slot, g)];
+        c->seg_off[slot][g + 1] = off;
+    }
+}
+
+// Entry p of the list in `slot` (segments concatenated in order); cap is the
+// capacity of one segment.
+__device__ __forceinline__ int list_entry(const Ctrl* c, const int* lists, int cap, int slot, int p) {
+    int g = 0;
+#pragma unroll
+    for (int q = 1; q < NSEG; ++q) g += p >= c->seg_off[slot][q];
+    return lists[(slot * NSEG + g) * cap + p - c->seg_off[slot][g]];
+}
+
+// Append the candidate tiles of lanes 0..4 of one wave (cand < 0: none) of
+// scenario `sid` to segment `grp` of list `slot`: stamps de-duplicate across
+// the grid (one generation per list), one counter update per call reserves
+// the slots.
+__device__ __forceinline__ void append_tiles(int cand, int sid, int tile_base, int gen, int* stamp,
+                                             int* lists, int* hot, int cap, int slot, int grp) {
+    const int lane = threadIdx.x & 63;
+    const bool ok = cand >= 0 && atomicMax(&stamp[tile_base + cand], gen) < gen;
+    const unsigned long long m = __ballot(ok);
+    const int n = __popcll(m);
+    if (n == 0) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&hot[hot_seg(slot, grp)], n);
+    base = __shfl(base, 0, 64);
+    if (ok) lists[(slot * NSEG + grp) * cap + base + __popcll(m & ((1ull << lane) - 1ull))] = pack_entry(sid, cand);
 }
 
 template <typename real>
@@ -356,7 +424,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             const int x = k % RW - HALO, y = k / RW - HALO;
             int gx = tx0 + x, gy = ty0 + y, fx = 0, fy = 0;
             if constexpr (EDGE) { gx = mirror(gx, nx, fx); gy = mirror(gy, ny, fy); }
-            const long gi = (long)gy * nx + gx;
+            const int gi = gy * nx + gx;
             const real H = a.Hi[gi];
             real qx = a.Qxi[gi], qy = a.Qyi[gi];
             if constexpr (EDGE) { if (fx & 1) qx = -qx; if (fy & 1) qy = -qy; }
@@ -394,7 +462,16 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     Le[j][i] = b + He[j][i];
                     if (j == 1) { Bc[i] = b; if (i >= 1 && i <= RUN) any |= w; }
                 }
-            if (!__any(any)) continue;   // the whole wave is dry here
+            if (!__any(any)) {   // the whole wave is dry here: U^{n+1/2} = 0
+#pragma unroll
+                for (int i = 0; i < RUN; ++i) {
+                    if (!inside(x0 + i, y)) continue;
+                    const int s = G::at(x0 + i, y);
+                    L.HX[s] = real(0);
+                    L.HY[s] = real(0);
+                }
+                continue;
+            }
             real ux[RUN + 2], uy[RUN + 2], uxs[RUN], uys[RUN], uxn[RUN], uyn[RUN];
 #pragma unroll
             for (int i = 0; i < RUN + 2; ++i) {
@@ -423,7 +500,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real Gy = (al * (e[2][1] - e[0][1]) + be * ((e[2][2] - e[0][2]) + (e[2][0] - e[0][0]))) * a.ih;
                 const int gx = tx0 + x0 + i, gy = ty0 + y;
                 const bool ins = inside(x0 + i, y);
-                const real cf = ins ? a.cf[(long)gy * nx + gx] : real(0);
+                const real cf = ins ? a.cf[gy * nx + gx] : real(0);
                 const real lam0 = Mth<real>::friction(cf, wc ? Hc : real(1));
                 Nb4<real> nb;
                 nb.ux[0] = ux[c - 1]; nb.uy[0] = uy[c - 1]; nb.w[0] = He[1][c - 1] > real(0);
@@ -474,6 +551,23 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 hxn[i] = L.HX[sn]; hyn[i] = L.HY[sn]; wn[i] = L.H[sn] > eps;
             }
             real out[RUN][5];
+            bool anyw = false;
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) anyw |= wr[i + 1];
+            if (!__any(anyw)) {   // the whole wave is dry: no forces, Q_t = 0
+#pragma unroll
+                for (int i = 0; i < RUN; ++i) {
+                    const int x = x0 + i;
+                    if (!inside(x, y)) continue;
+                    const int s = G::at(x, y);
+                    L.UX[s] = is_src(a, tx0 + x, ty0 + y) ? Hr[i + 1] + sdep : Hr[i + 1];
+                    L.UY[s] = real(0);
+                    L.LM[s] = real(0);
+                    L.GX[s] = real(0);
+                    L.GY[s] = real(0);
+                }
+                continue;
+            }
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
                 const int c = i + 1, x = x0 + i;
@@ -532,6 +626,17 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const int s = G::at(x0 - 2 + i, y);
                 cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.UY[s]; cl[i].ut = L.LM[s];
             }
+            bool anyw = false;
+#pragma unroll
+            for (int i = 1; i < RUN + 2; ++i) anyw |= cl[i].H > eps;
+            if (!__any(anyw)) {   // dry on both sides of every face: zero fluxes
+#pragma unroll
+                for (int f = 0; f < RUN; ++f) {
+                    const int s = G::at(x0 + f, y);
+                    L.HX[s] = real(0); L.HY[s] = real(0); L.H[s] = real(0);
+                }
+                continue;
+            }
             Face<real> lo[RUN + 1], hi[RUN + 1];
 #pragma unroll
             for (int i = 0; i < RUN + 1; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
@@ -558,13 +663,21 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const int s = G::at(x, y0 - 2 + i);
                 cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.LM[s]; cl[i].ut = L.UY[s];
             }
-            Face<real> lo[RUN + 2], hi[RUN + 2];
-#pragma unroll
-            for (int i = 0; i < RUN + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
-            // recon index i is cell y0 - 1 + i; face y0 + f between cells f and f+1
             real FH[RUN + 1], Fn[RUN + 1], Ft[RUN + 1];
+            bool anyw = false;
 #pragma unroll
-            for (int f = 0; f < RUN + 1; ++f) riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
+            for (int i = 1; i < RUN + 3; ++i) anyw |= cl[i].H > eps;
+            if (__any(anyw)) {
+                Face<real> lo[RUN + 2], hi[RUN + 2];
+#pragma unroll
+                for (int i = 0; i < RUN + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
+                // recon index i is cell y0 - 1 + i; face y0 + f between cells f and f+1
+#pragma unroll
+                for (int f = 0; f < RUN + 1; ++f) riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
+            } else {   // dry on both sides of every face of the run: zero fluxes
+#pragma unroll
+                for (int f = 0; f < RUN + 1; ++f) { FH[f] = real(0); Fn[f] = real(0); Ft[f] = real(0); }
+            }
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
                 const int y = y0 + i;
@@ -583,7 +696,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 L.GX[s] = w ? Mth<real>::div(qxo, Hc) : real(0);
                 L.GY[s] = w ? Mth<real>::div(qyo, Hc) : real(0);
                 if (x >= 0 && x < TX && y >= 0 && y < TY) {
-                    const long gi = (long)(ty0 + y) * nx + tx0 + x;
+                    const int gi = (ty0 + y) * nx + tx0 + x;
                     a.Ho[gi] = Hc;
                     a.Qxo[gi] = qxo;
                     a.Qyo[gi] = qyo;
@@ -651,12 +764,14 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
     __shared__ Lds<real, TX, TY> L;
     __shared__ double red_d[2][NWAVE];
     __shared__ int red_i[NWAVE];
+    __shared__ long long red_l[NWAVE];
     __shared__ int s_last;
 
     Ctrl* const ctrl = a.ctrl;
     if (ctrl->err_gate) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int count = a.skip ? ctrl->count[a.slot] : a.ntiles;
+    const int G = gridDim.x, grp = blockIdx.x % NSEG;
+    const int count = a.skip ? ctrl->seg_off[a.slot][NSEG] : a.ntiles;
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
     const int gen = (int)ctrl->step + 2;
@@ -666,8 +781,8 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
     bool bad = false;
     long long ncells = 0;
 
-    for (int p = blockIdx.x; p < count; p += gridDim.x) {
-        const int tile = a.skip ? a.list_in[p] : p;
+    for (int p = blockIdx.x; p < count; p += G) {
+        const int tile = a.skip ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p)) : p;
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
@@ -685,25 +800,32 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
         lsum = wave_sum(lsum);
         if (lane == 0) { red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum; }
         __syncthreads();
-        if (tid == 0) {
+        if (wv == 0) {
             int bb = 0;
-            double ms = 0.0, ls = 0.0;
-            for (int q = 0; q < NWAVE; ++q) { bb |= red_i[q]; ms += red_d[0][q]; ls += red_d[1][q]; }
-            a.mass[tile] = ms;
-            a.ledger[tile] += ls * a.h_d * a.h_d;
+#pragma unroll
+            for (int q = 0; q < NWAVE; ++q) bb |= red_i[q];
+            if (lane == 0) {
+                double ms = 0.0, ls = 0.0;
+                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; }
+                a.mass[tile] = ms;
+                a.ledger[tile] += ls * a.h_d * a.h_d;
+            }
             if (a.skip) {
+                // next list: this tile if K1-active at layer n or n+1, and the
+                // neighbours facing its wet edges (layer n+1)
                 const int ti = tile % a.ntx, tj = tile / a.ntx;
-                int* cnt = &ctrl->count[a.slot ^ 1];
-                if (bb & (1 | 32 | 64)) enqueue(tile, gen, a.stamp, a.list_out, cnt);
-                if ((bb & 2) && ti > 0) enqueue(tile - 1, gen, a.stamp, a.list_out, cnt);
-                if ((bb & 4) && ti < a.ntx - 1) enqueue(tile + 1, gen, a.stamp, a.list_out, cnt);
-                if ((bb & 8) && tj > 0) enqueue(tile - a.ntx, gen, a.stamp, a.list_out, cnt);
-                if ((bb & 16) && tj < a.nty - 1) enqueue(tile + a.ntx, gen, a.stamp, a.list_out, cnt);
+                int cand = -1;
+                if (lane == 0 && (bb & (1 | 32 | 64))) cand = tile;
+                if (lane == 1 && (bb & 2) && ti > 0) cand = tile - 1;
+                if (lane == 2 && (bb & 4) && ti < a.ntx - 1) cand = tile + 1;
+                if (lane == 3 && (bb & 8) && tj > 0) cand = tile - a.ntx;
+                if (lane == 4 && (bb & 16) && tj < a.nty - 1) cand = tile + a.ntx;
+                append_tiles(cand, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp);
             }
         }
     }
 
-    // ---- completion: maximum speed, error flag, last workgroup finalises
+    // ---- completion: per-workgroup results, two-level counter, last workgroup finalises
     vmax = wave_max(vmax);
     __syncthreads();
     if (lane == 0) red_d[0][wv] = (double)vmax;
@@ -711,25 +833,45 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
     if (tid == 0) {
         double vm = 0.0;
         for (int q = 0; q < NWAVE; ++q) vm = fmax(vm, red_d[0][q]);
-        if (vm > 0.0) atomic_max_speed(ctrl, (real)vm);
+        a.wg_speed[blockIdx.x] = (real)vm;
+        a.wg_cells[blockIdx.x] = ncells;
         if (anybad) atomicCAS(&ctrl->err, 0, -4);
-        if (ncells) atomicAdd((unsigned long long*)&ctrl->cells, (unsigned long long)ncells);
         __threadfence();
-        const unsigned prev = atomicAdd(&ctrl->done, 1u);
-        s_last = prev == gridDim.x - 1;
+        const int in_grp = (G - grp + NSEG - 1) / NSEG, ngrp = G < NSEG ? G : NSEG;
+        bool last = false;
+        if (atomicAdd((unsigned*)&a.hot[hot_done(grp)], 1u) == (unsigned)(in_grp - 1))
+            last = atomicAdd((unsigned*)&a.hot[hot_done(NSEG)], 1u) == (unsigned)(ngrp - 1);
+        s_last = last;
     }
     __syncthreads();
-    if (s_last && tid == 0) {
-        __threadfence();
+    if (!s_last) return;
+    __threadfence();
+    real vm = real(0);
+    long long cs = 0;
+    for (int k = tid; k < G; k += NT) { vm = rmax(vm, a.wg_speed[k]); cs += a.wg_cells[k]; }
+    vm = wave_max(vm);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cs += __shfl_xor(cs, o, 64);
+    __syncthreads();
+    if (lane == 0) { red_d[0][wv] = (double)vm; red_l[wv] = cs; }
+    __syncthreads();
+    if (tid == 0) {
+        double S = 0.0;
+        long long cells = 0;
+        for (int q = 0; q < NWAVE; ++q) { S = fmax(S, red_d[0][q]); cells += red_l[q]; }
         const double tau_done = ctrl->tau;
         ctrl->t += tau_done;
         ctrl->inflow += ctrl->dV;
         ctrl->last_tau = tau_done;
         ctrl->step += 1;
         ctrl->tiles += count;
-        if (a.skip) ctrl->count[a.slot] = 0;
-        next_step_scalars(a, ctrl);
-        ctrl->done = 0u;
+        ctrl->cells += cells;
+        next_step_scalars(a, ctrl, S);
+        if (a.skip) {
+            close_segments(ctrl, a.hot, a.slot ^ 1);
+            for (int g = 0; g < NSEG; ++g) a.hot[hot_seg(a.slot, g)] = 0;
+        }
+        for (int g = 0; g <= NSEG; ++g) a.hot[hot_done(g)] = 0;
         if (ctrl->err) ctrl->err_gate = ctrl->err;
         __threadfence();
     }
@@ -754,7 +896,7 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         const int lx = k % W - 1, ly = k / W - 1;
         int fx = 0, fy = 0;
         const int gx = mirror(tx0 + lx, nx, fx), gy = mirror(ty0 + ly, ny, fy);
-        const long gi = (long)gy * nx + gx;
+        const int gi = gy * nx + gx;
         const real H = a.Hi[gi];
         real qx = a.Qxi[gi], qy = a.Qyi[gi];
         if (fx & 1) qx = -qx;
@@ -804,8 +946,14 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         int ac = 0;
         for (int q = 0; q < NWAVE; ++q) { vm = rmax(vm, red_v[q]); ms += red_d[q]; ac |= red_i[q]; }
         a.mass[tile] = ms;
-        if (vm > real(0)) atomic_max_speed(a.ctrl, vm);
-        if (a.skip && ac) enqueue(tile, (int)a.ctrl->step + 1, a.stamp, a.list_out, &a.ctrl->count[a.slot]);
+        if (vm > real(0)) atomic_max_prep(a.ctrl, vm);
+    }
+    if (a.skip && wv == 0) {
+        int ac0 = 0;
+#pragma unroll
+        for (int q = 0; q < NWAVE; ++q) ac0 |= red_i[q];
+        append_tiles(lane == 0 && ac0 ? tile : -1, a.sid, a.tile_base, (int)a.lctrl->step + 1, a.stamp, a.lists,
+                     a.hot, a.list_cap, a.slot, blockIdx.x % NSEG);
     }
 }
 
@@ -815,10 +963,159 @@ __global__ void k_prepare_finish(Args<real> a) {
         Ctrl* c = a.ctrl;
         c->err = 0;
         c->err_gate = 0;
-        c->done = 0u;
-        next_step_scalars(a, c);
+        next_step_scalars(a, c, prep_speed(c, real(0)));
+        c->prep_speed = 0ull;
+        if (a.skip) close_segments(a.lctrl, a.hot, a.slot);
         if (c->err) c->err_gate = c->err;
     }
+}
+
+// ---------------------------------------------------------------- batched ensemble
+// Independent scenarios of uneven grid sizes advanced together: one launch per
+// step processes the active tiles of every scenario from one shared list
+// (entries tagged with the scenario), each scenario with its own time step,
+// clock, hydrograph and error state (Sec. 1: hundreds of runs over hydrograph
+// and hydraulic-structure settings).  The tile work is the same tile_step as
+// a single grid, so a scenario in a batch equals its standalone run bitwise.
+template <typename real>
+struct BatchArgs {
+    const Args<real>* scen;   // per scenario, buffers of this step's parity
+    int n;                    // scenarios
+    Ctrl* lctrl;              // list control of the batch
+    int* hot;
+    int* lists;
+    int list_cap;             // capacity of one list segment (all tiles of the batch)
+    int slot;                 // list slot read by this step
+    long long* wg_cells;
+};
+
+template <typename real, int TX, int TY, int NT, int LIM>
+__global__ __launch_bounds__(NT, 2048 / NT) void k_batch_step(BatchArgs<real> ba) {
+    constexpr int NWAVE = NT / 64;
+    __shared__ Lds<real, TX, TY> L;
+    __shared__ double red_d[3][NWAVE];
+    __shared__ int red_i[NWAVE];
+    __shared__ long long red_l[NWAVE];
+    __shared__ int s_last;
+
+    Ctrl* const lc = ba.lctrl;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int G = gridDim.x, grp = blockIdx.x % NSEG;
+    const int count = lc->seg_off[ba.slot][NSEG];
+    const int gen = (int)lc->step + 2;
+    long long ncells = 0;
+
+    for (int p = blockIdx.x; p < count; p += G) {
+        const int e = list_entry(lc, ba.lists, ba.list_cap, ba.slot, p);
+        const int sid = entry_sid(e), tile = entry_tile(e);
+        const Args<real>& a = ba.scen[sid];
+        Ctrl* const c = a.ctrl;
+        if (c->err_gate) continue;   // a stopped scenario drops out of the lists
+        const real tau = (real)c->tau, sdep = (real)c->sdepth;
+        const int nx = a.nx, ny = a.ny;
+        const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+        ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
+        const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
+        real vt = real(0);
+        bool bad = false;
+        double msum = 0.0, lsum = 0.0;
+        int bits = 0;
+        __syncthreads();   // LDS of the previous tile is free
+        if (edge)
+            tile_step<real, TX, TY, NT, LIM, true>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+        else
+            tile_step<real, TX, TY, NT, LIM, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
+        bits |= __any(bad) ? 128 : 0;
+        msum = wave_sum(msum);
+        lsum = wave_sum(lsum);
+        vt = wave_max(vt);
+        if (lane == 0) { red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum; red_d[2][wv] = (double)vt; }
+        __syncthreads();
+        if (wv == 0) {
+            int bb = 0;
+#pragma unroll
+            for (int q = 0; q < NWAVE; ++q) bb |= red_i[q];
+            if (lane == 0) {
+                double ms = 0.0, ls = 0.0, vm = 0.0;
+                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; vm = fmax(vm, red_d[2][q]); }
+                a.mass[tile] = ms;
+                a.ledger[tile] += ls * a.h_d * a.h_d;
+                if (vm > 0.0) atomic_max_prep(c, (real)vm);
+                if (bb & 128) atomicCAS(&c->err, 0, -4);
+            }
+            if (a.skip) {
+                const int ti = tile % a.ntx, tj = tile / a.ntx;
+                int cand = -1;
+                if (lane == 0 && (bb & (1 | 32 | 64))) cand = tile;
+                if (lane == 1 && (bb & 2) && ti > 0) cand = tile - 1;
+                if (lane == 2 && (bb & 4) && ti < a.ntx - 1) cand = tile + 1;
+                if (lane == 3 && (bb & 8) && tj > 0) cand = tile - a.ntx;
+                if (lane == 4 && (bb & 16) && tj < a.nty - 1) cand = tile + a.ntx;
+                append_tiles(cand, sid, a.tile_base, gen, a.stamp, ba.lists, ba.hot, ba.list_cap, ba.slot ^ 1, grp);
+            }
+        }
+    }
+
+    // ---- completion: two-level counter; the last workgroup finalises every scenario
+    if (tid == 0) {
+        ba.wg_cells[blockIdx.x] = ncells;
+        __threadfence();
+        const int in_grp = (G - grp + NSEG - 1) / NSEG, ngrp = G < NSEG ? G : NSEG;
+        bool last = false;
+        if (atomicAdd((unsigned*)&ba.hot[hot_done(grp)], 1u) == (unsigned)(in_grp - 1))
+            last = atomicAdd((unsigned*)&ba.hot[hot_done(NSEG)], 1u) == (unsigned)(ngrp - 1);
+        s_last = last;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    long long cs = 0;
+    for (int k = tid; k < G; k += NT) cs += ba.wg_cells[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cs += __shfl_xor(cs, o, 64);
+    if (lane == 0) red_l[wv] = cs;
+    for (int k = tid; k < ba.n; k += NT) {
+        const Args<real>& a = ba.scen[k];
+        Ctrl* const c = a.ctrl;
+        if (c->err_gate) continue;
+        const double tau_done = c->tau;
+        c->t += tau_done;
+        c->inflow += c->dV;
+        c->last_tau = tau_done;
+        c->step += 1;
+        next_step_scalars(a, c, prep_speed(c, real(0)));
+        c->prep_speed = 0ull;
+        if (c->err) c->err_gate = c->err;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long cells = 0;
+        for (int q = 0; q < NWAVE; ++q) cells += red_l[q];
+        lc->step += 1;
+        lc->tiles += count;
+        lc->cells += cells;
+        close_segments(lc, ba.hot, ba.slot ^ 1);
+        for (int g = 0; g < NSEG; ++g) ba.hot[hot_seg(ba.slot, g)] = 0;
+        for (int g = 0; g <= NSEG; ++g) ba.hot[hot_done(g)] = 0;
+    }
+    __threadfence();
+}
+
+// After the per-scenario preparation kernels: first time steps and list offsets.
+template <typename real>
+__global__ void k_batch_prepare_finish(BatchArgs<real> ba) {
+    for (int k = threadIdx.x; k < ba.n; k += blockDim.x) {
+        const Args<real>& a = ba.scen[k];
+        Ctrl* const c = a.ctrl;
+        c->err = 0;
+        c->err_gate = 0;
+        next_step_scalars(a, c, prep_speed(c, real(0)));
+        c->prep_speed = 0ull;
+        if (c->err) c->err_gate = c->err;
+    }
+    if (threadIdx.x == 0) close_segments(ba.lctrl, ba.hot, ba.slot);
 }
 
 // Fixed-order FP64 sum of per-tile partials (one workgroup of 1024 threads).

@@ -158,3 +158,107 @@ def random_state(nx, ny, h=5.0, seed=0, wet_frac=0.6, precision=32, **prm):
     p.update(prm)
     return dict(name="random-%dx%d" % (nx, ny), nx=nx, ny=ny, h=h, b=b, n_manning=nm,
                 solid=None, H0=H0, Qx0=Qx0, Qy0=Qy0, params=p, steps=200)
+
+
+def ensemble(n=256, seed0=1000, side_min=256, side_max=2048, h=25.0, gates_max=12,
+             precision=32):
+    """Batched-ensemble stand-in: scenario k (seed seed0 + k) has a square
+    grid whose side is drawn log-uniformly from [side_min, side_max], the
+    floodplain terrain family, a Gaussian inflow with peak U(5e3, 3e4) m^3/s
+    at U(1, 5) days (base flow 0.1 of the peak, sigma = t_peak/3, clock from
+    0), and 0..gates_max gate cells on the channel, each closed with
+    probability 1/2 (a closed gate is a solid cell)."""
+    out = []
+    for k in range(n):
+        rng = _rng(seed0 + k)
+        side = int(round(math.exp(rng.uniform(math.log(side_min), math.log(side_max)))))
+        q_peak = float(rng.uniform(5e3, 3e4))
+        t_peak = float(rng.uniform(1.0, 5.0)) * 86400.0
+        sc = floodplain(n=side, h=h, seed=int(rng.integers(2**31)), q_peak=q_peak, t_peak=t_peak,
+                        sigma_t=t_peak / 3.0, precision=precision)
+        sc["params"]["q_base"] = 0.1 * q_peak
+        ngates = int(rng.integers(0, gates_max + 1))
+        solid = np.zeros((side, side), np.uint8)
+        i0, j0, ni, nj = sc["params"]["inlet"]
+        cand = np.argwhere(sc["H0"] > 0.0)                 # channel cells
+        cand = cand[cand[:, 1] >= i0 + ni + 2]             # downstream of the inlet
+        if ngates and len(cand):
+            pick = cand[rng.choice(len(cand), size=min(ngates, len(cand)), replace=False)]
+            closed = rng.uniform(size=len(pick)) < 0.5
+            for (j, i), c in zip(pick, closed):
+                if c:
+                    solid[j, i] = 1
+        sc["solid"] = solid if solid.any() else None
+        sc["name"] = "ensemble-%d-side%d" % (k, side)
+        sc["steps"] = 2000
+        out.append(sc)
+    return out
+
+
+def _bilinear_up(z, r):
+    """Cell-centred bilinear upsampling by r with edge clamping."""
+    ny, nx = z.shape
+    x = (np.arange(nx * r) + 0.5) / r - 0.5
+    y = (np.arange(ny * r) + 0.5) / r - 0.5
+    x0 = np.clip(np.floor(x).astype(int), 0, nx - 1)
+    y0 = np.clip(np.floor(y).astype(int), 0, ny - 1)
+    x1 = np.clip(x0 + 1, 0, nx - 1)
+    y1 = np.clip(y0 + 1, 0, ny - 1)
+    fx = np.clip(x - x0, 0.0, 1.0)[None, :]
+    fy = np.clip(y - y0, 0.0, 1.0)[:, None]
+    a = z[np.ix_(y0, x0)] * (1 - fx) + z[np.ix_(y0, x1)] * fx
+    b = z[np.ix_(y1, x0)] * (1 - fx) + z[np.ix_(y1, x1)] * fx
+    return a * (1 - fy) + b * fy
+
+
+def nest(coarse, boxes, r=4, seed=0, detail=0.5):
+    """Nested-grid inputs: a coarse scenario and refined patches over the
+    coarse boxes (ci0, cj0, cw, ch).  The fine bed is the bilinear
+    upsampling of the coarse bed plus fBm detail of `detail` metres; each
+    covered coarse cell takes the mean of its r x r fine bed cells, so that
+    the coarse grid sees the fine bed's volume.  Fine initial water fills to
+    the parent coarse cell's level where that cell is wet (still water); the
+    covered coarse cells take the mean fine depth.  A patch carries the
+    extended fine grid (frame of NEST_FRAME fine cells round the covered
+    area).  Fine cells take the unit discharge of their parent where they are
+    wet; covered coarse cells take the mean fine discharge."""
+    G = NEST_FRAME
+    c = dict(coarse)
+    bc = np.array(coarse["b"], dtype=np.float64)
+    Hc = np.array(coarse["H0"], dtype=np.float64)
+    Qxc = np.array(coarse["Qx0"], dtype=np.float64)
+    Qyc = np.array(coarse["Qy0"], dtype=np.float64)
+    nmc = np.asarray(coarse["n_manning"], dtype=np.float64)
+    up = _bilinear_up(bc, r)
+    rng = _rng(seed)
+    d = fbm(up.shape[0], up.shape[1], 0.8, rng.integers(2**63), detail)
+    bf_all = up + d - 0.5 * detail
+    eta_c = np.where(Hc > 0.0, Hc + bc, -np.inf)
+    patches = []
+    for (ci0, cj0, cw, ch) in boxes:
+        # extended fine window in global fine indices
+        fi0, fj0 = ci0 * r - G, cj0 * r - G
+        nxf, nyf = cw * r + 2 * G, ch * r + 2 * G
+        bf = bf_all[fj0:fj0 + nyf, fi0:fi0 + nxf].copy()
+        par_i = np.floor_divide(np.arange(nxf) + fi0, r)
+        par_j = np.floor_divide(np.arange(nyf) + fj0, r)
+        PJ, PI = np.meshgrid(par_j, par_i, indexing="ij")
+        nmf = nmc[PJ, PI].copy()
+        eta = eta_c[PJ, PI]
+        Hf = np.where(np.isfinite(eta), np.maximum(eta - bf, 0.0), 0.0)
+        Qxf = np.where(Hf > 0.0, Qxc[PJ, PI], 0.0)
+        Qyf = np.where(Hf > 0.0, Qyc[PJ, PI], 0.0)
+        inner = (slice(G, G + ch * r), slice(G, G + cw * r))
+        cov = (slice(cj0, cj0 + ch), slice(ci0, ci0 + cw))
+        for fine_f, coarse_f in ((bf, bc), (Hf, Hc), (Qxf, Qxc), (Qyf, Qyc)):
+            coarse_f[cov] = fine_f[inner].reshape(ch, r, cw, r).mean(axis=(1, 3))
+        patches.append(dict(ci0=ci0, cj0=cj0, cw=cw, ch=ch, b=bf, n_manning=nmf,
+                            H0=Hf[inner].copy(), Qx0=Qxf[inner].copy(), Qy0=Qyf[inner].copy()))
+    c["b"], c["H0"], c["Qx0"], c["Qy0"] = bc, Hc, Qxc, Qyc
+    c["name"] = coarse["name"] + "-nest%d" % len(boxes)
+    return dict(coarse=c, patches=patches, r=r)
+
+
+# Frame width of a patch in fine cells: one more than the reach of one step
+# of the scheme (4 cells).
+NEST_FRAME = 5

@@ -61,6 +61,16 @@ EXPORTS = {
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "swe_active_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "swe_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
+    "swe_batch_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), _dp, ctypes.POINTER(_dp),
+                                           ctypes.POINTER(_dp), ctypes.POINTER(SweParams)]),
+    "swe_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
+    "swe_batch_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
+    "swe_batch_query": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]),
+    "swe_batch_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]),
+    "swe_batch_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]),
+    "swe_batch_destroy": (None, [ctypes.c_void_p]),
     "swe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -248,3 +258,81 @@ class Solver:
         if cnt < 0:
             _check(cnt)
         return np.sort(np.array(buf[:cnt], dtype=np.int64))
+
+
+class Batch:
+    """Scenarios of uneven grid sizes advanced together by one launch per step
+    (``swe_batch_*``).  Each scenario is a dict as for :class:`Solver`;
+    precision, limiter and tile shape come from the first one."""
+
+    def __init__(self, scenarios, tile=(0, 0), precision=None, stream="torch"):
+        L = load()
+        n = len(scenarios)
+        st = current_stream() if stream == "torch" else stream
+        self.shapes = [(int(sc["ny"]), int(sc["nx"])) for sc in scenarios]
+        self._keep = []
+        nx = (ctypes.c_int * n)(*[int(sc["nx"]) for sc in scenarios])
+        ny = (ctypes.c_int * n)(*[int(sc["ny"]) for sc in scenarios])
+        dx = (ctypes.c_double * n)(*[float(sc["h"]) for sc in scenarios])
+        bs = (_dp * n)()
+        nms = (_dp * n)()
+        prm = (SweParams * n)()
+        for k, sc in enumerate(scenarios):
+            shp = self.shapes[k]
+            pr = dict(sc["params"])
+            if precision is not None:
+                pr["precision"] = precision
+            p = make_params(pr, True, tile, st)
+            b = _f64(sc["b"], shp)
+            nm = _f64(sc.get("n_manning"), shp)
+            H0, Qx0, Qy0 = (_f64(sc.get(q), shp) for q in ("H0", "Qx0", "Qy0"))
+            solid = sc.get("solid")
+            solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+            p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
+            self._keep += [b, nm, H0, Qx0, Qy0, solid]
+            bs[k] = _ptr(b)
+            nms[k] = _ptr(nm)
+            prm[k] = p
+        self.n = n
+        self._h = L.swe_batch_create(n, nx, ny, dx, bs, nms, prm)
+        self._keep = None
+        if not self._h:
+            raise SweError(SWE_EINVAL, last_error())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def run(self, n):
+        return _check(load().swe_batch_run(self._h, int(n)))
+
+    def run_rc(self, n):
+        return load().swe_batch_run(self._h, int(n))
+
+    def run_timed(self, n):
+        ms = ctypes.c_double(0.0)
+        _check(load().swe_batch_run_timed(self._h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def query(self):
+        n = self.n
+        t, m, q, l = (np.empty(n) for _ in range(4))
+        st = (ctypes.c_long * n)()
+        _check(load().swe_batch_query(self._h, _ptr(t), _ptr(m), _ptr(q), _ptr(l), st))
+        return dict(time=t, mass=m, inflow=q, ledger=l, steps=np.array(st[:], dtype=np.int64))
+
+    def state(self, k):
+        shp = self.shapes[k]
+        H, Qx, Qy = (np.empty(shp) for _ in range(3))
+        _check(load().swe_batch_get_state(self._h, int(k), _ptr(H), _ptr(Qx), _ptr(Qy)))
+        return H, Qx, Qy
+
+    def work(self):
+        t, c, n = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        _check(load().swe_batch_work(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(n)))
+        return dict(tile_steps=t.value, cell_steps=c.value, total_tiles=n.value)
