@@ -177,6 +177,73 @@ int    swe_batch_work(swe_batch_t* b, long long* tile_steps, long long* cell_ste
 /* Free the batch and its device memory.  NULL-safe. */
 void   swe_batch_destroy(swe_batch_t* b);
 
+/* ------------------------------------------------------------------ nests
+ * Hierarchical grids (Sec. 2.2: the small-scale flow of zoomed-in areas fed
+ * back into the large-scale grid; Sec. 5: a 50 m grid with a 12.5 m local
+ * grid): one coarse grid and patches refined by r over boxes of coarse
+ * cells.  Per coarse step the coarse grid steps with tau_c, every patch takes
+ * r substeps of tau_c / r inside a frame of SWE_NEST_FRAME fine cells filled
+ * from the coarse layers n and n+1 (linear in time; fine depth
+ * max(0, H_c + b_c - b_fine) where the coarse cell is wet, else dry), and
+ * with feedback the covered coarse cells take the mean of their fine cells
+ * while the uncovered cells next to a box take the mismatch between the
+ * coarse and the summed fine fluxes through their shared face (clamped as in
+ * the final update).  tau_c = min(CFL step of the coarse layer as stepped and
+ * of the cells the feedback changed, r * CFL step of every patch after its
+ * last substep).  Without feedback (one-way zoom-in) the coarse grid runs as
+ * if alone and drives the patches.  The paper names the method, not the
+ * coupling; this is the reading implemented. */
+#define SWE_NEST_FRAME 5
+
+typedef struct {
+    int ci0, cj0, cw, ch;       /* covered coarse cells [ci0, ci0+cw) x [cj0, cj0+ch) */
+    /* fine bed [m] and Manning n over the extended patch, row-major
+     * (r*ch + 2*SWE_NEST_FRAME) x (r*cw + 2*SWE_NEST_FRAME); n may be NULL */
+    const double* b;
+    const double* n_M;
+    /* initial interior state, (r*ch) x (r*cw) row-major; NULL = 0 */
+    const double* H0;
+    const double* Qx0;
+    const double* Qy0;
+} swe_patch;
+
+typedef struct swe_nest_s swe_nest_t;
+
+/* Create a nest: the coarse grid as for swe_create (p: its parameters, the
+ * patches inherit the physics; tile_x = tile_y = 0 required), refinement
+ * 1 <= r <= 16 and npatch >= 1 patches.  Every box keeps
+ * ceil(SWE_NEST_FRAME / r) coarse cells from the domain edge, one uncovered
+ * cell from every other box and from the inlet, and holds no closed gate
+ * in it or its frame.  The coarse bed under a box should be the mean of the
+ * fine bed (it is taken as given).  Patches step every tile (no dry
+ * skipping).  NULL on error. */
+swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const double* n_M,
+                            const swe_params* p, int r, int feedback, int npatch,
+                            const swe_patch* patches);
+
+/* Advance n coarse steps (each with its r substeps; hipGraph replay).
+ * Synchronises; returns 0 or an SWE_E* code. */
+int    swe_nest_run(swe_nest_t* n, long coarse_steps);
+
+/* As swe_nest_run with a HIP event pair around every coarse step (all its
+ * launches); the summed time goes to *kernel_ms. */
+int    swe_nest_run_timed(swe_nest_t* n, long coarse_steps, double* kernel_ms);
+
+/* Clock [s], volume of the nested solution (FP64 sum of the coarse depths,
+ * covered cells holding the fine mean) [m^3], hydrograph volume [m^3], clamp
+ * ledger (coarse grid plus feedback) [m^3], completed coarse steps, and the
+ * time steps of the next coarse step and substeps [s].  Any may be NULL. */
+int    swe_nest_query(swe_nest_t* n, double* t, double* volume, double* inflow, double* ledger,
+                      long* steps, double* dt_coarse, double* dt_fine);
+
+/* Host FP64 copy of the coarse state (nx*ny each) or of patch k's interior
+ * ((r*ch) x (r*cw) each); any may be NULL. */
+int    swe_nest_get_coarse(swe_nest_t* n, double* H, double* Qx, double* Qy);
+int    swe_nest_get_patch(swe_nest_t* n, int k, double* H, double* Qx, double* Qy);
+
+/* Free the nest and its device memory.  NULL-safe. */
+void   swe_nest_destroy(swe_nest_t* n);
+
 /* Message of the last error on this host thread ("" if none). */
 const char* swe_last_error(void);
 

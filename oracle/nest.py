@@ -10,8 +10,12 @@ local grid).  The coupling is not spelled out in the paper; the reading used
 here is coarse-first subcycling with conservative flux matching:
 
   per coarse step
-  1. time steps: tau_c = min(tau_coarse, r * min_k tau_k) from the current
-     layers, tau_f = tau_c / r;
+  1. time steps: tau_c = min(tau_coarse, r * min_k tau_k), tau_f = tau_c / r,
+     where tau_k is the CFL step of patch k after its last substep (frame
+     included) and tau_coarse the CFL step of the largest of two speeds: the
+     coarse layer as the coarse step produced it, and the layer after the
+     feedback on the covered cells widened by 2 (the cells whose speed the
+     feedback can change); at the start, the CFL steps of the initial layers;
   2. the coarse grid advances over the whole domain with tau_c; the fluxes on
      the faces bounding each covered region are recorded (times tau_c);
   3. each patch advances r substeps with tau_f.  A patch is an ordinary grid
@@ -30,9 +34,7 @@ here is coarse-first subcycling with conservative flux matching:
      difference between the recorded coarse flux and the mean of the r fine
      face fluxes over the r substeps (depth clamped at 0 into the ledger, Q
      zeroed where H <= eps, as in the final update);
-  6. the coarse bed under a patch is the mean of the fine bed (an input);
-  7. the frames are refilled from the new coarse layer, so that the next
-     fine time step sees the current boundary values.
+  6. the coarse bed under a patch is the mean of the fine bed (an input).
 Without feedback (one-way zoom-in) steps 4 and 5 are skipped: the coarse grid
 runs as if alone and only drives the patches.  Patches must not touch each
 other, the domain edge (ceil(G/r) coarse cells of margin for the frame)
@@ -96,6 +98,11 @@ class OracleNest:
                     raise ValueError("patches must keep one uncovered coarse cell between them")
         Hc, Qxc, Qyc = self.c.state()
         self._fill_all(Hc, Qxc, Qyc, Hc, Qxc, Qyc, 0.0)
+        self.region = np.zeros((coarse["ny"], coarse["nx"]), dtype=bool)
+        for p in patches:
+            self.region[max(p["cj0"] - 2, 0):p["cj0"] + p["ch"] + 2,
+                        max(p["ci0"] - 2, 0):p["ci0"] + p["cw"] + 2] = True
+        self._set_taus(self.c.next_tau(), [P["sim"].next_tau() for P in self.P])
 
     # -------------------------------------------------------------- pieces
 
@@ -126,11 +133,13 @@ class OracleNest:
         for P in self.P:
             P["sim"].set_state(*self._frame(P, Hc0, Qxc0, Qyc0, Hc1, Qxc1, Qyc1, theta))
 
+    def _set_taus(self, tau_coarse, tau_patches):
+        tau_c = min([tau_coarse] + [self.r * t for t in tau_patches])
+        self.tau_c, self.tau_f = tau_c, tau_c / self.r
+
     def next_taus(self):
-        tc = self.c.next_tau()
-        tf = min(P["sim"].next_tau() for P in self.P) if self.P else np.inf
-        tau_c = min(tc, self.r * tf)
-        return tau_c, tau_c / self.r
+        """Coarse and fine time steps of the next coarse step."""
+        return self.tau_c, self.tau_f
 
     # -------------------------------------------------------------- one coarse step
 
@@ -142,6 +151,7 @@ class OracleNest:
             tau_f = tau_c / r
         Hc0, Qxc0, Qyc0 = self.c.state()
         self.c.step(tau_c)
+        s_pre = self.c.cell_speeds().max()
         # time-integrated coarse face fluxes; x faces (ny, nx+1) carry
         # (H, x-momentum, y-momentum), y faces (ny+1, nx) carry (H, y-momentum, x-momentum)
         cx = [tau_c * f for f in self.c.faces(0)]
@@ -150,6 +160,7 @@ class OracleNest:
         H, Qx, Qy = Hc1.copy(), Qxc1.copy(), Qyc1.copy()
         dH, dQx, dQy = (np.zeros_like(H) for _ in range(3))
         ring = np.zeros(H.shape, dtype=bool)
+        tau_k = []
         for P in self.P:
             p, sim = P["spec"], P["sim"]
             nxf, nyf = P["nxf"], P["nyf"]
@@ -164,6 +175,7 @@ class OracleNest:
                     fx[q][:, 1] += tau_f * Fx[q][G:G + nyf, G + nxf]
                     fy[q][0, :] += tau_f * Fy[q][G, G:G + nxf]
                     fy[q][1, :] += tau_f * Fy[q][G + nyf, G:G + nxf]
+            tau_k.append(sim.next_tau())
             if not self.feedback:
                 continue
             Hf, Qxf, Qyf = sim.state()
@@ -197,7 +209,9 @@ class OracleNest:
             Qy = np.where(ring, np.where(wet, Qy + dQy, 0.0), Qy)
             H = np.where(ring, Hcl, H)
             self.c.set_state(H, Qx, Qy)
-        self._fill_all(H, Qx, Qy, H, Qx, Qy, 0.0)
+            s_post = self.c.cell_speeds()[self.region].max()
+            s_pre = max(s_pre, s_post)
+        self._set_taus(self.c.tau_from_speed(s_pre), tau_k)
 
     def run(self, n, tau_c=None):
         for _ in range(n):

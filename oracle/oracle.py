@@ -77,6 +77,9 @@ def lib():
         L.orc_get_field.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_double_p]
         L.orc_get_faces.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                     _c_double_p, _c_double_p]
+        L.orc_cell_speeds.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.orc_tau_from_speed.restype = ctypes.c_double
+        L.orc_tau_from_speed.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_hydrograph_volume.restype = ctypes.c_double
         L.orc_hydrograph_volume.argtypes = [ctypes.c_double] * 6
         L.orc_tile_flags.argtypes = [ctypes.c_int] * 4 + [_c_double_p, _c_u8_p,
@@ -155,6 +158,14 @@ class OracleSim:
 
     def next_tau(self):
         return lib().orc_next_tau(self._h)
+
+    def cell_speeds(self):
+        out = np.empty((self.ny, self.nx))
+        lib().orc_cell_speeds(self._h, _dp(out))
+        return out
+
+    def tau_from_speed(self, smax):
+        return lib().orc_tau_from_speed(self._h, float(smax))
 
     def mass(self):
         return lib().orc_mass(self._h)

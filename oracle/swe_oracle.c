@@ -361,27 +361,37 @@ static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
  * only slow a particle down, never reverse it, so it sets no explicit limit;
  * counting it would let films just above eps (friction ~ H^(-4/3)) dictate
  * the time step. */
-static double cfl_tau(orc_sim* s)
+static double cell_speed(const orc_sim* s, long c)
 {
     const orc_params* p = &s->p;
-    double smax = 0.0;
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i) {
-            long c = P(s, i, j);
-            if (!s->wet[c]) continue;
-            double ux = s->Ux[c], uy = s->Uy[c];
-            double fx, fy;
-            soft_forces(s, c, s->Ux, s->Uy, &fx, &fy);
-            double us = fmax(fabs(ux), fabs(uy)) + sqrt(p->g * s->H[c]);
-            double upx = fabs(ux + sgn(fx) * sqrt(s->h * fabs(fx)));
-            double upy = fabs(uy + sgn(fy) * sqrt(s->h * fabs(fy)));
-            double sp = fmax(us, fmax(upx, upy));
-            if (sp > smax) smax = sp;
-        }
+    if (!s->wet[c]) return 0.0;
+    double ux = s->Ux[c], uy = s->Uy[c];
+    double fx, fy;
+    soft_forces(s, c, s->Ux, s->Uy, &fx, &fy);
+    double us = fmax(fabs(ux), fabs(uy)) + sqrt(p->g * s->H[c]);
+    double upx = fabs(ux + sgn(fx) * sqrt(s->h * fabs(fx)));
+    double upy = fabs(uy + sgn(fy) * sqrt(s->h * fabs(fy)));
+    return fmax(us, fmax(upx, upy));
+}
+
+static double tau_from_speed(const orc_sim* s, double smax)
+{
+    const orc_params* p = &s->p;
     double tau = p->tau_max > 0.0 ? p->tau_max : INFINITY;
     if (smax > 0.0) tau = fmin(tau, p->courant * s->h / smax);
     if (p->nu > 0.0) tau = fmin(tau, s->h * s->h / (4.0 * p->nu));
     return tau;
+}
+
+static double cfl_tau(orc_sim* s)
+{
+    double smax = 0.0;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            double sp = cell_speed(s, P(s, i, j));
+            if (sp > smax) smax = sp;
+        }
+    return tau_from_speed(s, smax);
 }
 
 /* ------------------------------------------------------------------ */
@@ -603,6 +613,20 @@ double orc_next_tau(orc_sim* s)
     if (!s) return NAN;
     prepare_layer(s);
     return cfl_tau(s);
+}
+
+int orc_cell_speeds(orc_sim* s, double* out)
+{
+    if (!s || !out) return ORC_EINVAL;
+    prepare_layer(s);
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) out[(long)j * s->nx + i] = cell_speed(s, P(s, i, j));
+    return 0;
+}
+
+double orc_tau_from_speed(const orc_sim* s, double smax)
+{
+    return s ? tau_from_speed(s, smax) : NAN;
 }
 
 static int step_with(orc_sim* s, double tau)

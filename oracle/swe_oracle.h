@@ -73,6 +73,10 @@ int    orc_run(orc_sim* s, long n);
 
 /* The CFL time step the next step would take (Sec. 2.3, stage I). */
 double orc_next_tau(orc_sim* s);
+/* CFL speed max(U_s, U_p) of every cell of the current layer (0 where dry),
+ * row-major nx*ny; and the time step that a maximum speed gives. */
+int    orc_cell_speeds(orc_sim* s, double* out);
+double orc_tau_from_speed(const orc_sim* s, double smax);
 
 double orc_mass(const orc_sim* s);      /* h^2 * sum H, compensated FP64 sum */
 double orc_time(const orc_sim* s);      /* simulated time */

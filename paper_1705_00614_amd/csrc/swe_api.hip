@@ -6,11 +6,13 @@
 // runs.  No arithmetic of the scheme runs on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,6 +48,7 @@ constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even)
 struct Launcher {
     int tx, ty, nt, precision, limiter;
     hipError_t (*step)(const void* args, int grid, hipStream_t st);
+    hipError_t (*step_tap)(const void* args, int grid, hipStream_t st);   // nested grids; may be null
     hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
@@ -53,10 +56,10 @@ struct Launcher {
     int (*occupancy)(int* blocks);
 };
 
-template <typename real, int TX, int TY, int NT, int LIM>
+template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
 hipError_t launch_step(const void* args, int grid, hipStream_t st) {
     const Args<real>& a = *static_cast<const Args<real>*>(args);
-    hipLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM>), dim3(grid), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM, TAP>), dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 template <typename real, int TX, int TY, int NT, int LIM>
@@ -85,26 +88,30 @@ hipError_t launch_prepare_finish(const void* args, hipStream_t st) {
 }
 template <typename real, int TX, int TY, int NT, int LIM>
 int occupancy(int* blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT, LIM>, NT, 0) ==
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT, LIM, false>, NT, 0) ==
                    hipSuccess ? 0 : -1;
 }
 
-#define LAUNCHER(real, TX, TY, NT, P, LIM)                                                       \
-    Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM>,                              \
+#define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, true>
+#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr
+#define LAUNCHER(real, TX, TY, NT, P, LIM, TAPS)                                                 \
+    Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, false>,                       \
+             TAPS(real, TX, TY, NT, LIM),                                                        \
              launch_batch_step<real, TX, TY, NT, LIM>, launch_batch_prepare_finish<real>,         \
              launch_prepare<real, TX, TY, NT>, launch_prepare_finish<real>,                      \
              occupancy<real, TX, TY, NT, LIM>}
-#define LAUNCHERS(real, TX, TY, NT, P) \
-    LAUNCHER(real, TX, TY, NT, P, 0), LAUNCHER(real, TX, TY, NT, P, 1), LAUNCHER(real, TX, TY, NT, P, 2)
+#define LAUNCHERS(real, TX, TY, NT, P, TAPS)                                       \
+    LAUNCHER(real, TX, TY, NT, P, 0, TAPS), LAUNCHER(real, TX, TY, NT, P, 1, TAPS), \
+        LAUNCHER(real, TX, TY, NT, P, 2, TAPS)
 
 // Tile shapes compiled in, each with the three limiters; the first shape of
-// each precision is its default.
+// each precision is its default and the one nested grids use.
 const Launcher kLaunchers[] = {
-    LAUNCHERS(float, 32, 32, 512, 32),
-    LAUNCHERS(float, 64, 16, 512, 32),
-    LAUNCHERS(float, 16, 16, 256, 32),
-    LAUNCHERS(double, 16, 16, 256, 64),
-    LAUNCHERS(double, 32, 16, 256, 64),
+    LAUNCHERS(float, 32, 32, 512, 32, TAP_STEP),
+    LAUNCHERS(float, 64, 16, 512, 32, NO_TAP_STEP),
+    LAUNCHERS(float, 16, 16, 256, 32, NO_TAP_STEP),
+    LAUNCHERS(double, 16, 16, 256, 64, TAP_STEP),
+    LAUNCHERS(double, 32, 16, 256, 64, NO_TAP_STEP),
 };
 
 const Launcher* find_launcher(int precision, int tx, int ty, int limiter) {
@@ -144,6 +151,10 @@ struct swe_s {
     hipGraphExec_t graph = nullptr;
     std::vector<unsigned char> args[2];   // kernel arguments per parity
     std::vector<uint8_t> solid;           // closed gates (host copy)
+    // member of a nest: the nest sets the time steps; flux taps
+    int hold = 0, ntap = 0;
+    const int* tap_rect = nullptr;
+    void* tap = nullptr;
 };
 
 namespace {
@@ -193,6 +204,15 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->nu_d = p.nu;
     a->nin_h2 = s->nin > 0 ? (double)s->nin * s->h * s->h : 0.0;
     a->q_base = p.q_base; a->q_peak = p.q_peak; a->t_peak = p.t_peak; a->sigma_t = p.sigma_t;
+    a->hold = s->hold;
+    a->ntap = s->ntap;
+    a->tap_rect = s->tap_rect;
+    a->tap = (real*)s->tap;
+}
+
+// Step kernel of a grid: the tapping variant for members of a nest.
+hipError_t launch_grid_step(swe_t* s, int par) {
+    return (s->ntap > 0 ? s->L->step_tap : s->L->step)(s->args[par].data(), s->grid, s->stream);
 }
 
 void build_args(swe_t* s) {
@@ -283,7 +303,7 @@ void free_all(swe_t* s) {
 int launch_steps(swe_t* s, long n) {
     for (long k = 0; k < n; ++k) {
         const int par = (int)(s->launched & 1);
-        HIPCHK(s->L->step(s->args[par].data(), s->grid, s->stream));
+        HIPCHK(launch_grid_step(s, par));
         s->launched++;
     }
     return 0;
@@ -294,7 +314,7 @@ int ensure_graph(swe_t* s) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < GRAPH_STEPS; ++k) {
-        hipError_t e = s->L->step(s->args[k & 1].data(), s->grid, s->stream);
+        hipError_t e = launch_grid_step(s, k & 1);
         if (e != hipSuccess) {
             hipStreamEndCapture(s->stream, &g);
             if (g) hipGraphDestroy(g);
@@ -325,13 +345,21 @@ int finish(swe_t* s) {
     return 0;
 }
 
+// Settings of a grid that is a member of a nest.
+struct GridExtra {
+    int hold, ntap;
+    const int* tap_rect;
+    void* tap;
+};
+
 }  // namespace
 
 extern "C" {
 
 const char* swe_last_error(void) { return g_err.c_str(); }
 
-swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p) {
+static swe_t* create_grid(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p,
+                          const GridExtra* ex) {
     g_err.clear();
     if (!p || !b) { set_err("swe_create: b and params are required"); return nullptr; }
     if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 31) - 1) {
@@ -371,6 +399,15 @@ swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
     s->precision = p->precision; s->rsize = p->precision == 32 ? 4 : 8;
     s->p.solid = nullptr; s->p.H0 = s->p.Qx0 = s->p.Qy0 = nullptr;
     s->nin = nin;
+    if (ex) {
+        s->hold = ex->hold;
+        s->ntap = ex->ntap;
+        s->tap_rect = ex->tap_rect;
+        s->tap = ex->tap;
+        if (s->ntap > 0 && !L->step_tap) {
+            set_err("nest: the tile shape has no tapping step kernel"); delete s; return nullptr;
+        }
+    }
     if (p->solid) s->solid.assign(p->solid, p->solid + (size_t)nx * ny);
     s->ntx = (nx + L->tx - 1) / L->tx;
     s->nty = (ny + L->ty - 1) / L->ty;
@@ -440,6 +477,10 @@ swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
 #undef CK
 }
 
+swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p) {
+    return create_grid(nx, ny, dx, b, n_M, p, nullptr);
+}
+
 void swe_destroy(swe_t* s) {
     if (!s) return;
     hipStreamSynchronize(s->stream);
@@ -487,7 +528,7 @@ int swe_run_timed(swe_t* s, long nsteps, double* kernel_ms) {
         for (long k = 0; k < m; ++k) {
             const int par = (int)(s->launched & 1);
             HIPCHK(hipEventRecord(ev[2 * k], s->stream));
-            HIPCHK(s->L->step(s->args[par].data(), s->grid, s->stream));
+            HIPCHK(launch_grid_step(s, par));
             HIPCHK(hipEventRecord(ev[2 * k + 1], s->stream));
             s->launched++;
         }
@@ -1031,3 +1072,506 @@ __global__ void swe::k_sum_tiles(const double* part, int n, double* out) {
     }
     if (t == 0) *out = buf[0];
 }
+
+// ====================================================================== nested grids
+
+#include "swe_nest.hpp"
+
+namespace {
+
+constexpr int NEST_GRAPH_STEPS = 8;   // coarse steps per captured graph (even)
+
+}  // namespace
+
+struct swe_nest_s {
+    int r = 1, np = 0, feedback = 1, precision = 32, rsize = 4;
+    swe_t* c = nullptr;
+    std::vector<swe_t*> p;
+    std::vector<swe_patch> box;      // host copy of the layout (pointers not kept)
+    hipStream_t stream = nullptr;
+    void* tap = nullptr;             // device taps: coarse boxes, then patches
+    int ntap = 0;
+    int* ints = nullptr;             // device ints: rects, ring CSR, forced tiles, regions
+    void* desc = nullptr;            // device NestPatch<real>[np]
+    double* ring_ledger = nullptr;
+    double* part = nullptr;          // volume partials
+    int npart = 0, chunk = 0;
+    double* scalar = nullptr;
+    int nforce = 0, nregion = 0, nregion_cells = 0, nring = 0;
+    const int* force_tiles = nullptr;
+    const int* region = nullptr;
+    long long launched = 0;          // coarse steps launched
+    hipGraphExec_t graph = nullptr;
+    std::vector<unsigned char> nargs;   // NestArgs<real>
+};
+
+namespace {
+
+void free_nest(swe_nest_t* n) {
+    if (n->graph) hipGraphExecDestroy(n->graph);
+    for (swe_t* q : n->p) if (q) swe_destroy(q);
+    if (n->c) swe_destroy(n->c);
+    void* ptrs[] = {n->tap, n->ints, n->desc, n->ring_ledger, n->part, n->scalar};
+    for (void* q : ptrs) if (q) hipFree(q);
+}
+
+template <typename real>
+void fill_nest_args(swe_nest_t* n, int nframe, int ncov, int nring, const int* ring_cell, const int* ring_off,
+                    const int* ring_face) {
+    n->nargs.assign(sizeof(swe::NestArgs<real>), 0);
+    swe::NestArgs<real>* a = (swe::NestArgs<real>*)n->nargs.data();
+    a->P = (const swe::NestPatch<real>*)n->desc;
+    a->np = n->np; a->r = n->r; a->nx = n->c->nx; a->ny = n->c->ny;
+    a->nframe = nframe; a->ncov = ncov; a->nring = nring;
+    for (int k = 0; k < 2; ++k) {
+        a->Hc[k] = (real*)n->c->Hb[k]; a->Qxc[k] = (real*)n->c->Qxb[k]; a->Qyc[k] = (real*)n->c->Qyb[k];
+    }
+    a->bc = (const real*)n->c->bed;
+    a->tap = (real*)n->tap;
+    a->ring_cell = ring_cell; a->ring_off = ring_off; a->ring_face = ring_face;
+    a->ring_ledger = n->ring_ledger;
+    a->eps = (real)n->c->p.eps;
+    a->ih = (real)(1.0 / n->c->h);
+    a->h2 = n->c->h * n->c->h;
+}
+
+template <typename real>
+int upload_desc(swe_nest_t* n, const std::vector<int>& frame_base, const std::vector<int>& cov_base,
+                const std::vector<int>& ftap, const std::vector<int>& ctap) {
+    std::vector<swe::NestPatch<real>> d(n->np);
+    for (int k = 0; k < n->np; ++k) {
+        const swe_patch& b = n->box[k];
+        swe::NestPatch<real>& e = d[k];
+        e.ci0 = b.ci0; e.cj0 = b.cj0; e.cw = b.cw; e.ch = b.ch;
+        e.nxe = n->p[k]->nx; e.nye = n->p[k]->ny;
+        e.frame_base = frame_base[k]; e.cov_base = cov_base[k];
+        e.ftap = ftap[k]; e.ctap = ctap[k];
+        for (int q = 0; q < 2; ++q) {
+            e.Hf[q] = (real*)n->p[k]->Hb[q]; e.Qxf[q] = (real*)n->p[k]->Qxb[q]; e.Qyf[q] = (real*)n->p[k]->Qyb[q];
+        }
+        e.bf = (const real*)n->p[k]->bed;
+        e.ctrl = n->p[k]->ctrl;
+    }
+    HIPCHK(hipMemcpyAsync(n->desc, d.data(), sizeof(swe::NestPatch<real>) * n->np, hipMemcpyHostToDevice,
+                          n->stream));
+    HIPCHK(hipStreamSynchronize(n->stream));
+    return 0;
+}
+
+int blocks_for(long long work, int bs) { return (int)((work + bs - 1) / bs); }
+
+// One coarse step with its substeps and the feedback, all launches on the
+// nest's stream.
+template <typename real>
+hipError_t nest_step_t(swe_nest_t* n) {
+    const swe::NestArgs<real>& na = *(const swe::NestArgs<real>*)n->nargs.data();
+    swe_t* c = n->c;
+    const int pc = (int)(c->launched & 1);
+    hipError_t e;
+    hipLaunchKernelGGL(swe::k_nest_zero<real>, dim3(blocks_for(n->ntap, 256) < 1024 ? blocks_for(n->ntap, 256) : 1024),
+                       dim3(256), 0, n->stream, (real*)n->tap, n->ntap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_grid_step(c, pc)) != hipSuccess) return e;
+    c->launched++;
+    for (int s = 0; s < n->r; ++s) {
+        const int pf = (int)(n->p[0]->launched & 1);
+        hipLaunchKernelGGL(swe::k_frame<real>, dim3(blocks_for(na.nframe, 256)), dim3(256), 0, n->stream, na, pf, pc,
+                           (real)((double)s / (double)n->r));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (swe_t* q : n->p) {
+            if ((e = launch_grid_step(q, pf)) != hipSuccess) return e;
+            q->launched++;
+        }
+    }
+    const Args<real>& an = *(const Args<real>*)c->args[pc ^ 1].data();
+    if (n->feedback) {
+        const int pf = (int)(n->p[0]->launched & 1);
+        hipLaunchKernelGGL(swe::k_feedback<real>, dim3(blocks_for(na.ncov + na.nring, 256)), dim3(256), 0,
+                           n->stream, na, pf, pc ^ 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (c->p.skip_dry && n->nforce > 0) {
+            hipLaunchKernelGGL(swe::k_nest_force<real>, dim3(blocks_for(n->nforce, 64)), dim3(64), 0, n->stream,
+                               an, n->force_tiles, n->nforce, pc ^ 1);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(swe::k_region_speed<real>, dim3(blocks_for(n->nregion_cells, 256)), dim3(256), 0,
+                           n->stream, an, n->region, n->nregion, n->nregion_cells);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, an, na, pc ^ 1);
+    return hipGetLastError();
+}
+
+hipError_t nest_step(swe_nest_t* n) {
+    return n->precision == 32 ? nest_step_t<float>(n) : nest_step_t<double>(n);
+}
+
+// Time steps of the first coarse step: frames from the initial coarse layer,
+// CFL steps of every grid, then the nest's rule.
+template <typename real>
+int nest_init_tau(swe_nest_t* n) {
+    const swe::NestArgs<real>& na = *(const swe::NestArgs<real>*)n->nargs.data();
+    const int pc = (int)(n->c->launched & 1), pf = (int)(n->p[0]->launched & 1);
+    hipLaunchKernelGGL(swe::k_frame<real>, dim3(blocks_for(na.nframe, 256)), dim3(256), 0, n->stream, na, pf, pc,
+                       (real)0);
+    HIPCHK(hipGetLastError());
+    for (swe_t* q : n->p) {
+        int rc = prepare(q);
+        if (rc) return rc;
+    }
+    const Args<real>& a = *(const Args<real>*)n->c->args[pc].data();
+    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, a, na, pc);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(n->stream));
+    return 0;
+}
+
+int nest_finish(swe_nest_t* n) {
+    HIPCHK(hipStreamSynchronize(n->stream));
+    return finish(n->c);
+}
+
+int nest_launch(swe_nest_t* n, long k) {
+    for (long i = 0; i < k; ++i) {
+        hipError_t e = nest_step(n);
+        if (e != hipSuccess) { set_hip_err("nest step", e); return SWE_EHIP; }
+        n->launched++;
+    }
+    return 0;
+}
+
+int nest_graph(swe_nest_t* n) {
+    if (n->graph) return 0;
+    // capture starts and ends on even parities of every grid
+    const long long c0 = n->c->launched;
+    std::vector<long long> p0;
+    for (swe_t* q : n->p) p0.push_back(q->launched);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < NEST_GRAPH_STEPS && e == hipSuccess; ++k) e = nest_step(n);
+    hipError_t e2 = hipStreamEndCapture(n->stream, &g);
+    // capture launched nothing: restore the host counters
+    n->c->launched = c0;
+    for (int k = 0; k < n->np; ++k) n->p[k]->launched = p0[k];
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        set_hip_err("nest graph capture", e != hipSuccess ? e : e2);
+        return SWE_EHIP;
+    }
+    e = hipGraphInstantiate(&n->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { n->graph = nullptr; set_hip_err("nest graph instantiation", e); return SWE_EHIP; }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p,
+                            int r, int feedback, int npatch, const swe_patch* patches) {
+    g_err.clear();
+    if (!p || !b || !patches || npatch < 1 || r < 1 || r > 16) {
+        set_err("swe_nest_create: need params, bed, 1 <= r <= 16 and at least one patch"); return nullptr;
+    }
+    if (p->tile_x != 0 || p->tile_y != 0) { set_err("swe_nest_create: nests use the default tile shape"); return nullptr; }
+    const int G = swe::NEST_FRAME, m = (G + r - 1) / r;
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        if (!q.b || q.cw < 1 || q.ch < 1 || q.ci0 < m || q.cj0 < m || q.ci0 + q.cw + m > nx ||
+            q.cj0 + q.ch + m > ny) {
+            set_err("swe_nest_create: a patch box or its frame leaves the coarse grid"); return nullptr;
+        }
+        if ((long long)(r * q.cw + 2 * G) * (r * q.ch + 2 * G) > (1LL << 30)) {
+            set_err("swe_nest_create: patch too large"); return nullptr;
+        }
+        if (p->inlet_ni > 0 && p->inlet_nj > 0 &&
+            !(p->inlet_i0 + p->inlet_ni <= q.ci0 - 1 || p->inlet_i0 >= q.ci0 + q.cw + 1 ||
+              p->inlet_j0 + p->inlet_nj <= q.cj0 - 1 || p->inlet_j0 >= q.cj0 + q.ch + 1)) {
+            set_err("swe_nest_create: a patch covers or touches the inlet"); return nullptr;
+        }
+        if (p->solid)
+            for (int j = q.cj0 - m; j < q.cj0 + q.ch + m; ++j)
+                for (int i = q.ci0 - m; i < q.ci0 + q.cw + m; ++i)
+                    if (p->solid[(size_t)j * nx + i]) {
+                        set_err("swe_nest_create: a closed gate lies under a patch or its frame"); return nullptr;
+                    }
+        for (int l = k + 1; l < npatch; ++l) {
+            const swe_patch& o = patches[l];
+            if (!(q.ci0 + q.cw + 1 <= o.ci0 || o.ci0 + o.cw + 1 <= q.ci0 || q.cj0 + q.ch + 1 <= o.cj0 ||
+                  o.cj0 + o.ch + 1 <= q.cj0)) {
+                set_err("swe_nest_create: patches must keep one uncovered cell between them"); return nullptr;
+            }
+        }
+    }
+    swe_nest_t* n = new (std::nothrow) swe_nest_s();
+    if (!n) { set_err("swe_nest_create: out of host memory"); return nullptr; }
+    n->r = r; n->np = npatch; n->feedback = feedback ? 1 : 0;
+    n->precision = p->precision; n->rsize = p->precision == 32 ? 4 : 8;
+    n->box.assign(patches, patches + npatch);
+
+#define NK(expr)                                                         \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) {                                          \
+            set_hip_err("swe_nest_create", e_);                          \
+            free_nest(n); delete n; return nullptr;                      \
+        }                                                                \
+    } while (0)
+
+    // ---- host layout: taps, rects, ring CSR, forced tiles, speed regions
+    std::vector<int> ctap(npatch), ftap(npatch), frame_base(npatch), cov_base(npatch);
+    int ntap = 0, nframe = 0, ncov = 0;
+    for (int k = 0; k < npatch; ++k) { ctap[k] = ntap; ntap += 3 * 2 * (patches[k].cw + patches[k].ch); }
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        ftap[k] = ntap; ntap += 3 * 2 * r * (q.cw + q.ch);
+        frame_base[k] = nframe;
+        nframe += (r * q.cw + 2 * G) * (r * q.ch + 2 * G) - r * q.cw * r * q.ch;
+        cov_base[k] = ncov; ncov += q.cw * q.ch;
+    }
+    n->ntap = ntap;
+    std::vector<int> ints;
+    const size_t o_crect = ints.size();
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        int v[5] = {q.ci0, q.cj0, q.ci0 + q.cw, q.cj0 + q.ch, ctap[k]};
+        ints.insert(ints.end(), v, v + 5);
+    }
+    const size_t o_frect = ints.size();
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        int v[5] = {G, G, G + r * q.cw, G + r * q.ch, ftap[k]};
+        ints.insert(ints.end(), v, v + 5);
+    }
+    // ring cells: uncovered cells sharing a face with a box, with the faces
+    std::map<int, std::vector<int>> faces_of;
+    std::vector<int> ring_order;
+    auto add_face = [&](int i, int j, int k, int side, int idx) {
+        const int c = j * nx + i;
+        std::vector<int>& f = faces_of[c];
+        if (f.empty()) ring_order.push_back(c);
+        f.push_back(k); f.push_back(side); f.push_back(idx);
+    };
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        for (int j = 0; j < q.ch; ++j) add_face(q.ci0 - 1, q.cj0 + j, k, 0, j);
+        for (int j = 0; j < q.ch; ++j) add_face(q.ci0 + q.cw, q.cj0 + j, k, 1, j);
+        for (int i = 0; i < q.cw; ++i) add_face(q.ci0 + i, q.cj0 - 1, k, 2, i);
+        for (int i = 0; i < q.cw; ++i) add_face(q.ci0 + i, q.cj0 + q.ch, k, 3, i);
+    }
+    const int nring = (int)ring_order.size();
+    n->nring = nring;
+    const size_t o_rcell = ints.size();
+    ints.insert(ints.end(), ring_order.begin(), ring_order.end());
+    const size_t o_roff = ints.size();
+    {
+        int off = 0;
+        ints.push_back(0);
+        for (int c : ring_order) { off += (int)faces_of[c].size() / 3; ints.push_back(off); }
+    }
+    const size_t o_rface = ints.size();
+    for (int c : ring_order) ints.insert(ints.end(), faces_of[c].begin(), faces_of[c].end());
+    faces_of.clear();
+
+    const Launcher* L = find_launcher(p->precision, 0, 0, p->limiter);
+    if (!L) { set_err("swe_nest_create: no kernel for this precision and limiter"); delete n; return nullptr; }
+    const int ntx = (nx + L->tx - 1) / L->tx, nty = (ny + L->ty - 1) / L->ty;
+    std::vector<char> forced((size_t)ntx * nty, 0);
+    const size_t o_region = ints.size();
+    int ncells = 0;
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        const int x0 = std::max(q.ci0 - 2, 0), y0 = std::max(q.cj0 - 2, 0);
+        const int x1 = std::min(q.ci0 + q.cw + 2, nx), y1 = std::min(q.cj0 + q.ch + 2, ny);
+        int v[5] = {x0, y0, x1, y1, ncells};
+        ints.insert(ints.end(), v, v + 5);
+        ncells += (x1 - x0) * (y1 - y0);
+        for (int tj = y0 / L->ty; tj <= (y1 - 1) / L->ty; ++tj)
+            for (int ti = x0 / L->tx; ti <= (x1 - 1) / L->tx; ++ti) forced[(size_t)tj * ntx + ti] = 1;
+    }
+    n->nregion = npatch;
+    n->nregion_cells = ncells;
+    const size_t o_force = ints.size();
+    for (size_t t = 0; t < forced.size(); ++t)
+        if (forced[t]) ints.push_back((int)t);
+    n->nforce = (int)(ints.size() - o_force);
+
+    // ---- device buffers
+    hipStream_t st = (hipStream_t)p->stream;
+    NK(hipMalloc(&n->tap, (size_t)ntap * n->rsize));
+    NK(hipMalloc((void**)&n->ints, sizeof(int) * ints.size()));
+    NK(hipMalloc(&n->ring_ledger, sizeof(double) * std::max(nring, 1)));
+    NK(hipMalloc(&n->desc, (n->precision == 32 ? sizeof(swe::NestPatch<float>) : sizeof(swe::NestPatch<double>)) *
+                               npatch));
+    n->chunk = 1 << 16;
+    n->npart = (int)(((long long)nx * ny + n->chunk - 1) / n->chunk);
+    NK(hipMalloc((void**)&n->part, sizeof(double) * n->npart));
+    NK(hipMalloc((void**)&n->scalar, sizeof(double)));
+    NK(hipMemcpy(n->ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice));
+    NK(hipMemset(n->ring_ledger, 0, sizeof(double) * std::max(nring, 1)));
+    n->force_tiles = n->ints + o_force;
+    n->region = n->ints + o_region;
+
+    // ---- grids: the coarse grid, then the patches on its stream
+    GridExtra cx{1, npatch, n->ints + o_crect, n->tap};
+    n->c = create_grid(nx, ny, dx, b, n_M, p, &cx);
+    if (!n->c) { std::string m_ = g_err; free_nest(n); delete n; g_err = m_; return nullptr; }
+    n->stream = n->c->stream;
+    swe_params pp = *p;
+    pp.inlet_i0 = pp.inlet_j0 = pp.inlet_ni = pp.inlet_nj = 0;
+    pp.q_base = pp.q_peak = 0.0;
+    pp.solid = nullptr;
+    pp.skip_dry = 0;
+    pp.stream = (void*)n->stream;
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        const int nxe = r * q.cw + 2 * G, nye = r * q.ch + 2 * G, nxf = r * q.cw;
+        std::vector<double> H((size_t)nxe * nye, 0.0), Qx(H.size(), 0.0), Qy(H.size(), 0.0);
+        for (int j = 0; j < r * q.ch; ++j)
+            for (int i = 0; i < nxf; ++i) {
+                const size_t src = (size_t)j * nxf + i, dst = (size_t)(j + G) * nxe + i + G;
+                if (q.H0) H[dst] = q.H0[src];
+                if (q.Qx0) Qx[dst] = q.Qx0[src];
+                if (q.Qy0) Qy[dst] = q.Qy0[src];
+            }
+        pp.H0 = H.data(); pp.Qx0 = Qx.data(); pp.Qy0 = Qy.data();
+        GridExtra fx{1, 1, n->ints + o_frect + 5 * k, n->tap};
+        swe_t* g = create_grid(nxe, nye, dx / r, q.b, q.n_M, &pp, &fx);
+        if (!g) { std::string m_ = g_err; free_nest(n); delete n; g_err = m_; return nullptr; }
+        n->p.push_back(g);
+    }
+    int rc = 0;
+    if (n->precision == 32) {
+        fill_nest_args<float>(n, nframe, ncov, nring, n->ints + o_rcell, n->ints + o_roff, n->ints + o_rface);
+        rc = upload_desc<float>(n, frame_base, cov_base, ftap, ctap);
+        if (!rc) rc = nest_init_tau<float>(n);
+    } else {
+        fill_nest_args<double>(n, nframe, ncov, nring, n->ints + o_rcell, n->ints + o_roff, n->ints + o_rface);
+        rc = upload_desc<double>(n, frame_base, cov_base, ftap, ctap);
+        if (!rc) rc = nest_init_tau<double>(n);
+    }
+    if (!rc) rc = nest_finish(n);
+    if (rc) { std::string m_ = g_err; free_nest(n); delete n; g_err = m_; return nullptr; }
+    (void)st;
+    return n;
+#undef NK
+}
+
+void swe_nest_destroy(swe_nest_t* n) {
+    if (!n) return;
+    if (n->stream) hipStreamSynchronize(n->stream);
+    free_nest(n);
+    delete n;
+}
+
+int swe_nest_run(swe_nest_t* n, long steps) {
+    if (!n || steps < 0) { set_err("swe_nest_run: invalid arguments"); return SWE_EINVAL; }
+    long left = steps;
+    int rc;
+    if (left > 0 && (n->c->launched & 1)) {
+        if ((rc = nest_launch(n, 1))) return rc;
+        --left;
+    }
+    if (left >= NEST_GRAPH_STEPS) {
+        if ((rc = nest_graph(n))) return rc;
+        while (left >= NEST_GRAPH_STEPS) {
+            HIPCHK(hipGraphLaunch(n->graph, n->stream));
+            n->launched += NEST_GRAPH_STEPS;
+            n->c->launched += NEST_GRAPH_STEPS;
+            for (swe_t* q : n->p) q->launched += (long long)NEST_GRAPH_STEPS * n->r;
+            left -= NEST_GRAPH_STEPS;
+        }
+    }
+    if ((rc = nest_launch(n, left))) return rc;
+    return nest_finish(n);
+}
+
+int swe_nest_run_timed(swe_nest_t* n, long steps, double* kernel_ms) {
+    if (!n || steps < 0 || !kernel_ms) { set_err("swe_nest_run_timed: invalid arguments"); return SWE_EINVAL; }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double total = 0.0;
+    int rc = 0;
+    for (long k = 0; k < steps && rc == 0; ++k) {
+        HIPCHK(hipEventRecord(e0, n->stream));
+        rc = nest_launch(n, 1);
+        HIPCHK(hipEventRecord(e1, n->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *kernel_ms = total;
+    if (rc) return rc;
+    return nest_finish(n);
+}
+
+int swe_nest_query(swe_nest_t* n, double* t, double* volume, double* inflow, double* ledger, long* steps,
+                   double* dt_coarse, double* dt_fine) {
+    if (!n) { set_err("swe_nest_query: NULL handle"); return SWE_EINVAL; }
+    Ctrl c, f;
+    int rc = sync_ctrl(n->c, &c);
+    if (rc) return rc;
+    if ((rc = sync_ctrl(n->p[0], &f))) return rc;
+    if (t) *t = c.t;
+    if (inflow) *inflow = c.inflow;
+    if (steps) *steps = (long)c.step;
+    if (dt_coarse) *dt_coarse = c.tau;
+    if (dt_fine) *dt_fine = f.tau;
+    const int par = (int)(c.step & 1);
+    if (volume) {
+        const int cells = n->c->nx * n->c->ny;
+        if (n->precision == 32)
+            hipLaunchKernelGGL(swe::k_field_partials<float>, dim3(n->npart), dim3(256), 0, n->stream,
+                               (const float*)n->c->Hb[par], cells, n->chunk, n->part);
+        else
+            hipLaunchKernelGGL(swe::k_field_partials<double>, dim3(n->npart), dim3(256), 0, n->stream,
+                               (const double*)n->c->Hb[par], cells, n->chunk, n->part);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(swe::k_sum_tiles, dim3(1), dim3(1024), 0, n->stream, n->part, n->npart, n->scalar);
+        HIPCHK(hipGetLastError());
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, n->scalar, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        HIPCHK(hipStreamSynchronize(n->stream));
+        *volume = v * n->c->h * n->c->h;
+    }
+    if (ledger) {
+        hipLaunchKernelGGL(swe::k_sum_tiles, dim3(1), dim3(1024), 0, n->stream, n->ring_ledger, n->nring,
+                           n->scalar);
+        HIPCHK(hipGetLastError());
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, n->scalar, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        HIPCHK(hipStreamSynchronize(n->stream));
+        *ledger = v + swe_ledger(n->c);
+    }
+    return 0;
+}
+
+int swe_nest_get_coarse(swe_nest_t* n, double* H, double* Qx, double* Qy) {
+    if (!n) { set_err("swe_nest_get_coarse: NULL handle"); return SWE_EINVAL; }
+    return swe_get_state(n->c, H, Qx, Qy);
+}
+
+int swe_nest_get_patch(swe_nest_t* n, int k, double* H, double* Qx, double* Qy) {
+    if (!n || k < 0 || k >= n->np) { set_err("swe_nest_get_patch: invalid arguments"); return SWE_EINVAL; }
+    swe_t* g = n->p[k];
+    const int G = swe::NEST_FRAME, nxe = g->nx, nxf = nxe - 2 * G, nyf = g->ny - 2 * G;
+    std::vector<double> a((size_t)nxe * g->ny), b(a.size()), c(a.size());
+    int rc = swe_get_state(g, a.data(), b.data(), c.data());
+    if (rc) return rc;
+    double* outs[3] = {H, Qx, Qy};
+    const std::vector<double>* srcs[3] = {&a, &b, &c};
+    for (int q = 0; q < 3; ++q) {
+        if (!outs[q]) continue;
+        for (int j = 0; j < nyf; ++j)
+            std::memcpy(outs[q] + (size_t)j * nxf, srcs[q]->data() + (size_t)(j + G) * nxe + G, sizeof(double) * nxf);
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+// swe_nest.hpp -- gfx950 kernels of hierarchical (nested) grids.
+//
+// Method: arXiv 1705.00614, Sec. 2.2 (a hierarchy of grids in which the
+// small-scale flow of a zoomed-in area feeds back into the large-scale grid)
+// and Sec. 5 (a 50 m global grid with a 12.5 m local grid).  The paper does
+// not spell out the coupling; the one implemented here is coarse-first
+// subcycling with conservative flux matching.  Per coarse step:
+//
+//   coarse   one ordinary step of the coarse grid with time step tau_c; the
+//            step adds tau_c * flux of the faces bounding every covered box
+//            into its taps
+//   r times  k_frame fills the frame of every patch (the FRAME cells round
+//            its interior, one more than the reach of one step) from the
+//            covering coarse cell, linear in time between the coarse layers
+//            n and n+1 (depth and discharge interpolated; fine depth
+//            max(0, H_c + b_c - b_fine) where the coarse cell is wet, else
+//            dry); then one ordinary step of every patch with tau_c / r,
+//            adding tau_f * flux of its interior boundary faces into its taps
+//   feedback k_feedback: each covered coarse cell takes the mean of its
+//            r x r fine cells; each uncovered cell next to a covered box
+//            takes (coarse tap - mean of the r fine taps of the same coarse
+//            face) / h_c through that face, with the final update's clamp,
+//            ledger and dry rule; k_nest_force puts the tiles round the
+//            covered boxes on the coarse tile list; k_region_speed gathers
+//            the CFL speed of the changed cells
+//   tau      k_nest_tau: tau_c = min(CFL step of the coarse speeds,
+//            r * CFL step of every patch after its last substep), tau_f =
+//            tau_c / r, and the coarse hydrograph volume of the next step.
+//
+// All of it is device work on one stream (capturable in a graph); the host
+// only launches.
+#pragma once
+
+#include "swe_step.hpp"
+
+namespace swe {
+
+constexpr int NEST_FRAME = 5;   // frame width in fine cells
+
+template <typename real>
+struct NestPatch {
+    int ci0, cj0, cw, ch;          // covered coarse box
+    int nxe, nye;                  // extended fine grid (interior + frame)
+    int frame_base, cov_base;      // prefix sums over the patches: frame cells, covered cells
+    int ftap, ctap;                // offsets of the patch's and the coarse box's taps
+    real* Hf[2]; real* Qxf[2]; real* Qyf[2];
+    const real* bf;
+    Ctrl* ctrl;
+};
+
+template <typename real>
+struct NestArgs {
+    const NestPatch<real>* P;
+    int np, r, nx, ny;             // patches, refinement, coarse grid
+    int nframe, ncov, nring;       // frame cells, covered cells, ring cells (all patches)
+    real* Hc[2]; real* Qxc[2]; real* Qyc[2];
+    const real* bc;
+    real* tap;
+    const int* ring_cell;          // coarse cell of each ring cell
+    const int* ring_off;           // CSR offsets into ring_face (nring + 1)
+    const int* ring_face;          // per face: patch, side (0 W, 1 E, 2 S, 3 N), index along the side
+    double* ring_ledger;           // clamp volume per ring cell (accumulated)
+    real eps, ih;                  // dry threshold, 1 / h_c
+    double h2;                     // h_c^2
+};
+
+__device__ __forceinline__ int floor_div(int a, int r) { return a >= 0 ? a / r : -((-a + r - 1) / r); }
+
+template <typename real>
+__device__ __forceinline__ int find_patch(const NestPatch<real>* P, int np, int t, bool frame) {
+    int k = 0;
+    for (int q = 1; q < np; ++q) k += t >= (frame ? P[q].frame_base : P[q].cov_base);
+    return k;
+}
+
+// Zero the taps at the start of a coarse step.
+template <typename real>
+__global__ void k_nest_zero(real* tap, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tap[i] = real(0);
+}
+
+// Frame of every patch at time theta in [0, 1) of the coarse step, written to
+// the patch buffers pf; the coarse layers n and n+1 are in buffers pc, pc^1.
+template <typename real>
+__global__ void k_frame(NestArgs<real> n, int pf, int pc, real theta) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n.nframe) return;
+    const int k = find_patch(n.P, n.np, t, true);
+    const NestPatch<real>& d = n.P[k];
+    constexpr int G = NEST_FRAME;
+    const int nxe = d.nxe, nye = d.nye;
+    int m = t - d.frame_base, fi, fj;
+    if (m < G * nxe) {
+        fj = m / nxe; fi = m % nxe;
+    } else if (m < 2 * G * nxe) {
+        m -= G * nxe; fj = nye - G + m / nxe; fi = m % nxe;
+    } else {
+        m -= 2 * G * nxe;
+        fj = G + m / (2 * G);
+        const int c = m % (2 * G);
+        fi = c < G ? c : nxe - 2 * G + c;
+    }
+    const int ci = d.ci0 + floor_div(fi - G, n.r), cj = d.cj0 + floor_div(fj - G, n.r);
+    const int gc = cj * n.nx + ci, gf = fj * nxe + fi;
+    const real u = real(1) - theta;
+    const real Hm = u * n.Hc[pc][gc] + theta * n.Hc[pc ^ 1][gc];
+    const bool w = Hm > n.eps;
+    const real eta = Hm + n.bc[gc];
+    d.Hf[pf][gf] = w ? rmax(real(0), eta - d.bf[gf]) : real(0);
+    d.Qxf[pf][gf] = w ? u * n.Qxc[pc][gc] + theta * n.Qxc[pc ^ 1][gc] : real(0);
+    d.Qyf[pf][gf] = w ? u * n.Qyc[pc][gc] + theta * n.Qyc[pc ^ 1][gc] : real(0);
+}
+
+// Restriction of the fine layer (patch buffers pf) into the covered coarse
+// cells and the flux correction of the ring cells, both in coarse buffer po.
+template <typename real>
+__global__ void k_feedback(NestArgs<real> n, int pf, int po) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = n.r;
+    if (t < n.ncov) {
+        const int k = find_patch(n.P, n.np, t, false);
+        const NestPatch<real>& d = n.P[k];
+        const int m = t - d.cov_base, cy = m / d.cw, cx = m % d.cw;
+        const int gc = (d.cj0 + cy) * n.nx + d.ci0 + cx;
+        double sH = 0.0, sX = 0.0, sY = 0.0;
+        for (int jj = 0; jj < r; ++jj)
+            for (int ii = 0; ii < r; ++ii) {
+                const int gf = (NEST_FRAME + cy * r + jj) * d.nxe + NEST_FRAME + cx * r + ii;
+                sH += (double)d.Hf[pf][gf];
+                sX += (double)d.Qxf[pf][gf];
+                sY += (double)d.Qyf[pf][gf];
+            }
+        const double inv = 1.0 / (double)(r * r);
+        n.Hc[po][gc] = (real)(sH * inv);
+        n.Qxc[po][gc] = (real)(sX * inv);
+        n.Qyc[po][gc] = (real)(sY * inv);
+        return;
+    }
+    const int q = t - n.ncov;
+    if (q >= n.nring) return;
+    const int gc = n.ring_cell[q];
+    real dH = real(0), dQx = real(0), dQy = real(0);
+    for (int e = n.ring_off[q]; e < n.ring_off[q + 1]; ++e) {
+        const int k = n.ring_face[3 * e], side = n.ring_face[3 * e + 1], idx = n.ring_face[3 * e + 2];
+        const NestPatch<real>& d = n.P[k];
+        const int nxf = r * d.cw, nyf = r * d.ch;
+        const int pc_ = 2 * (d.cw + d.ch), pf_ = 2 * (nxf + nyf);
+        const int oc = side == 0 ? idx : side == 1 ? d.ch + idx : side == 2 ? 2 * d.ch + idx : 2 * d.ch + d.cw + idx;
+        const int of = side == 0 ? r * idx : side == 1 ? nyf + r * idx
+                     : side == 2 ? 2 * nyf + r * idx : 2 * nyf + nxf + r * idx;
+        real corr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            real fs = real(0);
+            for (int j = 0; j < r; ++j) fs += n.tap[d.ftap + c * pf_ + of + j];
+            corr[c] = (n.tap[d.ctap + c * pc_ + oc] - fs / (real)r) * n.ih;
+        }
+        // the covered box lies east of a W ring cell (its outflow face) and
+        // north of an S ring cell
+        const real sg = (side == 0 || side == 2) ? real(1) : real(-1);
+        dH += sg * corr[0];
+        if (side < 2) { dQx += sg * corr[1]; dQy += sg * corr[2]; }
+        else { dQy += sg * corr[1]; dQx += sg * corr[2]; }
+    }
+    const real Hn = n.Hc[po][gc] + dH;
+    const real Hcl = rmax(Hn, real(0));
+    n.ring_ledger[q] += (double)(Hcl - Hn) * n.h2;
+    const bool w = Hcl > n.eps;
+    n.Hc[po][gc] = Hcl;
+    n.Qxc[po][gc] = w ? n.Qxc[po][gc] + dQx : real(0);
+    n.Qyc[po][gc] = w ? n.Qyc[po][gc] + dQy : real(0);
+}
+
+// Put the tiles round the covered boxes on the coarse tile list of the next
+// step (list slot `slot`, generation of that list), so that the cells the
+// feedback changed are stepped and both buffers of the pair stay consistent.
+template <typename real>
+__global__ void k_nest_force(Args<real> a, const int* tiles, int ntiles_forced, int slot) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gen = (int)a.ctrl->step + 1;
+    append_tiles(t < ntiles_forced ? tiles[t] : -1, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, slot,
+                 blockIdx.x % NSEG);
+}
+
+// CFL speed of the new coarse layer (buffers of a's input) on the cells the
+// feedback can change: each covered box widened by 2 cells (rects: x0, y0,
+// x1, y1, cell prefix), gathered into the coarse control block.
+template <typename real>
+__global__ void k_region_speed(Args<real> a, const int* rects, int nrect, int ncells) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    real vmax = real(0);
+    if (t < ncells) {
+        int k = 0;
+        for (int q = 1; q < nrect; ++q) k += t >= rects[5 * q + 4];
+        const int* R = rects + 5 * k;
+        const int m = t - R[4], w = R[2] - R[0];
+        const int gx = R[0] + m % w, gy = R[1] + m / w;
+        const real eps = a.eps;
+        real Hs[5], ux[5], uy[5];
+        const int ox[5] = {0, -1, 1, 0, 0}, oy[5] = {0, 0, 0, -1, 1};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            int fx = 0, fy = 0;
+            const int x = mirror(gx + ox[q], a.nx, fx), y = mirror(gy + oy[q], a.ny, fy);
+            const int gi = y * a.nx + x;
+            const real H = a.Hi[gi];
+            real qx = a.Qxi[gi], qy = a.Qyi[gi];
+            if (fx & 1) qx = -qx;
+            if (fy & 1) qy = -qy;
+            const bool wq = H > eps;
+            Hs[q] = H;
+            ux[q] = wq ? Mth<real>::div(qx, H) : real(0);
+            uy[q] = wq ? Mth<real>::div(qy, H) : real(0);
+        }
+        if (Hs[0] > eps) {
+            Nb4<real> nb;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { nb.ux[q] = ux[q + 1]; nb.uy[q] = uy[q + 1]; nb.w[q] = Hs[q + 1] > eps; }
+            real fx, fy;
+            soft_forces(a, Hs[0], ux[0], uy[0], nb, fx, fy);
+            vmax = cfl_speed(a, Hs[0], ux[0], uy[0], fx, fy);
+        }
+    }
+    vmax = wave_max(vmax);
+    if ((threadIdx.x & 63) == 0 && vmax > real(0)) atomic_max_prep(a.ctrl, vmax);
+}
+
+// Time steps of the next coarse step and its substeps; errors of any grid
+// stop all of them.  `slot` is the coarse list slot of the next step.
+template <typename real>
+__global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Ctrl* c = a.ctrl;
+    const double S = fmax(c->speed, prep_speed(c, real(0)));
+    c->prep_speed = 0ull;
+    c->speed = S;
+    double tc = cfl_tau_of(a, S);
+    for (int k = 0; k < n.np; ++k) tc = fmin(tc, (double)n.r * n.P[k].ctrl->tau_cfl);
+    tc = (double)(real)tc;
+    set_next_step(a, c, tc);
+    const double tf = (double)(real)(tc / (double)n.r);
+    int e = c->err;
+    for (int k = 0; k < n.np; ++k) {
+        Ctrl* p = n.P[k].ctrl;
+        p->tau = tf;
+        p->dV = 0.0;
+        p->sdepth = 0.0;
+        if (!e && p->err) e = p->err;
+    }
+    if (a.skip) close_segments(c, a.hot, slot);
+    if (e) {
+        c->err = e;
+        c->err_gate = e;
+        for (int k = 0; k < n.np; ++k) n.P[k].ctrl->err_gate = e;
+    }
+}
+
+// Fixed-order sum of a field (volume of the nested solution): per-block
+// partials, then k_sum_tiles.
+template <typename real>
+__global__ void k_field_partials(const real* f, int n, int chunk, double* part) {
+    __shared__ double red[256 / 64];
+    const int b = blockIdx.x, i0 = b * chunk, i1 = min(n, i0 + chunk);
+    double s = 0.0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) s += (double)f[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int q = 0; q < (int)blockDim.x / 64; ++q) v += red[q];
+        part[b] = v;
+    }
+}
+
+}  // namespace swe

@@ -69,6 +69,8 @@ struct Ctrl {
     long long step;      // completed steps
     long long tiles;     // processed tile-steps
     long long cells;     // processed in-domain cell-steps
+    double speed;        // maximum CFL speed of the current layer
+    double tau_cfl;      // CFL time step of the current layer (rounded to the stencil type)
 };
 
 // A tile-list entry packs the scenario of a batch (0 for a single grid) above
@@ -100,6 +102,12 @@ struct Args {
     real h, ih, g, eps, nuh2, fcor, wx, wy, kw, hw;     // stencil constants
     double h_d, g_d, cfl, tau_max, tau_min, nu_d, nin_h2;
     double q_base, q_peak, t_peak, sigma_t;
+    // nested grids: the step leaves tau, dV and sdepth to the nest (hold);
+    // tap rectangles [x0, y0, x1, y1, offset] whose boundary-face fluxes
+    // (times tau) the step adds into tap (TAP kernels only)
+    int hold, ntap;
+    const int* tap_rect;
+    real* tap;
 };
 
 // ---------------------------------------------------------------- math
@@ -283,13 +291,19 @@ __device__ __forceinline__ double hydro_volume(double qb, double qp, double tp, 
     return v;
 }
 
-// Next time step and source from the maximum speed S of the new layer.
+// CFL time step from the maximum speed S of a layer (Sec. 2.3, stage I),
+// rounded to the stencil type.
 template <typename real>
-__device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
+__device__ double cfl_tau_of(const Args<real>& a, double S) {
     double tau = a.tau_max > 0.0 ? a.tau_max : __builtin_inf();
     if (S > 0.0) tau = fmin(tau, a.cfl * a.h_d / S);
     if (a.nu_d > 0.0) tau = fmin(tau, a.h_d * a.h_d / (4.0 * a.nu_d));
-    tau = (double)(real)tau;
+    return (double)(real)tau;
+}
+
+// Time step tau of the next step and its hydrograph volume and source depth.
+template <typename real>
+__device__ void set_next_step(const Args<real>& a, Ctrl* c, double tau) {
     if (!(tau >= a.tau_min) || !(tau < __builtin_inf())) c->err = -5;
     c->tau = tau;
     double dV = 0.0;
@@ -297,6 +311,16 @@ __device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
         dV = hydro_volume(a.q_base, a.q_peak, a.t_peak, a.sigma_t, c->t, tau);
     c->dV = dV;
     c->sdepth = a.nin_h2 > 0.0 ? (double)(real)(dV / a.nin_h2) : 0.0;
+}
+
+// Bookkeeping of a new layer with maximum speed S: its CFL step, and unless
+// a nest sets the steps (hold), the next step's scalars.
+template <typename real>
+__device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
+    const double tau = cfl_tau_of(a, S);
+    c->speed = S;
+    c->tau_cfl = tau;
+    if (!a.hold) set_next_step(a, c, tau);
 }
 
 // Prefix offsets of the list segments of `slot` from their counters.
@@ -338,6 +362,34 @@ __device__ __forceinline__ void append_tiles(int cand, int sid, int tile_base, i
 template <typename real>
 __device__ __forceinline__ bool is_src(const Args<real>& a, int gx, int gy) {
     return (unsigned)(gx - a.i0) < (unsigned)a.ni && (unsigned)(gy - a.j0) < (unsigned)a.nj;
+}
+
+// Flux taps of nested grids.  A tap rectangle [x0, x1) x [y0, y1) of cells
+// owns 2(y1-y0) + 2(x1-x0) boundary faces, stored side by side (west x faces
+// at x0, east x faces at x1, south y faces at y0, north y faces at y1) in
+// three component planes: depth, normal momentum, tangential momentum.  Cell
+// (gx, gy) adds tau * flux of its west face (fluxes xH, xN, xT) and its south
+// face (yH, yN, yT) where they are tap faces.
+template <typename real>
+__device__ __forceinline__ void tap_faces(const Args<real>& a, int gx, int gy, real tau, real xH, real xN,
+                                          real xT, real yH, real yN, real yT) {
+    for (int q = 0; q < a.ntap; ++q) {
+        const int* R = a.tap_rect + 5 * q;
+        const int w = R[2] - R[0], hh = R[3] - R[1], per = 2 * (w + hh);
+        real* T = a.tap + R[4];
+        if ((gx == R[0] || gx == R[2]) && gy >= R[1] && gy < R[3]) {
+            const int k = (gx == R[0] ? 0 : hh) + gy - R[1];
+            T[k] += tau * xH;
+            T[per + k] += tau * xN;
+            T[2 * per + k] += tau * xT;
+        }
+        if ((gy == R[1] || gy == R[3]) && gx >= R[0] && gx < R[2]) {
+            const int k = 2 * hh + (gy == R[1] ? 0 : w) + gx - R[0];
+            T[k] += tau * yH;
+            T[per + k] += tau * yN;
+            T[2 * per + k] += tau * yT;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- LDS of a tile
@@ -399,7 +451,7 @@ __device__ void fill_ghosts(int tx0, int ty0, int nx, int ny, int x0, int x1, in
 
 // bits: 1 own wet, 2 W edge, 4 E edge, 8 S edge, 16 N edge (layer n+1),
 // 32 ring wet (layer n+1), 64 K1-active at layer n
-template <typename real, int TX, int TY, int NT, int LIM, bool EDGE>
+template <typename real, int TX, int TY, int NT, int LIM, bool EDGE, bool TAP>
 __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, int ty0,
                           real tau, real sdep, real& vmax, bool& bad, double& msum, double& lsum,
                           int& bits) {
@@ -655,6 +707,19 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     // ---- FY + final update: columns -1..TX, runs of 4 cells along y
     {
         constexpr int NC = TX + 2, NRY = (TY + 2 + RUN - 1) / RUN, NR = NC * NRY;
+        // tap faces in this tile: a face belongs to the tile of the cell east
+        // (x face) or north (y face) of it
+        bool tap_here = false;
+        if constexpr (TAP) {
+            for (int q = 0; q < a.ntap; ++q) {
+                const int* R = a.tap_rect + 5 * q;
+                const bool xs = ty0 < R[3] && ty0 + TY > R[1] &&
+                                ((R[0] >= tx0 && R[0] < tx0 + TX) || (R[2] >= tx0 && R[2] < tx0 + TX));
+                const bool ys = tx0 < R[2] && tx0 + TX > R[0] &&
+                                ((R[1] >= ty0 && R[1] < ty0 + TY) || (R[3] >= ty0 && R[3] < ty0 + TY));
+                tap_here |= xs || ys;
+            }
+        }
         for (int k = tid; k < NR; k += NT) {
             const int x = k % NC - 1, y0 = (k / NC) * RUN - 1;
             Cell<real> cl[RUN + 4];
@@ -703,6 +768,10 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     msum += (double)Hc;
                     lsum += (double)(Hc - Hn);
                     bad |= !finite(Hn) || !finite(qx) || !finite(qy);
+                    if constexpr (TAP) {
+                        if (tap_here)
+                            tap_faces(a, tx0 + x, ty0 + y, tau, L.HX[s], L.HY[s], L.H[s], FH[i], Fn[i], Ft[i]);
+                    }
                 }
             }
         }
@@ -758,7 +827,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
 // ---------------------------------------------------------------- step kernel
 
-template <typename real, int TX, int TY, int NT, int LIM>
+template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
 __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
@@ -790,9 +859,9 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
         int bits = 0;
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, TAP>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
         else
-            tile_step<real, TX, TY, NT, LIM, false>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, TAP>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
         // block reductions: flags, volume and ledger partials
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
@@ -1022,9 +1091,9 @@ __global__ __launch_bounds__(NT, 2048 / NT) void k_batch_step(BatchArgs<real> ba
         int bits = 0;
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
         else
-            tile_step<real, TX, TY, NT, LIM, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         bits |= __any(bad) ? 128 : 0;

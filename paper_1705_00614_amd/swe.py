@@ -39,6 +39,15 @@ class SweParams(ctypes.Structure):
     ]
 
 
+class SwePatch(ctypes.Structure):
+    """Mirror of swe_patch in swe.h."""
+    _fields_ = [("ci0", ctypes.c_int), ("cj0", ctypes.c_int), ("cw", ctypes.c_int), ("ch", ctypes.c_int),
+                ("b", _dp), ("n_M", _dp), ("H0", _dp), ("Qx0", _dp), ("Qy0", _dp)]
+
+
+NEST_FRAME = 5   # SWE_NEST_FRAME
+
+
 # Every function declared in include/swe.h, with its ctypes signature.
 EXPORTS = {
     "swe_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
@@ -71,6 +80,16 @@ EXPORTS = {
     "swe_batch_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]),
     "swe_batch_destroy": (None, [ctypes.c_void_p]),
+    "swe_nest_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
+                                          ctypes.POINTER(SweParams), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p]),
+    "swe_nest_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
+    "swe_nest_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
+    "swe_nest_query": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long),
+                                      _dp, _dp]),
+    "swe_nest_get_coarse": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "swe_nest_get_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]),
+    "swe_nest_destroy": (None, [ctypes.c_void_p]),
     "swe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -336,3 +355,87 @@ class Batch:
         t, c, n = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
         _check(load().swe_batch_work(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(n)))
         return dict(tile_steps=t.value, cell_steps=c.value, total_tiles=n.value)
+
+
+class Nest:
+    """Coarse grid with refined patches (``swe_nest_*``), from a dict with
+    keys coarse (scenario dict), patches (dicts with ci0, cj0, cw, ch and the
+    extended fine b, n_manning, interior H0, Qx0, Qy0) and r."""
+
+    def __init__(self, nest, feedback=True, precision=None, skip_dry=True, stream="torch"):
+        L = load()
+        sc, r = nest["coarse"], int(nest["r"])
+        st = current_stream() if stream == "torch" else stream
+        pr = dict(sc["params"])
+        if precision is not None:
+            pr["precision"] = precision
+        p = make_params(pr, skip_dry, (0, 0), st)
+        self.shape = (int(sc["ny"]), int(sc["nx"]))
+        self.r = r
+        b = _f64(sc["b"], self.shape)
+        nm = _f64(sc.get("n_manning"), self.shape)
+        H0, Qx0, Qy0 = (_f64(sc.get(q), self.shape) for q in ("H0", "Qx0", "Qy0"))
+        solid = sc.get("solid")
+        solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+        p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
+        keep = [b, nm, H0, Qx0, Qy0, solid]
+        pats = nest["patches"]
+        arr = (SwePatch * len(pats))()
+        self.pshapes = []
+        for k, q in enumerate(pats):
+            cw, ch = int(q["cw"]), int(q["ch"])
+            ext = (r * ch + 2 * NEST_FRAME, r * cw + 2 * NEST_FRAME)
+            inner = (r * ch, r * cw)
+            fb = _f64(q["b"], ext)
+            fn = _f64(q.get("n_manning"), ext)
+            fH, fX, fY = (_f64(q.get(f), inner) for f in ("H0", "Qx0", "Qy0"))
+            keep += [fb, fn, fH, fX, fY]
+            arr[k] = SwePatch(int(q["ci0"]), int(q["cj0"]), cw, ch, _ptr(fb), _ptr(fn), _ptr(fH), _ptr(fX),
+                              _ptr(fY))
+            self.pshapes.append(inner)
+        self._h = L.swe_nest_create(self.shape[1], self.shape[0], float(sc["h"]), _ptr(b), _ptr(nm),
+                                    ctypes.byref(p), r, 1 if feedback else 0, len(pats),
+                                    ctypes.cast(arr, ctypes.c_void_p))
+        del keep
+        if not self._h:
+            raise SweError(SWE_EINVAL, last_error())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_nest_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def run(self, n):
+        return _check(load().swe_nest_run(self._h, int(n)))
+
+    def run_rc(self, n):
+        return load().swe_nest_run(self._h, int(n))
+
+    def run_timed(self, n):
+        ms = ctypes.c_double(0.0)
+        _check(load().swe_nest_run_timed(self._h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def query(self):
+        v = [ctypes.c_double() for _ in range(6)]
+        st = ctypes.c_long()
+        _check(load().swe_nest_query(self._h, ctypes.byref(v[0]), ctypes.byref(v[1]), ctypes.byref(v[2]),
+                                     ctypes.byref(v[3]), ctypes.byref(st), ctypes.byref(v[4]),
+                                     ctypes.byref(v[5])))
+        return dict(time=v[0].value, volume=v[1].value, inflow=v[2].value, ledger=v[3].value,
+                    steps=st.value, dt_coarse=v[4].value, dt_fine=v[5].value)
+
+    def coarse_state(self):
+        H, Qx, Qy = (np.empty(self.shape) for _ in range(3))
+        _check(load().swe_nest_get_coarse(self._h, _ptr(H), _ptr(Qx), _ptr(Qy)))
+        return H, Qx, Qy
+
+    def patch_state(self, k):
+        shp = self.pshapes[k]
+        H, Qx, Qy = (np.empty(shp) for _ in range(3))
+        _check(load().swe_nest_get_patch(self._h, int(k), _ptr(H), _ptr(Qx), _ptr(Qy)))
+        return H, Qx, Qy

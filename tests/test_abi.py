@@ -37,19 +37,29 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert isinstance(L.swe_last_error(), bytes)
 
 
-def test_params_struct_matches_header_field_order():
+def _struct_fields(name):
     txt = open(HEADER).read()
-    body = txt[txt.index("typedef struct {"):txt.index("} swe_params;")]
+    end = txt.index("} %s;" % name)
+    body = txt[txt.rindex("typedef struct {", 0, end):end]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = []
     for decl in body.split(";")[:-1]:
         decl = decl.replace("typedef struct {", "").strip()
         if not decl:
             continue
-        names = decl.split()[-1] if "," not in decl else decl
         for part in decl.split(","):
             fields.append(part.strip().split()[-1].lstrip("*"))
-    assert fields == [f[0] for f in swe.SweParams._fields_]
+    return fields
+
+
+def test_params_struct_matches_header_field_order():
+    assert _struct_fields("swe_params") == [f[0] for f in swe.SweParams._fields_]
+
+
+def test_patch_struct_matches_header_field_order():
+    assert _struct_fields("swe_patch") == [f[0] for f in swe.SwePatch._fields_]
+    txt = open(HEADER).read()
+    assert "#define SWE_NEST_FRAME %d" % swe.NEST_FRAME in txt
 
 
 def test_library_built_for_gfx950():

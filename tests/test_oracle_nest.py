@@ -72,6 +72,8 @@ def test_volume_conserved_with_inflow():
         assert min(p["sim"].state()[0].min() for p in N.P) > 0.0
         err = N.volume() - V0 - N.inflow() - N.total_ledger()
         assert abs(err) <= 1e-12 * V0, (k, err / V0)
+        # the next coarse step respects the CFL step of the coarse layer after the feedback
+        assert N.tau_c <= N.c.next_tau() and N.tau_f == N.tau_c / N.r
     assert N.inflow() > 0.0 and N.total_ledger() == 0.0
 
 
