@@ -16,10 +16,18 @@ roofline     the step kernel: algorithmic bytes (32 B per processed FP32 cell:
              reads H, Qx, Qy, b, c_f; writes H, Qx, Qy) per launch over its
              mean launch duration, from per-launch HIP events over the timed
              steps, against the 8 TB/s HBM peak
+             traffic: HBM bytes per launch of the same kernel on the same
+             workload and steps from rocprofv3 FETCH_SIZE and WRITE_SIZE
+             counters scaled by a plain copy of known size (a summary under
+             profiles/), or null when the kernel source changed since
 cpu_baseline the FP64 CPU oracle on the host, a bounded sample of the same
              workload (its first steps from the initial state, every cell)
+
+--copy-calibration M copies M MiB device to device once before the warm-up,
+so that a counter run of this command also measures the copy kernel.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,10 +50,38 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--warmup-launches", action="store_true",
+                    help="run the warm-up as single launches (no hipGraph), e.g. under counter collection")
     ap.add_argument("--graph", action="store_true",
                     help="time hipGraph replays instead of per-launch events (no roofline)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    src = os.path.join(ROOT, "paper_1705_00614_amd", "csrc", "swe_step.hpp")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def profiled_traffic(key):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    with the current kernel source for the same workload and steps."""
+    path = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_digest() or vals.get("run_key") != key:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(sc, steps):
@@ -80,9 +116,20 @@ def main():
     prec = sc["params"]["precision"]
     stream = torch.cuda.Stream()          # default priority, not the null stream
     with torch.cuda.stream(stream):
+        if args.copy_calibration > 0:
+            n = args.copy_calibration * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         g = swe.Solver(sc, tile=tile)
         V0 = g.mass()
-        g.run(args.warmup)
+        if args.warmup_launches:
+            g.run_timed(args.warmup)
+        else:
+            g.run(args.warmup)
         torch.cuda.synchronize()
         w0, t_sim0 = g.work(), g.time()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -131,8 +178,10 @@ def main():
     if kernel_ms is not None:
         alg_bytes = BYTES_PER_CELL[prec] * cells
         achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+        key = "%s n=%d tile=%s warmup=%d steps=%d" % (args.workload, args.n, args.tile, args.warmup, args.steps)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(key),
+                           "traffic_unit": "HBM bytes per launch",
                            "kernel": "swe::k_step<%s,%d,%d>" % ("float" if prec == 32 else "double",
                                                                 w1["tile"][0], w1["tile"][1]),
                            "mean_launch_us": kernel_ms * 1e3 / args.steps,

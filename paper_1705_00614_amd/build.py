@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe_hip.so")
 SOURCES = [os.path.join(CSRC, "swe_api.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "swe_step.hpp"),
+DEPS = SOURCES + [os.path.join(CSRC, "swe_step.hpp"), os.path.join(CSRC, "swe_nest.hpp"),
                   os.path.join(os.path.dirname(HERE), "include", "swe.h")]
 
 # Packed FP32 instructions are disabled on purpose: every FP32 operation is
@@ -20,8 +20,10 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False, resource_report=None):
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", LIB] + SOURCES
+def build(verbose=False, resource_report=None, out=None, defines=()):
+    """Compile the library (to `out`, default in-tree); `defines` are extra
+    -D settings such as SWE_WAVES_PER_SIMD_F32=2."""
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-D" + d for d in defines] + ["-o", out or LIB] + SOURCES
     if resource_report:
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -30,10 +32,10 @@ def build(verbose=False, resource_report=None):
             f.write(res.stderr)
     if res.returncode != 0:
         sys.stderr.write(res.stderr)
-        raise RuntimeError("hipcc failed building %s" % LIB)
+        raise RuntimeError("hipcc failed building %s" % (out or LIB))
     if verbose:
         sys.stderr.write(res.stderr)
-    return LIB
+    return out or LIB
 
 
 if __name__ == "__main__":

@@ -5,6 +5,7 @@
 // Sec. 2.3) on the caller's stream, replaying captured hipGraphs for long
 // runs.  No arithmetic of the scheme runs on the host.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -47,9 +48,12 @@ constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even)
 
 struct Launcher {
     int tx, ty, nt, precision, limiter;
-    hipError_t (*step)(const void* args, int grid, hipStream_t st);
-    hipError_t (*step_tap)(const void* args, int grid, hipStream_t st);   // nested grids; may be null
-    hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st);
+    // step kernels; the optional events are stamped by the dispatch itself
+    // (start and end of this kernel only)
+    hipError_t (*step)(const void* args, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+    hipError_t (*step_tap)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
+                           hipEvent_t e1);   // nested grids; may be null
+    hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
     hipError_t (*prepare_finish)(const void* args, hipStream_t st);
@@ -57,15 +61,15 @@ struct Launcher {
 };
 
 template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
-hipError_t launch_step(const void* args, int grid, hipStream_t st) {
+hipError_t launch_step(const void* args, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const Args<real>& a = *static_cast<const Args<real>*>(args);
-    hipLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM, TAP>), dim3(grid), dim3(NT), 0, st, a);
+    hipExtLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM, TAP>), dim3(grid), dim3(NT), 0, st, e0, e1, 0, a);
     return hipGetLastError();
 }
 template <typename real, int TX, int TY, int NT, int LIM>
-hipError_t launch_batch_step(const void* bargs, int grid, hipStream_t st) {
+hipError_t launch_batch_step(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const swe::BatchArgs<real>& b = *static_cast<const swe::BatchArgs<real>*>(bargs);
-    hipLaunchKernelGGL((swe::k_batch_step<real, TX, TY, NT, LIM>), dim3(grid), dim3(NT), 0, st, b);
+    hipExtLaunchKernelGGL((swe::k_batch_step<real, TX, TY, NT, LIM>), dim3(grid), dim3(NT), 0, st, e0, e1, 0, b);
     return hipGetLastError();
 }
 template <typename real>
@@ -106,8 +110,14 @@ int occupancy(int* blocks) {
 
 // Tile shapes compiled in, each with the three limiters; the first shape of
 // each precision is its default and the one nested grids use.
+// 256 threads per 32 x 32 tile: two workgroups per CU (LDS-bound), a
+// register budget with no spills, and the lowest latency per tile, which
+// sets the step time when few tiles are wet.
+#ifndef SWE_F32_THREADS
+#define SWE_F32_THREADS 256
+#endif
 const Launcher kLaunchers[] = {
-    LAUNCHERS(float, 32, 32, 512, 32, TAP_STEP),
+    LAUNCHERS(float, 32, 32, SWE_F32_THREADS, 32, TAP_STEP),
     LAUNCHERS(float, 64, 16, 512, 32, NO_TAP_STEP),
     LAUNCHERS(float, 16, 16, 256, 32, NO_TAP_STEP),
     LAUNCHERS(double, 16, 16, 256, 64, TAP_STEP),
@@ -211,8 +221,8 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
 }
 
 // Step kernel of a grid: the tapping variant for members of a nest.
-hipError_t launch_grid_step(swe_t* s, int par) {
-    return (s->ntap > 0 ? s->L->step_tap : s->L->step)(s->args[par].data(), s->grid, s->stream);
+hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    return (s->ntap > 0 ? s->L->step_tap : s->L->step)(s->args[par].data(), s->grid, s->stream, e0, e1);
 }
 
 void build_args(swe_t* s) {
@@ -291,13 +301,13 @@ int set_state_impl(swe_t* s, const double* H, const double* Qx, const double* Qy
 }
 
 void free_all(swe_t* s) {
-    if (s->graph) hipGraphExecDestroy(s->graph);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
     void* ptrs[] = {s->Hb[0], s->Hb[1], s->Qxb[0], s->Qxb[1], s->Qyb[0], s->Qyb[1], s->bed, s->cf,
                     s->ctrl, s->hot, s->lists, s->stamp, s->wg_speed, s->wg_cells, s->mass, s->ledger,
                     s->scalar};
     for (void* q : ptrs)
-        if (q) hipFree(q);
-    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+        if (q) (void)hipFree(q);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
 int launch_steps(swe_t* s, long n) {
@@ -316,21 +326,56 @@ int ensure_graph(swe_t* s) {
     for (int k = 0; k < GRAPH_STEPS; ++k) {
         hipError_t e = launch_grid_step(s, k & 1);
         if (e != hipSuccess) {
-            hipStreamEndCapture(s->stream, &g);
-            if (g) hipGraphDestroy(g);
+            (void)hipStreamEndCapture(s->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
             set_hip_err("graph capture", e);
             return SWE_EHIP;
         }
     }
     HIPCHK(hipStreamEndCapture(s->stream, &g));
     hipError_t e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         s->graph = nullptr;
         set_hip_err("graph instantiation", e);
         return SWE_EHIP;
     }
     return 0;
+}
+
+// Launch n steps, each given an event pair to stamp (launch_one(e0, e1));
+// *ms gets the summed durations.  Up to POOL pairs are recorded before the stream is drained, so a
+// run of that many steps has no host synchronisation inside it.
+template <typename F>
+int timed_launches(hipStream_t st, long n, double* ms, F&& launch_one) {
+    constexpr long POOL = 16384;
+    const long m = n < POOL ? n : POOL;
+    std::vector<hipEvent_t> ev(2 * (size_t)m);
+    int rc = 0;
+    size_t made = 0;
+    for (; made < ev.size(); ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) { set_err("timed run: hipEventCreate failed"); rc = SWE_EHIP; break; }
+    double total = 0.0;
+    long left = n;
+    while (rc == 0 && left > 0) {
+        const long c = left < m ? left : m;
+        for (long k = 0; k < c && rc == 0; ++k) {
+            const hipError_t e = launch_one(ev[2 * k], ev[2 * k + 1]);
+            if (e != hipSuccess) { set_hip_err("timed run", e); rc = SWE_EHIP; }
+        }
+        if (rc == 0 && hipStreamSynchronize(st) != hipSuccess) { set_err("timed run: sync failed"); rc = SWE_EHIP; }
+        for (long k = 0; k < c && rc == 0; ++k) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, ev[2 * k], ev[2 * k + 1]) != hipSuccess) {
+                set_err("timed run: event timing failed"); rc = SWE_EHIP;
+            }
+            total += f;
+        }
+        left -= c;
+    }
+    for (size_t k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+    *ms = total;
+    return rc;
 }
 
 int finish(swe_t* s) {
@@ -483,7 +528,7 @@ swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
 
 void swe_destroy(swe_t* s) {
     if (!s) return;
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
     free_all(s);
     delete s;
 }
@@ -517,31 +562,13 @@ int swe_run(swe_t* s, long nsteps) {
 
 int swe_run_timed(swe_t* s, long nsteps, double* kernel_ms) {
     if (!s || nsteps < 0 || !kernel_ms) { set_err("swe_run_timed: invalid arguments"); return SWE_EINVAL; }
-    const long chunk = 256;
-    std::vector<hipEvent_t> ev(2 * chunk);
-    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    double total = 0.0;
-    long left = nsteps;
-    int rc = 0;
-    while (left > 0 && rc == 0) {
-        const long m = left < chunk ? left : chunk;
-        for (long k = 0; k < m; ++k) {
-            const int par = (int)(s->launched & 1);
-            HIPCHK(hipEventRecord(ev[2 * k], s->stream));
-            HIPCHK(launch_grid_step(s, par));
-            HIPCHK(hipEventRecord(ev[2 * k + 1], s->stream));
-            s->launched++;
-        }
-        HIPCHK(hipStreamSynchronize(s->stream));
-        for (long k = 0; k < m; ++k) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
-            total += ms;
-        }
-        left -= m;
-    }
-    for (auto& e : ev) hipEventDestroy(e);
-    *kernel_ms = total;
+    int rc = timed_launches(s->stream, nsteps, kernel_ms, [&](hipEvent_t e0, hipEvent_t e1) {
+        const int par = (int)(s->launched & 1);
+        const hipError_t e = launch_grid_step(s, par, e0, e1);
+        s->launched++;
+        return e;
+    });
+    if (rc) return rc;
     return finish(s);
 }
 
@@ -794,7 +821,7 @@ int batch_finish(swe_batch_t* b) {
 int batch_launch(swe_batch_t* b, long n) {
     for (long k = 0; k < n; ++k) {
         const int par = (int)(b->launched & 1);
-        HIPCHK(b->L->batch_step(b->bargs[par].data(), b->grid, b->stream));
+        HIPCHK(b->L->batch_step(b->bargs[par].data(), b->grid, b->stream, nullptr, nullptr));
         b->launched++;
     }
     return 0;
@@ -952,7 +979,7 @@ int swe_batch_run(swe_batch_t* b, long nsteps) {
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < GRAPH_STEPS; ++k) {
-                hipError_t e = b->L->batch_step(b->bargs[k & 1].data(), b->grid, b->stream);
+                hipError_t e = b->L->batch_step(b->bargs[k & 1].data(), b->grid, b->stream, nullptr, nullptr);
                 if (e != hipSuccess) {
                     (void)hipStreamEndCapture(b->stream, &g);
                     if (g) (void)hipGraphDestroy(g);
@@ -977,24 +1004,13 @@ int swe_batch_run(swe_batch_t* b, long nsteps) {
 
 int swe_batch_run_timed(swe_batch_t* b, long nsteps, double* kernel_ms) {
     if (!b || nsteps < 0 || !kernel_ms) { set_err("swe_batch_run_timed: invalid arguments"); return SWE_EINVAL; }
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    double total = 0.0;
-    for (long k = 0; k < nsteps; ++k) {
+    int rc = timed_launches(b->stream, nsteps, kernel_ms, [&](hipEvent_t e0, hipEvent_t e1) {
         const int par = (int)(b->launched & 1);
-        HIPCHK(hipEventRecord(e0, b->stream));
-        HIPCHK(b->L->batch_step(b->bargs[par].data(), b->grid, b->stream));
-        HIPCHK(hipEventRecord(e1, b->stream));
+        const hipError_t e = b->L->batch_step(b->bargs[par].data(), b->grid, b->stream, e0, e1);
         b->launched++;
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        total += ms;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *kernel_ms = total;
+        return e;
+    });
+    if (rc) return rc;
     return batch_finish(b);
 }
 
@@ -1108,11 +1124,11 @@ struct swe_nest_s {
 namespace {
 
 void free_nest(swe_nest_t* n) {
-    if (n->graph) hipGraphExecDestroy(n->graph);
+    if (n->graph) (void)hipGraphExecDestroy(n->graph);
     for (swe_t* q : n->p) if (q) swe_destroy(q);
     if (n->c) swe_destroy(n->c);
     void* ptrs[] = {n->tap, n->ints, n->desc, n->ring_ledger, n->part, n->scalar};
-    for (void* q : ptrs) if (q) hipFree(q);
+    for (void* q : ptrs) if (q) (void)hipFree(q);
 }
 
 template <typename real>
@@ -1255,12 +1271,12 @@ int nest_graph(swe_nest_t* n) {
     n->c->launched = c0;
     for (int k = 0; k < n->np; ++k) n->p[k]->launched = p0[k];
     if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         set_hip_err("nest graph capture", e != hipSuccess ? e : e2);
         return SWE_EHIP;
     }
     e = hipGraphInstantiate(&n->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) { n->graph = nullptr; set_hip_err("nest graph instantiation", e); return SWE_EHIP; }
     return 0;
 }
@@ -1461,7 +1477,7 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
 
 void swe_nest_destroy(swe_nest_t* n) {
     if (!n) return;
-    if (n->stream) hipStreamSynchronize(n->stream);
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
     free_nest(n);
     delete n;
 }
@@ -1490,23 +1506,13 @@ int swe_nest_run(swe_nest_t* n, long steps) {
 
 int swe_nest_run_timed(swe_nest_t* n, long steps, double* kernel_ms) {
     if (!n || steps < 0 || !kernel_ms) { set_err("swe_nest_run_timed: invalid arguments"); return SWE_EINVAL; }
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    double total = 0.0;
-    int rc = 0;
-    for (long k = 0; k < steps && rc == 0; ++k) {
-        HIPCHK(hipEventRecord(e0, n->stream));
-        rc = nest_launch(n, 1);
-        HIPCHK(hipEventRecord(e1, n->stream));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        total += ms;
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    *kernel_ms = total;
+    int rc = timed_launches(n->stream, steps, kernel_ms, [&](hipEvent_t e0, hipEvent_t e1) {
+        hipError_t e = hipEventRecord(e0, n->stream);
+        if (e == hipSuccess) e = nest_step(n);
+        if (e == hipSuccess) e = hipEventRecord(e1, n->stream);
+        n->launched++;
+        return e;
+    });
     if (rc) return rc;
     return nest_finish(n);
 }

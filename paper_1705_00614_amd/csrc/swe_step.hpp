@@ -827,8 +827,21 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
 // ---------------------------------------------------------------- step kernel
 
+// Waves per SIMD the step kernels are compiled for: the register budget per
+// lane is 512 / WAVES_PER_SIMD.  A budget below the kernel's live state spills
+// to scratch memory, which every launch then writes and reads through HBM.
+#ifndef SWE_WAVES_PER_SIMD_F32
+#define SWE_WAVES_PER_SIMD_F32 2
+#endif
+#ifndef SWE_WAVES_PER_SIMD_F64
+#define SWE_WAVES_PER_SIMD_F64 2
+#endif
+template <typename real> constexpr int waves_per_simd() {
+    return sizeof(real) == 4 ? SWE_WAVES_PER_SIMD_F32 : SWE_WAVES_PER_SIMD_F64;
+}
+
 template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
-__global__ __launch_bounds__(NT, 2048 / NT) void k_step(Args<real> a) {
+__global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
     __shared__ double red_d[2][NWAVE];
@@ -1059,7 +1072,7 @@ struct BatchArgs {
 };
 
 template <typename real, int TX, int TY, int NT, int LIM>
-__global__ __launch_bounds__(NT, 2048 / NT) void k_batch_step(BatchArgs<real> ba) {
+__global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(BatchArgs<real> ba) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
     __shared__ double red_d[3][NWAVE];
