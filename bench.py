@@ -71,17 +71,26 @@ def profiled_traffic(key):
     path = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
     if not os.path.exists(path):
         return None
-    vals = {}
+    blocks, cur = [], {}
     for line in open(path):
-        if ":" in line and not line.startswith("#"):
+        if line.startswith("#"):
+            continue
+        if not line.strip():
+            if cur:
+                blocks.append(cur)
+            cur = {}
+        elif ":" in line:
             k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_digest() or vals.get("run_key") != key:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+            cur[k.strip()] = v.strip()
+    if cur:
+        blocks.append(cur)
+    for vals in blocks:
+        if vals.get("kernel_source_sha256_16") == kernel_source_digest() and vals.get("run_key") == key:
+            try:
+                return float(vals["hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def cpu_baseline(sc, steps):
