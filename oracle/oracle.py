@@ -78,6 +78,7 @@ def lib():
         L.orc_get_faces.argtypes = [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                     _c_double_p, _c_double_p]
         L.orc_cell_speeds.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.orc_set_correction.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p]
         L.orc_tau_from_speed.restype = ctypes.c_double
         L.orc_tau_from_speed.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_hydrograph_volume.restype = ctypes.c_double
@@ -163,6 +164,17 @@ class OracleSim:
         out = np.empty((self.ny, self.nx))
         lib().orc_cell_speeds(self._h, _dp(out))
         return out
+
+    def set_correction(self, dE, dN):
+        """Flux corrections (3, ny, nx) through east and north faces, or None."""
+        if dE is None and dN is None:
+            rc = lib().orc_set_correction(self._h, None, None)
+        else:
+            shp = (3, self.ny, self.nx)
+            self._corr = [_f64(np.zeros(shp) if a is None else a, shp) for a in (dE, dN)]
+            rc = lib().orc_set_correction(self._h, _dp(self._corr[0]), _dp(self._corr[1]))
+        if rc:
+            raise RuntimeError("orc_set_correction failed: %d" % rc)
 
     def tau_from_speed(self, smax):
         return lib().orc_tau_from_speed(self._h, float(smax))

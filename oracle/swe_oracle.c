@@ -58,6 +58,7 @@ struct orc_sim {
     double *Utx, *Uty, *etat;       /* post-Lagrangian velocity and level */
     double *FxH, *FxQn, *FxQt;      /* x-faces (nx+1)*ny */
     double *FyH, *FyQn, *FyQt;      /* y-faces nx*(ny+1) */
+    double *corrE, *corrN;          /* flux corrections (3 planes of nx*ny) or NULL */
     double t, tau_last, ledger, inflow;
     long steps;
 };
@@ -154,6 +155,8 @@ void orc_destroy(orc_sim* s)
     free(s->solid);
     free(s->wet);
     free(s->wett);
+    free(s->corrE);
+    free(s->corrN);
     free(s);
 }
 
@@ -526,6 +529,22 @@ static void riemann(double g, face_state L, face_state R,
     *Fqt = 0.5 * (hL * L.un * L.ut + hR * R.un * R.ut) - 0.5 * a * (hR * R.ut - hL * L.ut);
 }
 
+/* Learned flux correction (added to the stage III fluxes before the final
+ * update): planes [mass, x-momentum, y-momentum] of the correction through
+ * the east (or north) face of cell k, which lies between cells cl and cr.
+ * The mass correction is dropped where its donor (upwind) cell is dry after
+ * the Lagrangian stage; wall faces take none. */
+static void add_correction(const orc_sim* s, const double* corr, long k, long cl, long cr,
+                           double* fH, double* fN, double* fT, int xface)
+{
+    const long n = (long)s->nx * s->ny;
+    const double dH = corr[k], dX = corr[n + k], dY = corr[2 * n + k];
+    const long donor = dH > 0.0 ? cl : cr;
+    if (s->wett[donor]) *fH += dH;
+    *fN += xface ? dX : dY;
+    *fT += xface ? dY : dX;
+}
+
 static void fluxes(orc_sim* s)
 {
     const double g = s->p.g;
@@ -538,6 +557,9 @@ static void fluxes(orc_sim* s)
             face_state R = reconstruct(s, cr, 1, -1, s->Utx, s->Uty);
             long f = (long)j * (s->nx + 1) + i;
             riemann(g, L, R, &s->FxH[f], &s->FxQn[f], &s->FxQt[f]);
+            if (s->corrE && i >= 1 && i <= s->nx - 1)
+                add_correction(s, s->corrE, (long)j * s->nx + i - 1, cl, cr,
+                               &s->FxH[f], &s->FxQn[f], &s->FxQt[f], 1);
         }
     /* y-faces: face j-1/2 between cells j-1 and j, j = 0..ny */
     for (int j = 0; j <= s->ny; ++j)
@@ -547,6 +569,9 @@ static void fluxes(orc_sim* s)
             face_state R = reconstruct(s, cr, px, -1, s->Uty, s->Utx);
             long f = (long)j * s->nx + i;
             riemann(g, L, R, &s->FyH[f], &s->FyQn[f], &s->FyQt[f]);
+            if (s->corrN && j >= 1 && j <= s->ny - 1)
+                add_correction(s, s->corrN, (long)(j - 1) * s->nx + i, cl, cr,
+                               &s->FyH[f], &s->FyQn[f], &s->FyQt[f], 0);
         }
 }
 
@@ -737,6 +762,21 @@ int orc_get_faces(const orc_sim* s, int dir, double* FH, double* Fqn, double* Fq
     if (FH) memcpy(FH, a, (size_t)n * sizeof(double));
     if (Fqn) memcpy(Fqn, b, (size_t)n * sizeof(double));
     if (Fqt) memcpy(Fqt, c, (size_t)n * sizeof(double));
+    return 0;
+}
+
+int orc_set_correction(orc_sim* s, const double* dE, const double* dN)
+{
+    if (!s) return ORC_EINVAL;
+    const long n = 3L * s->nx * s->ny;
+    free(s->corrE); free(s->corrN);
+    s->corrE = s->corrN = NULL;
+    if (!dE && !dN) return 0;
+    s->corrE = zalloc(n);
+    s->corrN = zalloc(n);
+    if (!s->corrE || !s->corrN) return ORC_ENOMEM;
+    if (dE) memcpy(s->corrE, dE, (size_t)n * sizeof(double));
+    if (dN) memcpy(s->corrN, dN, (size_t)n * sizeof(double));
     return 0;
 }
 
