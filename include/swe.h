@@ -136,6 +136,37 @@ int    swe_active_tiles(swe_t* s, int* out, int cap);
  * [ms].  For measurement. */
 int    swe_run_timed(swe_t* s, long nsteps, double* kernel_ms);
 
+/* Flux corrections added to the stage III fluxes (Sec. 2.3) of every later
+ * step, before the final update: dE through the east face and dN through the
+ * north face of each cell, each 3 planes of nx*ny (mass, x-momentum,
+ * y-momentum) row-major, FP64 on the host, copied.  The mass part is dropped
+ * where the face's upwind cell is dry after the Lagrangian stage, the
+ * momentum part unless both cells are wet; wall faces take none.  One of them NULL means zeros there; both NULL switch the
+ * corrections off.  Default tile shapes only; not for grids of a nest. */
+int    swe_set_correction(swe_t* s, const double* dE, const double* dN);
+
+/* Hold the step length at tau > 0 from the next step on (the CFL step is
+ * still recorded but not used; the hydrograph volume follows the clock);
+ * tau = 0 returns to CFL steps. */
+int    swe_hold_dt(swe_t* s, double tau);
+
+/* Line taps (training data for the learned correction): with r > 0 every
+ * later step adds tau * flux of the x faces whose column is a multiple of r,
+ * per row, and of the y faces whose row is a multiple of r, per column, into
+ * tapx [3][ny][nx/r + 1] and tapy [3][ny/r + 1][nx] (planes: mass, normal
+ * momentum, tangential momentum; the wall faces at nx and ny stay 0).  nx
+ * and ny must be multiples of r; default tile shape; r = 0 switches them
+ * off.  swe_zero_line_taps clears them; swe_get_line_taps copies them to the
+ * host (either may be NULL). */
+int    swe_enable_line_taps(swe_t* s, int r);
+int    swe_zero_line_taps(swe_t* s);
+int    swe_get_line_taps(swe_t* s, double* tapx, double* tapy);
+
+/* Set the current layer of coarse (both buffers) to the means of r x r
+ * cells of fine's current layer, and its clock to fine's; the coarse grid is
+ * r times smaller in each direction, same precision. */
+int    swe_restrict(swe_t* fine, swe_t* coarse, int r);
+
 /* ------------------------------------------------------------------ batches
  * A batch advances n independent scenarios together -- the paper's use case
  * of hundreds of runs over hydrograph and hydraulic-structure settings
@@ -243,6 +274,100 @@ int    swe_nest_get_patch(swe_nest_t* n, int k, double* H, double* Qx, double* Q
 
 /* Free the nest and its device memory.  NULL-safe. */
 void   swe_nest_destroy(swe_nest_t* n);
+
+/* ------------------------------------------------------------------ learned correction
+ * A convolutional network (four 3x3 valid convolutions, 6 -> 32 -> 32 -> 32
+ * -> 6 channels, tanh after the first three; bf16 weights and activations,
+ * FP32 accumulation on MFMA) that maps a crop of (S+9)^2 coarse cells to
+ * flux corrections of its central (S+1)^2 cells (an S x S tile and the cell
+ * row and column before it): (mass, x-momentum, y-momentum) through the
+ * east face, then the north face of each cell.  The
+ * corrections are added to the stage III fluxes (Sec. 2.3) of a coarse grid
+ * before its final update.  The paper has no learned component; this is an
+ * addition, trained on fine runs of this solver.
+ *
+ * Crops on the host are FP64 (n, S+9, S+9, 6) row-major, channels last:
+ * H, Ux, Uy, b, n_M, wet (U = Q/H where H > eps, else 0; wet 0/1), each
+ * divided by in_scale[k].  Network outputs (n, S+1, S+1, 6) are in units of
+ * out_scale (the correction is output * out_scale[k]).  Parameters are
+ * packed per layer as W[out][in][3][3] then b[out], layers in order, FP64 on
+ * the host (FP32 on the device). */
+typedef struct swe_lc_s swe_lc_t;
+
+/* Number of packed parameters. */
+int       swe_lc_nparams(void);
+
+/* Network for tiles of S = tile cells, buffers for up to max_crops crops,
+ * zero parameters; stream: hipStream_t or NULL for a private one.  NULL on
+ * error. */
+swe_lc_t* swe_lc_create(int tile, int max_crops, const double* in_scale, const double* out_scale,
+                        void* stream);
+void      swe_lc_destroy(swe_lc_t* c);
+
+/* Set (resets the Adam moments) or read the packed parameters. */
+int       swe_lc_set_params(swe_lc_t* c, const double* params);
+int       swe_lc_get_params(swe_lc_t* c, double* params);
+
+/* Network output of n host crops; out (n, S+1, S+1, 6) may be NULL. */
+int       swe_lc_forward(swe_lc_t* c, int n, const double* x, double* out);
+
+/* One training step on n host crops with labels y and mask (both
+ * (n, S+1, S+1, 6)): loss 1/2 sum mask (out - y)^2 / max(sum mask, 1), its
+ * gradient by back-propagation, then one Adam step (beta 0.9, 0.999, eps
+ * 1e-8) with learning rate lr (lr = 0: gradient only).  *loss may be NULL. */
+int       swe_lc_train_step(swe_lc_t* c, int n, const double* x, const double* y, const double* mask,
+                            double lr, double* loss);
+
+/* Packed gradient of the last training step. */
+int       swe_lc_get_grads(swe_lc_t* c, double* grads);
+
+/* Stored values of the last forward (test access): which = l in 0..3 gives
+ * the bf16 input of layer l, (n, S+9-2l, S+9-2l, real input channels);
+ * which = 4 + l the bf16 gradient dL/dz of layer l's output,
+ * (n, S+7-2l, S+7-2l, real output channels). */
+int       swe_lc_get_layer(swe_lc_t* c, int which, double* out);
+
+/* Attach the network to grid s (same tile size S, max_crops at least the
+ * grid's tile count, default tile shape): from then on every step of s first
+ * evaluates the network on the crops of s's active tiles, on s's stream, and
+ * uses the corrections of those tiles' cells and of the cell row and column
+ * before each (so every face of an active tile carries a fresh correction;
+ * other faces lie between dry cells and move no water).
+ * c = NULL detaches.  The network must outlive the attachment and must not
+ * be used on its own stream while s runs. */
+int       swe_lc_attach(swe_lc_t* c, swe_t* s);
+
+/* The crops the attached network would read before the next step of s: host
+ * FP64 (n, S+9, S+9, 6) into x (room for every tile), their tile indices
+ * (row-major tile order) into tiles (may be NULL).  Returns n, or a negative
+ * SWE_E* code. */
+int       swe_lc_gather(swe_lc_t* c, swe_t* s, double* x, int* tiles);
+
+/* Training data from the solver's own fine runs.  swe_lc_data allocates a
+ * device data set of `capacity` crops (emptying it).  swe_lc_collect takes
+ * one coarse interval of the fine grid f (line taps r enabled) and the
+ * coarse grid g (r times smaller, line taps 1 enabled, tiles of the
+ * network's size): g's layer becomes the r x r means of f's, the interval is
+ * tau_c = min(g's CFL step, m * f's CFL step); the crops of g's active tiles
+ * are added with labels (mean fine flux through each coarse east and north
+ * face over the m fine steps of tau_c / m, minus the coarse flux of one step
+ * of tau_c from the same layer, divided by out_scale; mask 0 on wall faces
+ * and cells outside the grid).  f advances by m steps and returns to CFL
+ * steps; *tau_out (may be NULL) gets tau_c.  swe_lc_get_data copies crops
+ * [first, first+n) back (any output may be NULL). */
+int       swe_lc_data(swe_lc_t* c, int capacity);
+int       swe_lc_data_count(swe_lc_t* c);
+int       swe_lc_collect(swe_lc_t* c, swe_t* f, swe_t* g, int r, int m, double* tau_out);
+int       swe_lc_get_data(swe_lc_t* c, int first, int n, double* x, double* y, double* mask, int* tiles);
+
+/* iters Adam steps (learning rate lr) on minibatches of `batch` distinct
+ * crops of the data set drawn with a seeded generator; losses (may be NULL)
+ * gets the loss of each step. */
+int       swe_lc_fit(swe_lc_t* c, int iters, int batch, double lr, unsigned long long seed, double* losses);
+
+/* New output scales (6 values > 0); the labels already in the data set are
+ * re-expressed in them. */
+int       swe_lc_set_out_scale(swe_lc_t* c, const double* out_scale);
 
 /* Message of the last error on this host thread ("" if none). */
 const char* swe_last_error(void);

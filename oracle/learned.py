@@ -12,7 +12,8 @@ kernels are checked against:
 
   network   four 3x3 "valid" convolutions (no padding) 6 -> 32 -> 32 -> 32 -> 6
             channels, tanh after the first three, linear output; an input
-            crop of (S + 8)^2 cells gives an S^2 output.  Output channels:
+            crop of (S + 9)^2 cells gives the (S + 1)^2 outputs of an S x S
+            tile and the cell row and column before it.  Output channels:
             corrections of (mass, x-momentum, y-momentum) flux through the
             east face, then through the north face, of each cell, in units of
             the scale vector the caller applies.
@@ -151,29 +152,37 @@ def mirror_index(i, n):
 
 
 def crops(feat, tiles, S):
-    """Input windows (len(tiles), S + 2*HALO, S + 2*HALO, 6) of the S x S
-    output tiles (tx, ty) (tile indices), mirrored at the domain edges.  A
-    velocity channel is mirrored as the cell's value; walls act through the
-    wet/dry and bed channels only."""
+    """Input windows (len(tiles), S + 1 + 2*HALO, S + 1 + 2*HALO, 6) of the
+    S x S tiles (tx, ty) (tile indices) and the cell row and column before
+    each (output cells tx*S - 1 .. tx*S + S - 1), mirrored at the domain
+    edges.  A velocity channel is mirrored as the cell's value; walls act
+    through the wet/dry and bed channels only."""
     ny, nx, _ = feat.shape
-    out = np.empty((len(tiles), S + 2 * HALO, S + 2 * HALO, feat.shape[2]))
+    side = S + 1 + 2 * HALO
+    out = np.empty((len(tiles), side, side, feat.shape[2]))
     for k, (tx, ty) in enumerate(tiles):
-        ys = mirror_index(np.arange(ty * S - HALO, ty * S + S + HALO), ny)
-        xs = mirror_index(np.arange(tx * S - HALO, tx * S + S + HALO), nx)
+        ys = mirror_index(np.arange(ty * S - 1 - HALO, ty * S - 1 - HALO + side), ny)
+        xs = mirror_index(np.arange(tx * S - 1 - HALO, tx * S - 1 - HALO + side), nx)
         out[k] = feat[np.ix_(ys, xs)]
     return out
 
 
 def corrections(out, tiles, S, ny, nx, scale):
-    """Scatter network outputs (len(tiles), S, S, 6) into east- and north-face
-    corrections (3, ny, nx) each, times the output scales."""
+    """Scatter network outputs (len(tiles), S+1, S+1, 6) of the cells
+    tx*S - 1 .. tx*S + S - 1 into east- and north-face corrections (3, ny, nx)
+    each, times the output scales (cells outside the grid dropped)."""
     dE = np.zeros((3, ny, nx))
     dN = np.zeros((3, ny, nx))
     o = out * np.asarray(scale, dtype=np.float64)
     for k, (tx, ty) in enumerate(tiles):
-        y0, x0 = ty * S, tx * S
-        h, w = min(S, ny - y0), min(S, nx - x0)
-        for c in range(3):
-            dE[c, y0:y0 + h, x0:x0 + w] = o[k, :h, :w, c]
-            dN[c, y0:y0 + h, x0:x0 + w] = o[k, :h, :w, 3 + c]
+        for j in range(S + 1):
+            gy = ty * S - 1 + j
+            if not 0 <= gy < ny:
+                continue
+            for i in range(S + 1):
+                gx = tx * S - 1 + i
+                if not 0 <= gx < nx:
+                    continue
+                dE[:, gy, gx] = o[k, j, i, 0:3]
+                dN[:, gy, gx] = o[k, j, i, 3:6]
     return dE, dN

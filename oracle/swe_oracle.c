@@ -533,7 +533,8 @@ static void riemann(double g, face_state L, face_state R,
  * update): planes [mass, x-momentum, y-momentum] of the correction through
  * the east (or north) face of cell k, which lies between cells cl and cr.
  * The mass correction is dropped where its donor (upwind) cell is dry after
- * the Lagrangian stage; wall faces take none. */
+ * the Lagrangian stage, the momentum correction unless both cells are wet (a
+ * film would otherwise gain momentum without water); wall faces take none. */
 static void add_correction(const orc_sim* s, const double* corr, long k, long cl, long cr,
                            double* fH, double* fN, double* fT, int xface)
 {
@@ -541,8 +542,10 @@ static void add_correction(const orc_sim* s, const double* corr, long k, long cl
     const double dH = corr[k], dX = corr[n + k], dY = corr[2 * n + k];
     const long donor = dH > 0.0 ? cl : cr;
     if (s->wett[donor]) *fH += dH;
-    *fN += xface ? dX : dY;
-    *fT += xface ? dY : dX;
+    if (s->wett[cl] && s->wett[cr]) {
+        *fN += xface ? dX : dY;
+        *fT += xface ? dY : dX;
+    }
 }
 
 static void fluxes(orc_sim* s)

@@ -79,7 +79,8 @@ int    orc_cell_speeds(orc_sim* s, double* out);
 /* Flux corrections added to every later step's stage III fluxes: dE through
  * the east face and dN through the north face of each cell, 3 planes of
  * nx*ny each (mass, x-momentum, y-momentum); the mass part is dropped where
- * the upwind cell is dry after the Lagrangian stage, wall faces take none.
+ * the upwind cell is dry after the Lagrangian stage, the momentum part
+ * unless both cells are wet; wall faces take none.
  * Both NULL clears them. */
 int    orc_set_correction(orc_sim* s, const double* dE, const double* dN);
 double orc_tau_from_speed(const orc_sim* s, double smax);

@@ -53,6 +53,8 @@ struct Launcher {
     hipError_t (*step)(const void* args, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*step_tap)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
                            hipEvent_t e1);   // nested grids; may be null
+    hipError_t (*step_corr)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
+                            hipEvent_t e1);  // learned flux corrections; may be null
     hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
@@ -60,10 +62,10 @@ struct Launcher {
     int (*occupancy)(int* blocks);
 };
 
-template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
+template <typename real, int TX, int TY, int NT, int LIM, int MODE>
 hipError_t launch_step(const void* args, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const Args<real>& a = *static_cast<const Args<real>*>(args);
-    hipExtLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM, TAP>), dim3(grid), dim3(NT), 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((swe::k_step<real, TX, TY, NT, LIM, MODE>), dim3(grid), dim3(NT), 0, st, e0, e1, 0, a);
     return hipGetLastError();
 }
 template <typename real, int TX, int TY, int NT, int LIM>
@@ -92,14 +94,15 @@ hipError_t launch_prepare_finish(const void* args, hipStream_t st) {
 }
 template <typename real, int TX, int TY, int NT, int LIM>
 int occupancy(int* blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT, LIM, false>, NT, 0) ==
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, swe::k_step<real, TX, TY, NT, LIM, swe::MODE_PLAIN>, NT, 0) ==
                    hipSuccess ? 0 : -1;
 }
 
-#define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, true>
-#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr
+#define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, swe::MODE_TAP>, \
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_CORR>
+#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr
 #define LAUNCHER(real, TX, TY, NT, P, LIM, TAPS)                                                 \
-    Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, false>,                       \
+    Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, swe::MODE_PLAIN>,             \
              TAPS(real, TX, TY, NT, LIM),                                                        \
              launch_batch_step<real, TX, TY, NT, LIM>, launch_batch_prepare_finish<real>,         \
              launch_prepare<real, TX, TY, NT>, launch_prepare_finish<real>,                      \
@@ -165,6 +168,17 @@ struct swe_s {
     int hold = 0, ntap = 0;
     const int* tap_rect = nullptr;
     void* tap = nullptr;
+    // learned flux corrections (east and north faces, 3 planes each)
+    void* corrE = nullptr;
+    void* corrN = nullptr;
+    bool corr = false;
+    // line taps (training labels): coarsening factor and buffers
+    int tap_r = 0;
+    void* tapx = nullptr;
+    void* tapy = nullptr;
+    // attached network: launched before every step to fill the corrections
+    struct swe_lc_s* lc = nullptr;
+    hipError_t (*pre_step)(swe_t* s, int par) = nullptr;
 };
 
 namespace {
@@ -218,11 +232,21 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->ntap = s->ntap;
     a->tap_rect = s->tap_rect;
     a->tap = (real*)s->tap;
+    a->corrE = (const real*)s->corrE;
+    a->corrN = (const real*)s->corrN;
+    a->tap_r = s->tap_r;
+    a->tapx = (real*)s->tapx;
+    a->tapy = (real*)s->tapy;
 }
 
 // Step kernel of a grid: the tapping variant for members of a nest.
 hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-    return (s->ntap > 0 ? s->L->step_tap : s->L->step)(s->args[par].data(), s->grid, s->stream, e0, e1);
+    if (s->pre_step) {
+        const hipError_t e = s->pre_step(s, par);
+        if (e != hipSuccess) return e;
+    }
+    auto f = (s->ntap > 0 || s->tap_r > 0) ? s->L->step_tap : s->corr ? s->L->step_corr : s->L->step;
+    return f(s->args[par].data(), s->grid, s->stream, e0, e1);
 }
 
 void build_args(swe_t* s) {
@@ -304,7 +328,7 @@ void free_all(swe_t* s) {
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     void* ptrs[] = {s->Hb[0], s->Hb[1], s->Qxb[0], s->Qxb[1], s->Qyb[0], s->Qyb[1], s->bed, s->cf,
                     s->ctrl, s->hot, s->lists, s->stamp, s->wg_speed, s->wg_cells, s->mass, s->ledger,
-                    s->scalar};
+                    s->scalar, s->corrE, s->corrN, s->tapx, s->tapy};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -317,6 +341,13 @@ int launch_steps(swe_t* s, long n) {
         s->launched++;
     }
     return 0;
+}
+
+// The captured graph holds the kernel of the current mode; a mode change
+// drops it.
+void drop_graph(swe_t* s) {
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
 }
 
 int ensure_graph(swe_t* s) {
@@ -376,6 +407,33 @@ int timed_launches(hipStream_t st, long n, double* ms, F&& launch_one) {
     for (size_t k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
     *ms = total;
     return rc;
+}
+
+template <typename real>
+hipError_t fill_dev(void* p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(swe::k_fill<real>, dim3(1024), dim3(256), 0, st, (real*)p, (long)n, real(0));
+    return hipGetLastError();
+}
+
+// Next step's length (tau <= 0: the layer's CFL step) and hydrograph
+// scalars, on the device; the tile list is kept.
+int set_dt_now(swe_t* s, double tau) {
+    const int par = (int)(s->launched & 1);
+    if (s->precision == 32)
+        hipLaunchKernelGGL(swe::k_set_dt<float>, dim3(1), dim3(64), 0, s->stream, *(const Args<float>*)s->args[par].data(),
+                           tau);
+    else
+        hipLaunchKernelGGL(swe::k_set_dt<double>, dim3(1), dim3(64), 0, s->stream,
+                           *(const Args<double>*)s->args[par].data(), tau);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return 0;
+}
+
+int grid_for_cells(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 int finish(swe_t* s) {
@@ -617,9 +675,10 @@ int swe_set_time(swe_t* s, double t) {
     char* cb = (char*)s->ctrl;
     HIPCHK(hipMemcpyAsync(cb + offsetof(Ctrl, t), &t, sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    // the next source volume depends on the clock: recompute the layer scalars
+    // the next source volume depends on the clock; the step length and the
+    // tile lists stay
     s->launched = c.step;
-    return prepare(s);
+    return set_dt_now(s, s->hold ? c.tau : 0.0);
 }
 
 double swe_mass(swe_t* s) {
@@ -702,6 +761,158 @@ int swe_active_tiles(swe_t* s, int* out, int cap) {
     }
     HIPCHK(hipStreamSynchronize(s->stream));
     return c.seg_off[par][swe::NSEG];
+}
+
+static size_t line_tap_sizes(const swe_t* s, size_t* nyx) {
+    const size_t ax = 3 * (size_t)s->ny * (s->nx / s->tap_r + 1);
+    *nyx = 3 * (size_t)(s->ny / s->tap_r + 1) * s->nx;
+    return ax;
+}
+
+int swe_enable_line_taps(swe_t* s, int r) {
+    if (!s || r < 0) { set_err("swe_enable_line_taps: invalid arguments"); return SWE_EINVAL; }
+    if (r == 0) {
+        if (s->tapx) (void)hipFree(s->tapx);
+        if (s->tapy) (void)hipFree(s->tapy);
+        s->tapx = s->tapy = nullptr;
+        s->tap_r = 0;
+        build_args(s);
+        drop_graph(s);
+        return 0;
+    }
+    if (s->nx % r || s->ny % r) { set_err("swe_enable_line_taps: grid size not a multiple of r"); return SWE_EINVAL; }
+    if (!s->L->step_tap || s->ntap > 0 || s->corr) {
+        set_err("swe_enable_line_taps: needs the default tile shape, not a nest member or corrected grid");
+        return SWE_EINVAL;
+    }
+    if (s->tapx) { (void)hipFree(s->tapx); (void)hipFree(s->tapy); s->tapx = s->tapy = nullptr; }
+    s->tap_r = r;
+    size_t ny_ = 0, nx_ = line_tap_sizes(s, &ny_);
+    HIPCHK(hipMalloc(&s->tapx, nx_ * s->rsize));
+    HIPCHK(hipMalloc(&s->tapy, ny_ * s->rsize));
+    build_args(s);
+    drop_graph(s);
+    return swe_zero_line_taps(s);
+}
+
+int swe_zero_line_taps(swe_t* s) {
+    if (!s || !s->tap_r) { set_err("swe_zero_line_taps: no line taps"); return SWE_EINVAL; }
+    size_t ny_ = 0, nx_ = line_tap_sizes(s, &ny_);
+    if (s->precision == 32) {
+        HIPCHK(fill_dev<float>(s->tapx, nx_, s->stream));
+        HIPCHK(fill_dev<float>(s->tapy, ny_, s->stream));
+    } else {
+        HIPCHK(fill_dev<double>(s->tapx, nx_, s->stream));
+        HIPCHK(fill_dev<double>(s->tapy, ny_, s->stream));
+    }
+    return 0;
+}
+
+int swe_get_line_taps(swe_t* s, double* tx, double* ty) {
+    if (!s || !s->tap_r) { set_err("swe_get_line_taps: no line taps"); return SWE_EINVAL; }
+    size_t ny_ = 0, nx_ = line_tap_sizes(s, &ny_);
+    double* outs[2] = {tx, ty};
+    void* srcs[2] = {s->tapx, s->tapy};
+    size_t ns[2] = {nx_, ny_};
+    for (int q = 0; q < 2; ++q) {
+        if (!outs[q]) continue;
+        std::vector<unsigned char> buf(ns[q] * s->rsize);
+        HIPCHK(hipMemcpyAsync(buf.data(), srcs[q], buf.size(), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < ns[q]; ++i)
+            outs[q][i] = s->precision == 32 ? (double)((float*)buf.data())[i] : ((double*)buf.data())[i];
+    }
+    return 0;
+}
+
+int swe_hold_dt(swe_t* s, double tau) {
+    if (!s || !(tau >= 0.0) || !std::isfinite(tau)) { set_err("swe_hold_dt: invalid arguments"); return SWE_EINVAL; }
+    if (s->ntap > 0) { set_err("swe_hold_dt: the nest sets the steps of its grids"); return SWE_EINVAL; }
+    Ctrl c;
+    int rc = sync_ctrl(s, &c);
+    if (rc) return rc;
+    s->launched = c.step;
+    s->hold = tau > 0.0 ? 1 : 0;
+    build_args(s);
+    drop_graph(s);
+    return set_dt_now(s, tau);
+}
+
+int swe_restrict(swe_t* fine, swe_t* coarse, int r) {
+    if (!fine || !coarse || r < 1 || fine->nx != r * coarse->nx || fine->ny != r * coarse->ny ||
+        fine->precision != coarse->precision) {
+        set_err("swe_restrict: the fine grid must be r times the coarse grid, same precision");
+        return SWE_EINVAL;
+    }
+    Ctrl cf, cc;
+    int rc = sync_ctrl(fine, &cf);
+    if (rc) return rc;
+    if ((rc = sync_ctrl(coarse, &cc))) return rc;
+    coarse->launched = cc.step;
+    const int pf = (int)(cf.step & 1);
+    const int nc = coarse->nx * coarse->ny;
+    if (fine->precision == 32)
+        hipLaunchKernelGGL(swe::k_restrict<float>, dim3(grid_for_cells(nc)), dim3(256), 0, fine->stream,
+                           (const float*)fine->Hb[pf], (const float*)fine->Qxb[pf], (const float*)fine->Qyb[pf], fine->nx, r,
+                           (float*)coarse->Hb[0], (float*)coarse->Qxb[0], (float*)coarse->Qyb[0], (float*)coarse->Hb[1],
+                           (float*)coarse->Qxb[1], (float*)coarse->Qyb[1], coarse->nx, coarse->ny);
+    else
+        hipLaunchKernelGGL(swe::k_restrict<double>, dim3(grid_for_cells(nc)), dim3(256), 0, fine->stream,
+                           (const double*)fine->Hb[pf], (const double*)fine->Qxb[pf], (const double*)fine->Qyb[pf],
+                           fine->nx, r, (double*)coarse->Hb[0], (double*)coarse->Qxb[0], (double*)coarse->Qyb[0],
+                           (double*)coarse->Hb[1], (double*)coarse->Qxb[1], (double*)coarse->Qyb[1], coarse->nx,
+                           coarse->ny);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(fine->stream));
+    // the coarse clock follows the fine one
+    char* cb = (char*)coarse->ctrl;
+    HIPCHK(hipMemcpyAsync(cb + offsetof(Ctrl, t), &cf.t, sizeof(double), hipMemcpyHostToDevice, coarse->stream));
+    return prepare(coarse);
+}
+
+static int ensure_corr_buffers(swe_t* s) {
+    if (s->corrE) return 0;
+    const size_t n = 3 * (size_t)s->nx * s->ny;
+    HIPCHK(hipMalloc(&s->corrE, n * s->rsize));
+    HIPCHK(hipMalloc(&s->corrN, n * s->rsize));
+    HIPCHK(hipMemsetAsync(s->corrE, 0, n * s->rsize, s->stream));
+    HIPCHK(hipMemsetAsync(s->corrN, 0, n * s->rsize, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    build_args(s);
+    drop_graph(s);
+    return 0;
+}
+
+int swe_set_correction(swe_t* s, const double* dE, const double* dN) {
+    if (!s) { set_err("swe_set_correction: NULL handle"); return SWE_EINVAL; }
+    if (!dE && !dN) {
+        if (s->lc) { set_err("swe_set_correction: a network is attached"); return SWE_EINVAL; }
+        if (s->corr) drop_graph(s);
+        s->corr = false;
+        return 0;
+    }
+    if (!s->L->step_corr) { set_err("swe_set_correction: the tile shape has no correcting step kernel"); return SWE_EINVAL; }
+    if (s->ntap > 0) { set_err("swe_set_correction: not for grids of a nest"); return SWE_EINVAL; }
+    const size_t n = 3 * (size_t)s->nx * s->ny;
+    if (s->lc) { set_err("swe_set_correction: a network is attached (swe_lc_attach(NULL, grid) first)"); return SWE_EINVAL; }
+    int rc = ensure_corr_buffers(s);
+    if (rc) return rc;
+    std::vector<unsigned char> buf(n * s->rsize);
+    const double* src[2] = {dE, dN};
+    void* dst[2] = {s->corrE, s->corrN};
+    for (int q = 0; q < 2; ++q) {
+        for (size_t i = 0; i < n; ++i) {
+            const double v = src[q] ? src[q][i] : 0.0;
+            if (!std::isfinite(v)) { set_err("swe_set_correction: non-finite correction"); return SWE_EINVAL; }
+            if (s->precision == 32) ((float*)buf.data())[i] = (float)v;
+            else ((double*)buf.data())[i] = v;
+        }
+        HIPCHK(hipMemcpyAsync(dst[q], buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (!s->corr) drop_graph(s);
+    s->corr = true;
+    return 0;
 }
 
 }  // extern "C"
@@ -1577,6 +1788,654 @@ int swe_nest_get_patch(swe_nest_t* n, int k, double* H, double* Qx, double* Qy) 
         for (int j = 0; j < nyf; ++j)
             std::memcpy(outs[q] + (size_t)j * nxf, srcs[q]->data() + (size_t)(j + G) * nxe + G, sizeof(double) * nxf);
     }
+    return 0;
+}
+
+}  // extern "C"
+
+// ====================================================================== learned coarse correction
+
+#include "swe_lc.hpp"
+
+struct swe_lc_s {
+    int S = 32, So = 33, max_crops = 0;   // grid tile side; network output side S + 1
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    float in_scale[6], out_scale[6];
+    float* dscale = nullptr;           // device copies: input scales then output scales
+    float* params = nullptr;           // packed FP32 master weights and biases
+    float* grads = nullptr;
+    float* m1 = nullptr;               // Adam moments
+    float* m2 = nullptr;
+    long long adam_t = 0;
+    unsigned short* wf = nullptr;      // bf16 weights [tap][out][in]
+    unsigned short* wb = nullptr;      // bf16 weights [tap][in][out]
+    unsigned short* act[swe::lc::NL] = {};   // layer inputs (bf16)
+    float* out = nullptr;              // last layer output (FP32, 16 channels)
+    unsigned short* g[swe::lc::NL] = {};     // dL/dz of each layer (bf16)
+    float* y = nullptr;                // labels and mask of a training batch
+    float* mask = nullptr;
+    float* part = nullptr;             // weight-gradient partials
+    int part_blocks = 0;
+    double* loss_part = nullptr;
+    int loss_blocks = 0;
+    int last_n = 0;                    // crops of the last forward
+    // training data set on the device: crops, labels, masks, tile indices
+    int cap = 0, count = 0;
+    unsigned short* dX = nullptr;
+    float* dY = nullptr;
+    float* dM = nullptr;
+    int* dT = nullptr;
+    int* dmc = nullptr;                // mask ones per crop (collection scratch)
+    int* idx = nullptr;                // minibatch indices
+    std::vector<int> mcount;           // mask ones per data-set crop (host)
+};
+
+namespace {
+
+namespace L_ = swe::lc;
+
+int lc_in(const swe_lc_t* c, int l) { return c->So + 2 * L_::HALO - 2 * l; }   // input side of layer l
+
+void free_lc(swe_lc_t* c) {
+    void* ptrs[] = {c->params, c->grads, c->m1, c->m2, c->wf, c->wb, c->out, c->y, c->mask, c->part, c->loss_part,
+                    c->dscale, c->dX, c->dY, c->dM, c->dT, c->dmc, c->idx};
+    for (void* q : ptrs) if (q) (void)hipFree(q);
+    for (int l = 0; l < L_::NL; ++l) {
+        if (c->act[l]) (void)hipFree(c->act[l]);
+        if (c->g[l]) (void)hipFree(c->g[l]);
+    }
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+hipError_t lc_pack(swe_lc_t* c) {
+    hipLaunchKernelGGL(L_::k_pack_weights, dim3(64), dim3(256), 0, c->stream, c->params, c->wf, c->wb);
+    return hipGetLastError();
+}
+
+int grid_for(long long items, int per_block) {
+    long long b = (items + per_block - 1) / per_block;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+// Forward over n crops already in act[0]; the count may come from the device.
+hipError_t lc_forward(swe_lc_t* c, int n, const int* cnt_dev, hipStream_t st) {
+    const int S = c->S;
+    // worst-case items for the grid size: n crops x 16-pixel blocks
+    auto items = [&](int l) { const int so = lc_in(c, l) - 2; return (long long)n * ((so * so + 15) / 16); };
+    hipLaunchKernelGGL((L_::k_conv_fwd<16, 32, false>), dim3(grid_for(items(0), 4)), dim3(256), 0, st,
+                       c->act[0], (void*)c->act[1], c->wf + L_::wb_off(0), c->params + L_::p_off(0) + L_::w_count(0),
+                       32, lc_in(c, 0), cnt_dev, n);
+    hipLaunchKernelGGL((L_::k_conv_fwd<32, 32, false>), dim3(grid_for(items(1), 4)), dim3(256), 0, st,
+                       c->act[1], (void*)c->act[2], c->wf + L_::wb_off(1), c->params + L_::p_off(1) + L_::w_count(1),
+                       32, lc_in(c, 1), cnt_dev, n);
+    hipLaunchKernelGGL((L_::k_conv_fwd<32, 32, false>), dim3(grid_for(items(2), 4)), dim3(256), 0, st,
+                       c->act[2], (void*)c->act[3], c->wf + L_::wb_off(2), c->params + L_::p_off(2) + L_::w_count(2),
+                       32, lc_in(c, 2), cnt_dev, n);
+    hipLaunchKernelGGL((L_::k_conv_fwd<32, 16, true>), dim3(grid_for(items(3), 4)), dim3(256), 0, st,
+                       c->act[3], (void*)c->out, c->wf + L_::wb_off(3), c->params + L_::p_off(3) + L_::w_count(3),
+                       6, lc_in(c, 3), cnt_dev, n);
+    (void)S;
+    return hipGetLastError();
+}
+
+// Backward of the last forward (n crops) from g[3] (dL/dz of the last layer),
+// into the packed FP32 gradient.
+hipError_t lc_backward(swe_lc_t* c, int n) {
+    hipError_t e;
+    auto wgrad = [&](int l) -> hipError_t {
+        const int so = lc_in(c, l) - 2;
+        const long long total = (long long)n * so * so;
+        int chunk = (int)((total + c->part_blocks - 1) / c->part_blocks);
+        chunk = (chunk + 15) / 16 * 16;
+        const int nblk = (int)((total + chunk - 1) / chunk);
+        float* gl = c->grads + L_::p_off(l);
+        if (l == 0) {
+            hipLaunchKernelGGL((L_::k_conv_bwd_w<16, 32>), dim3(nblk), dim3(256), 0, c->stream, c->g[0], c->act[0],
+                               c->part, lc_in(c, 0), n, chunk);
+            hipLaunchKernelGGL((L_::k_reduce_w<16, 32>), dim3(32), dim3(256), 0, c->stream, c->part, nblk, gl, 6, 32);
+        } else if (l < 3) {
+            hipLaunchKernelGGL((L_::k_conv_bwd_w<32, 32>), dim3(nblk), dim3(256), 0, c->stream, c->g[l], c->act[l],
+                               c->part, lc_in(c, l), n, chunk);
+            hipLaunchKernelGGL((L_::k_reduce_w<32, 32>), dim3(32), dim3(256), 0, c->stream, c->part, nblk, gl, 32, 32);
+        } else {
+            hipLaunchKernelGGL((L_::k_conv_bwd_w<32, 16>), dim3(nblk), dim3(256), 0, c->stream, c->g[3], c->act[3],
+                               c->part, lc_in(c, 3), n, chunk);
+            hipLaunchKernelGGL((L_::k_reduce_w<32, 16>), dim3(32), dim3(256), 0, c->stream, c->part, nblk, gl, 32, 6);
+        }
+        return hipGetLastError();
+    };
+    auto bdata = [&](int l) -> hipError_t {   // g[l-1] from g[l]
+        const int si = lc_in(c, l);
+        const long long items = (long long)n * ((si * si + 15) / 16);
+        if (l == 3)
+            hipLaunchKernelGGL((L_::k_conv_bwd_data<32, 16>), dim3(grid_for(items, 4)), dim3(256), 0, c->stream,
+                               c->g[3], c->act[3], c->g[2], c->wb + L_::wb_off(3), si, n);
+        else
+            hipLaunchKernelGGL((L_::k_conv_bwd_data<32, 32>), dim3(grid_for(items, 4)), dim3(256), 0, c->stream,
+                               c->g[l], c->act[l], c->g[l - 1], c->wb + L_::wb_off(l), si, n);
+        return hipGetLastError();
+    };
+    for (int l = 3; l >= 0; --l) {
+        if ((e = wgrad(l)) != hipSuccess) return e;
+        if (l > 0 && (e = bdata(l)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Host FP64 crops (n, Sin, Sin, 6) -> bf16 act[0] with 16 channels.
+int lc_upload_crops(swe_lc_t* c, int n, const double* x) {
+    const int si = lc_in(c, 0);
+    const size_t npx = (size_t)n * si * si;
+    std::vector<unsigned short> h(npx * 16, 0);
+    for (size_t p = 0; p < npx; ++p)
+        for (int k = 0; k < 6; ++k) {
+            const float f = (float)x[p * 6 + k];
+            unsigned u;
+            std::memcpy(&u, &f, 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            h[p * 16 + k] = (unsigned short)(u >> 16);
+        }
+    HIPCHK(hipMemcpyAsync(c->act[0], h.data(), h.size() * 2, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_lc_nparams(void) { return L_::NPARAM; }
+
+swe_lc_t* swe_lc_create(int tile, int max_crops, const double* in_scale, const double* out_scale, void* stream) {
+    g_err.clear();
+    if (tile < 1 || tile > 64 || max_crops < 1 || max_crops > (1 << 20) || !in_scale || !out_scale) {
+        set_err("swe_lc_create: need 1 <= tile <= 64, 1 <= max_crops <= 2^20 and both scale vectors");
+        return nullptr;
+    }
+    for (int k = 0; k < 6; ++k)
+        if (!(in_scale[k] > 0.0) || !(out_scale[k] > 0.0) || !std::isfinite(in_scale[k]) ||
+            !std::isfinite(out_scale[k])) {
+            set_err("swe_lc_create: scales must be finite and > 0"); return nullptr;
+        }
+    swe_lc_t* c = new (std::nothrow) swe_lc_s();
+    if (!c) { set_err("swe_lc_create: out of host memory"); return nullptr; }
+    c->S = tile; c->So = tile + 1; c->max_crops = max_crops;
+    for (int k = 0; k < 6; ++k) { c->in_scale[k] = (float)in_scale[k]; c->out_scale[k] = (float)out_scale[k]; }
+#define LK(expr)                                                               \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) { set_hip_err("swe_lc_create", e_); free_lc(c); delete c; return nullptr; } \
+    } while (0)
+    if (stream) c->stream = (hipStream_t)stream;
+    else { LK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
+    LK(hipMalloc((void**)&c->dscale, sizeof(float) * 12));
+    {
+        float sc[12];
+        for (int k = 0; k < 6; ++k) { sc[k] = c->in_scale[k]; sc[6 + k] = c->out_scale[k]; }
+        LK(hipMemcpyAsync(c->dscale, sc, sizeof sc, hipMemcpyHostToDevice, c->stream));
+        LK(hipStreamSynchronize(c->stream));
+    }
+    LK(hipMalloc((void**)&c->params, sizeof(float) * L_::NPARAM));
+    LK(hipMalloc((void**)&c->grads, sizeof(float) * L_::NPARAM));
+    LK(hipMalloc((void**)&c->m1, sizeof(float) * L_::NPARAM));
+    LK(hipMalloc((void**)&c->m2, sizeof(float) * L_::NPARAM));
+    LK(hipMalloc((void**)&c->wf, 2 * L_::NWB));
+    LK(hipMalloc((void**)&c->wb, 2 * L_::NWB));
+    for (int l = 0; l < L_::NL; ++l) {
+        const size_t si = lc_in(c, l), so = si - 2;
+        LK(hipMalloc((void**)&c->act[l], 2 * (size_t)max_crops * si * si * L_::CIN[l]));
+        LK(hipMalloc((void**)&c->g[l], 2 * (size_t)max_crops * so * so * L_::COUT[l]));
+    }
+    LK(hipMalloc((void**)&c->out, sizeof(float) * (size_t)max_crops * c->So * c->So * 16));
+    LK(hipMalloc((void**)&c->y, sizeof(float) * (size_t)max_crops * c->So * c->So * 6));
+    LK(hipMalloc((void**)&c->mask, sizeof(float) * (size_t)max_crops * c->So * c->So * 6));
+    c->part_blocks = 512;
+    LK(hipMalloc((void**)&c->part, sizeof(float) * (size_t)c->part_blocks * (9 * 32 * 32 + 32)));
+    c->loss_blocks = 256;
+    LK(hipMalloc((void**)&c->loss_part, sizeof(double) * c->loss_blocks));
+    LK(hipMemsetAsync(c->params, 0, sizeof(float) * L_::NPARAM, c->stream));
+    LK(hipMemsetAsync(c->m1, 0, sizeof(float) * L_::NPARAM, c->stream));
+    LK(hipMemsetAsync(c->m2, 0, sizeof(float) * L_::NPARAM, c->stream));
+    LK(hipMemsetAsync(c->act[0], 0, 2 * (size_t)max_crops * lc_in(c, 0) * lc_in(c, 0) * 16, c->stream));
+    LK(lc_pack(c));
+    LK(hipStreamSynchronize(c->stream));
+#undef LK
+    return c;
+}
+
+void swe_lc_destroy(swe_lc_t* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_lc(c);
+    delete c;
+}
+
+int swe_lc_set_params(swe_lc_t* c, const double* params) {
+    if (!c || !params) { set_err("swe_lc_set_params: NULL argument"); return SWE_EINVAL; }
+    std::vector<float> h(L_::NPARAM);
+    for (int k = 0; k < L_::NPARAM; ++k) {
+        if (!std::isfinite(params[k])) { set_err("swe_lc_set_params: non-finite parameter"); return SWE_EINVAL; }
+        h[k] = (float)params[k];
+    }
+    HIPCHK(hipMemcpyAsync(c->params, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(c->m1, 0, sizeof(float) * L_::NPARAM, c->stream));
+    HIPCHK(hipMemsetAsync(c->m2, 0, sizeof(float) * L_::NPARAM, c->stream));
+    c->adam_t = 0;
+    HIPCHK(lc_pack(c));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+static int lc_read_floats(swe_lc_t* c, const float* src, double* dst, size_t n) {
+    std::vector<float> h(n);
+    HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < n; ++k) dst[k] = h[k];
+    return 0;
+}
+
+int swe_lc_get_params(swe_lc_t* c, double* params) {
+    if (!c || !params) { set_err("swe_lc_get_params: NULL argument"); return SWE_EINVAL; }
+    return lc_read_floats(c, c->params, params, L_::NPARAM);
+}
+
+int swe_lc_get_grads(swe_lc_t* c, double* grads) {
+    if (!c || !grads) { set_err("swe_lc_get_grads: NULL argument"); return SWE_EINVAL; }
+    return lc_read_floats(c, c->grads, grads, L_::NPARAM);
+}
+
+int swe_lc_forward(swe_lc_t* c, int n, const double* x, double* out) {
+    if (!c || !x || n < 1 || n > c->max_crops) { set_err("swe_lc_forward: invalid arguments"); return SWE_EINVAL; }
+    int rc = lc_upload_crops(c, n, x);
+    if (rc) return rc;
+    HIPCHK(lc_forward(c, n, nullptr, c->stream));
+    c->last_n = n;
+    if (out) {
+        const size_t np = (size_t)n * c->So * c->So;
+        std::vector<float> h(np * 16);
+        HIPCHK(hipMemcpyAsync(h.data(), c->out, sizeof(float) * h.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t p = 0; p < np; ++p)
+            for (int k = 0; k < 6; ++k) out[p * 6 + k] = h[p * 16 + k];
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int swe_lc_get_layer(swe_lc_t* c, int which, double* out) {
+    if (!c || !out || which < 0 || which >= 2 * L_::NL || c->last_n < 1) {
+        set_err("swe_lc_get_layer: invalid arguments or no forward yet"); return SWE_EINVAL;
+    }
+    const int l = which % L_::NL;
+    const bool grad = which >= L_::NL;
+    const int side = grad ? lc_in(c, l) - 2 : lc_in(c, l);
+    const int C = grad ? L_::COUT[l] : L_::CIN[l];
+    const int Creal = grad ? L_::COUT_REAL[l] : L_::CIN_REAL[l];
+    const size_t np = (size_t)c->last_n * side * side;
+    std::vector<unsigned short> h(np * C);
+    HIPCHK(hipMemcpyAsync(h.data(), grad ? c->g[l] : c->act[l], 2 * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t p = 0; p < np; ++p)
+        for (int k = 0; k < Creal; ++k) {
+            const unsigned u = (unsigned)h[p * C + k] << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            out[p * Creal + k] = f;
+        }
+    return 0;
+}
+
+int swe_lc_train_step(swe_lc_t* c, int n, const double* x, const double* y, const double* mask, double lr,
+                      double* loss) {
+    if (!c || !x || !y || !mask || n < 1 || n > c->max_crops || !(lr >= 0.0)) {
+        set_err("swe_lc_train_step: invalid arguments"); return SWE_EINVAL;
+    }
+    int rc = lc_upload_crops(c, n, x);
+    if (rc) return rc;
+    const size_t np = (size_t)n * c->So * c->So;
+    std::vector<float> hy(np * 6), hm(np * 6);
+    double cnt = 0.0;
+    for (size_t k = 0; k < np * 6; ++k) { hy[k] = (float)y[k]; hm[k] = (float)mask[k]; cnt += mask[k]; }
+    HIPCHK(hipMemcpyAsync(c->y, hy.data(), sizeof(float) * hy.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->mask, hm.data(), sizeof(float) * hm.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(lc_forward(c, n, nullptr, c->stream));
+    c->last_n = n;
+    const float inv = (float)(1.0 / (cnt > 1.0 ? cnt : 1.0));
+    hipLaunchKernelGGL(L_::k_loss, dim3(c->loss_blocks), dim3(256), 0, c->stream, c->out, c->y, c->mask, c->g[3],
+                       (int)np, inv, c->loss_part);
+    HIPCHK(hipGetLastError());
+    HIPCHK(lc_backward(c, n));
+    if (lr > 0.0) {
+        c->adam_t++;
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = (float)(1.0 - std::pow(b1, (double)c->adam_t));
+        const float c2 = (float)(1.0 - std::pow(b2, (double)c->adam_t));
+        hipLaunchKernelGGL(L_::k_adam, dim3(64), dim3(256), 0, c->stream, c->params, c->grads, c->m1, c->m2,
+                           L_::NPARAM, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+        HIPCHK(hipGetLastError());
+        HIPCHK(lc_pack(c));
+    }
+    if (loss) {
+        std::vector<double> lp(c->loss_blocks);
+        HIPCHK(hipMemcpyAsync(lp.data(), c->loss_part, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double s = 0.0;
+        for (double v : lp) s += v;
+        *loss = s;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Before each step of a grid with an attached network: crops of the active
+// tiles from the current layer, the network, the corrections of those tiles.
+template <typename real>
+hipError_t lc_pre_step_t(swe_t* s, int par) {
+    swe_lc_t* c = s->lc;
+    const Args<real>& a = *(const Args<real>*)s->args[par].data();
+    const int S = c->S, So = c->So, Sin = So + 2 * L_::HALO;
+    const int slot = par;
+    const int* cnt = s->p.skip_dry ? &s->ctrl->seg_off[slot][swe::NSEG] : nullptr;
+    const int nmax = s->ntiles;
+    hipLaunchKernelGGL(L_::k_gather<real>, dim3(grid_for((long long)nmax * Sin * Sin, 256)), dim3(256), 0, s->stream,
+                       a, slot, S, c->dscale, c->act[0], (int*)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = lc_forward(c, nmax, cnt, s->stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(L_::k_scatter<real>, dim3(grid_for((long long)nmax * So * So, 256)), dim3(256), 0, s->stream, a,
+                       slot, S, c->dscale + 6, c->out, (real*)s->corrE, (real*)s->corrN);
+    return hipGetLastError();
+}
+
+hipError_t lc_pre_step(swe_t* s, int par) {
+    return s->precision == 32 ? lc_pre_step_t<float>(s, par) : lc_pre_step_t<double>(s, par);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_lc_attach(swe_lc_t* c, swe_t* s) {
+    if (!s) { set_err("swe_lc_attach: NULL grid"); return SWE_EINVAL; }
+    if (!c) {
+        if (s->lc) drop_graph(s);
+        s->lc = nullptr;
+        s->pre_step = nullptr;
+        s->corr = false;
+        return 0;
+    }
+    if (s->L->tx != c->S || s->L->ty != c->S) { set_err("swe_lc_attach: the network's tile differs from the grid's"); return SWE_EINVAL; }
+    if (c->max_crops < s->ntiles) { set_err("swe_lc_attach: the network has fewer crop buffers than the grid has tiles"); return SWE_EINVAL; }
+    if (!s->L->step_corr || s->ntap > 0) { set_err("swe_lc_attach: grid cannot take corrections"); return SWE_EINVAL; }
+    // the network's kernels for this grid run on the grid's stream
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int rc = ensure_corr_buffers(s);
+    if (rc) return rc;
+    drop_graph(s);
+    s->lc = c;
+    s->pre_step = lc_pre_step;
+    s->corr = true;
+    return 0;
+}
+
+int swe_lc_gather(swe_lc_t* c, swe_t* s, double* x, int* tiles) {
+    if (!c || !s || !x) { set_err("swe_lc_gather: NULL argument"); return SWE_EINVAL; }
+    if (s->L->tx != c->S || s->L->ty != c->S || c->max_crops < s->ntiles) {
+        set_err("swe_lc_gather: network and grid do not fit together"); return SWE_EINVAL;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Ctrl ct;
+    int rc = sync_ctrl(s, &ct);
+    if (rc) return rc;
+    const int par = (int)(s->launched & 1);
+    const int n = s->p.skip_dry ? ct.seg_off[par][swe::NSEG] : s->ntiles;
+    const int Sin = c->So + 2 * L_::HALO;
+    if (s->precision == 32)
+        hipLaunchKernelGGL(L_::k_gather<float>, dim3(grid_for((long long)s->ntiles * Sin * Sin, 256)), dim3(256), 0,
+                           s->stream, *(const Args<float>*)s->args[par].data(), par, c->S, c->dscale, c->act[0],
+                           (int*)nullptr);
+    else
+        hipLaunchKernelGGL(L_::k_gather<double>, dim3(grid_for((long long)s->ntiles * Sin * Sin, 256)), dim3(256), 0,
+                           s->stream, *(const Args<double>*)s->args[par].data(), par, c->S, c->dscale, c->act[0],
+                           (int*)nullptr);
+    HIPCHK(hipGetLastError());
+    const size_t np = (size_t)n * Sin * Sin;
+    std::vector<unsigned short> h(np * 16);
+    HIPCHK(hipMemcpyAsync(h.data(), c->act[0], 2 * h.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t p = 0; p < np; ++p)
+        for (int k = 0; k < 6; ++k) {
+            const unsigned u = (unsigned)h[p * 16 + k] << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            x[p * 6 + k] = f;
+        }
+    if (tiles) {
+        if (!s->p.skip_dry) {
+            for (int k = 0; k < n; ++k) tiles[k] = k;
+        } else {
+            int got = 0;
+            for (int g = 0; g < swe::NSEG; ++g) {
+                const int m = ct.seg_off[par][g + 1] - ct.seg_off[par][g];
+                if (m <= 0) continue;
+                HIPCHK(hipMemcpyAsync(tiles + got, s->lists + ((size_t)par * swe::NSEG + g) * s->ntiles,
+                                      sizeof(int) * m, hipMemcpyDeviceToHost, s->stream));
+                got += m;
+            }
+            HIPCHK(hipStreamSynchronize(s->stream));
+            for (int k = 0; k < n; ++k) tiles[k] = swe::entry_tile(tiles[k]);
+        }
+    }
+    return n;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One optimisation step on the crops already in act[0], y and mask.
+int lc_opt_step(swe_lc_t* c, int n, double cnt, double lr, double* loss) {
+    HIPCHK(lc_forward(c, n, nullptr, c->stream));
+    c->last_n = n;
+    const size_t np = (size_t)n * c->So * c->So;
+    const float inv = (float)(1.0 / (cnt > 1.0 ? cnt : 1.0));
+    hipLaunchKernelGGL(L_::k_loss, dim3(c->loss_blocks), dim3(256), 0, c->stream, c->out, c->y, c->mask, c->g[3],
+                       (int)np, inv, c->loss_part);
+    HIPCHK(hipGetLastError());
+    HIPCHK(lc_backward(c, n));
+    if (lr > 0.0) {
+        c->adam_t++;
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = (float)(1.0 - std::pow(b1, (double)c->adam_t));
+        const float c2 = (float)(1.0 - std::pow(b2, (double)c->adam_t));
+        hipLaunchKernelGGL(L_::k_adam, dim3(64), dim3(256), 0, c->stream, c->params, c->grads, c->m1, c->m2,
+                           L_::NPARAM, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+        HIPCHK(hipGetLastError());
+        HIPCHK(lc_pack(c));
+    }
+    if (loss) {
+        std::vector<double> lp(c->loss_blocks);
+        HIPCHK(hipMemcpyAsync(lp.data(), c->loss_part, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double sum = 0.0;
+        for (double v : lp) sum += v;
+        *loss = sum;
+    }
+    return 0;
+}
+
+template <typename real>
+int lc_collect_t(swe_lc_t* c, swe_t* f, swe_t* g, int r, double tau_c, int n) {
+    const int S = c->S, So = c->So;
+    const double inv = 1.0 / tau_c;
+    hipLaunchKernelGGL(L_::k_labels<real>, dim3(grid_for_cells((long long)n * So * So)), dim3(256), 0, c->stream,
+                       c->dT + c->count, n, S, g->ntx, g->nx, g->ny, r, (const real*)f->tapx, (const real*)f->tapy,
+                       (const real*)g->tapx, (const real*)g->tapy, inv, c->dscale + 6,
+                       c->dY + (size_t)c->count * So * So * 6, c->dM + (size_t)c->count * So * So * 6, c->dmc);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_lc_data(swe_lc_t* c, int capacity) {
+    if (!c || capacity < 1) { set_err("swe_lc_data: invalid arguments"); return SWE_EINVAL; }
+    void* old[] = {c->dX, c->dY, c->dM, c->dT, c->dmc, c->idx};
+    for (void* q : old) if (q) (void)hipFree(q);
+    const int So = c->So, Sin = So + 2 * L_::HALO;
+    c->cap = capacity;
+    c->count = 0;
+    c->mcount.clear();
+    HIPCHK(hipMalloc((void**)&c->dX, 2 * (size_t)capacity * Sin * Sin * 16));
+    HIPCHK(hipMalloc((void**)&c->dY, sizeof(float) * (size_t)capacity * So * So * 6));
+    HIPCHK(hipMalloc((void**)&c->dM, sizeof(float) * (size_t)capacity * So * So * 6));
+    HIPCHK(hipMalloc((void**)&c->dT, sizeof(int) * (size_t)capacity));
+    HIPCHK(hipMalloc((void**)&c->dmc, sizeof(int) * (size_t)capacity));
+    HIPCHK(hipMalloc((void**)&c->idx, sizeof(int) * (size_t)c->max_crops));
+    HIPCHK(hipMemsetAsync(c->dX, 0, 2 * (size_t)capacity * Sin * Sin * 16, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int swe_lc_data_count(swe_lc_t* c) { return c ? c->count : -1; }
+
+int swe_lc_collect(swe_lc_t* c, swe_t* f, swe_t* g, int r, int m, double* tau_out) {
+    if (!c || !f || !g || r < 1 || m < 1 || !c->dX) { set_err("swe_lc_collect: invalid arguments or no data set"); return SWE_EINVAL; }
+    if (f->tap_r != r || g->tap_r != 1 || f->precision != g->precision || g->L->tx != c->S || g->L->ty != c->S ||
+        c->max_crops < g->ntiles) {
+        set_err("swe_lc_collect: fine grid needs line taps r, coarse grid line taps 1, tiles of the network's size");
+        return SWE_EINVAL;
+    }
+    int rc = swe_restrict(f, g, r);   // coarse layer = restricted fine layer, CFL step recorded
+    if (rc) return rc;
+    Ctrl cf, cg;
+    if ((rc = sync_ctrl(f, &cf)) || (rc = sync_ctrl(g, &cg))) return rc;
+    double tau_c = std::fmin(cg.tau_cfl, (double)m * cf.tau_cfl);
+    if (!(tau_c > 0.0) || !std::isfinite(tau_c)) { set_err("swe_lc_collect: no finite time step"); return SWE_EDTCOLLAPSE; }
+    const double tau_f = g->precision == 32 ? (double)(float)(tau_c / m) : tau_c / m;
+    tau_c = tau_f * m;
+    // crops of the restricted layer
+    const int parg = (int)(g->launched & 1);
+    const int n = g->p.skip_dry ? cg.seg_off[parg][swe::NSEG] : g->ntiles;
+    if (n == 0) { if (tau_out) *tau_out = 0.0; return 0; }
+    if (c->count + n > c->cap) { set_err("swe_lc_collect: data set full"); return SWE_ENOMEM; }
+    const int S = c->S, Sin = c->So + 2 * L_::HALO;
+    unsigned short* xo = c->dX + (size_t)c->count * Sin * Sin * 16;
+    if (g->precision == 32)
+        hipLaunchKernelGGL(L_::k_gather<float>, dim3(grid_for_cells((long long)n * Sin * Sin)), dim3(256), 0, g->stream,
+                           *(const Args<float>*)g->args[parg].data(), parg, S, c->dscale, xo, c->dT + c->count);
+    else
+        hipLaunchKernelGGL(L_::k_gather<double>, dim3(grid_for_cells((long long)n * Sin * Sin)), dim3(256), 0,
+                           g->stream, *(const Args<double>*)g->args[parg].data(), parg, S, c->dscale, xo,
+                           c->dT + c->count);
+    HIPCHK(hipGetLastError());
+    // one coarse step and m fine steps of the same interval, line taps on
+    if ((rc = swe_hold_dt(g, tau_c)) || (rc = swe_zero_line_taps(g)) || (rc = launch_steps(g, 1)) ||
+        (rc = finish(g)))
+        return rc;
+    if ((rc = swe_hold_dt(f, tau_f)) || (rc = swe_zero_line_taps(f)) || (rc = launch_steps(f, m)) ||
+        (rc = finish(f)) || (rc = swe_hold_dt(f, 0.0)))
+        return rc;
+    HIPCHK(hipMemsetAsync(c->dmc, 0, sizeof(int) * n, c->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    rc = g->precision == 32 ? lc_collect_t<float>(c, f, g, r, tau_c, n) : lc_collect_t<double>(c, f, g, r, tau_c, n);
+    if (rc) return rc;
+    std::vector<int> mc(n);
+    HIPCHK(hipMemcpyAsync(mc.data(), c->dmc, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->mcount.insert(c->mcount.end(), mc.begin(), mc.end());
+    c->count += n;
+    if (tau_out) *tau_out = tau_c;
+    return 0;
+}
+
+int swe_lc_get_data(swe_lc_t* c, int first, int n, double* x, double* y, double* mask, int* tiles) {
+    if (!c || first < 0 || n < 0 || first + n > c->count) { set_err("swe_lc_get_data: invalid range"); return SWE_EINVAL; }
+    const int So = c->So, Sin = So + 2 * L_::HALO;
+    if (x) {
+        std::vector<unsigned short> h((size_t)n * Sin * Sin * 16);
+        HIPCHK(hipMemcpyAsync(h.data(), c->dX + (size_t)first * Sin * Sin * 16, 2 * h.size(), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t p = 0; p < (size_t)n * Sin * Sin; ++p)
+            for (int k = 0; k < 6; ++k) {
+                const unsigned u = (unsigned)h[p * 16 + k] << 16;
+                float fl;
+                std::memcpy(&fl, &u, 4);
+                x[p * 6 + k] = fl;
+            }
+    }
+    float* srcs[2] = {c->dY, c->dM};
+    double* outs[2] = {y, mask};
+    for (int q = 0; q < 2; ++q) {
+        if (!outs[q]) continue;
+        int rc = lc_read_floats(c, srcs[q] + (size_t)first * So * So * 6, outs[q], (size_t)n * So * So * 6);
+        if (rc) return rc;
+    }
+    if (tiles) {
+        HIPCHK(hipMemcpyAsync(tiles, c->dT + first, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return 0;
+}
+
+int swe_lc_fit(swe_lc_t* c, int iters, int batch, double lr, unsigned long long seed, double* losses) {
+    if (!c || iters < 0 || batch < 1 || batch > c->max_crops || !(lr > 0.0) || c->count < 1) {
+        set_err("swe_lc_fit: invalid arguments or empty data set"); return SWE_EINVAL;
+    }
+    const int So = c->So;
+    const int nb = batch < c->count ? batch : c->count;
+    std::vector<int> perm(c->count), pick(nb);
+    for (int k = 0; k < c->count; ++k) perm[k] = k;
+    unsigned long long st = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto next = [&]() {   // 64-bit LCG (Knuth's MMIX constants), upper bits
+        st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+        return (unsigned)(st >> 33);
+    };
+    for (int it = 0; it < iters; ++it) {
+        // partial Fisher-Yates: nb distinct crops
+        double cnt = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const int j = b + (int)(next() % (unsigned)(c->count - b));
+            std::swap(perm[b], perm[j]);
+            pick[b] = perm[b];
+            cnt += c->mcount[perm[b]];
+        }
+        HIPCHK(hipMemcpyAsync(c->idx, pick.data(), sizeof(int) * nb, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(L_::k_batch_copy, dim3(2048), dim3(256), 0, c->stream, c->idx, nb, So, c->dX, c->dY, c->dM,
+                           c->act[0], c->y, c->mask);
+        HIPCHK(hipGetLastError());
+        int rc = lc_opt_step(c, nb, cnt, lr, losses ? &losses[it] : nullptr);
+        if (rc) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int swe_lc_set_out_scale(swe_lc_t* c, const double* out_scale) {
+    if (!c || !out_scale) { set_err("swe_lc_set_out_scale: NULL argument"); return SWE_EINVAL; }
+    float ratio[6];
+    for (int k = 0; k < 6; ++k) {
+        if (!(out_scale[k] > 0.0) || !std::isfinite(out_scale[k])) { set_err("swe_lc_set_out_scale: scales must be > 0"); return SWE_EINVAL; }
+        ratio[k] = (float)(c->out_scale[k] / out_scale[k]);
+        c->out_scale[k] = (float)out_scale[k];
+    }
+    HIPCHK(hipMemcpyAsync(c->dscale + 6, c->out_scale, sizeof(float) * 6, hipMemcpyHostToDevice, c->stream));
+    if (c->count > 0) {
+        float* dr = c->out + 0;   // scratch: the output buffer holds at least 6 floats
+        HIPCHK(hipMemcpyAsync(dr, ratio, sizeof ratio, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(L_::k_rescale, dim3(2048), dim3(256), 0, c->stream, c->dY,
+                           (size_t)c->count * c->So * c->So * 6, (const float*)dr);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
 

@@ -1,0 +1,464 @@
+// swe_lc.hpp -- gfx950 kernels of the learned coarse-grid flux correction.
+//
+// A small convolutional network (four 3x3 valid convolutions, 6 -> 32 -> 32
+// -> 32 -> 6 channels, tanh after the first three) reads the state of a
+// coarse grid and predicts corrections of the stage III face fluxes (Sec. 2.3
+// of arXiv 1705.00614; the learned part is an addition of this build, the
+// paper has none).  The network runs on crops: for an active S x S tile the
+// (S+9)^2 window round the tile and the cell row and column before it
+// (mirrored at walls) gives the (S+1)^2 corrections of those cells, so that
+// the tile's west and south boundary faces (east and north faces of the
+// neighbours' cells) are always fresh.
+//
+// Layouts: activations bf16, [crop][y][x][C] with C = 16 (the 6 features,
+// zero padded) or 32; weights bf16 as [tap][out][in] (forward) and
+// [tap][in][out] (backward data), both padded to multiples of 16; FP32 master
+// weights, gradients and Adam moments in the packed order (W[out][in][3][3],
+// then b[out]) per layer.  Every contraction is a 16x16x16 bf16 MFMA with
+// FP32 accumulation: a wave owns 16 consecutive pixels (M) of one crop and
+// all output channels (N tiles of 16), the reduction (K) runs over the 9 taps
+// times the input channels in chunks of 16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swe {
+namespace lc {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NL = 4;                         // layers
+constexpr int HALO = NL;                      // crop margin
+constexpr int CIN[NL] = {16, 32, 32, 32};     // padded input channels
+constexpr int COUT[NL] = {32, 32, 32, 16};    // padded output channels
+constexpr int CIN_REAL[NL] = {6, 32, 32, 32};
+constexpr int COUT_REAL[NL] = {32, 32, 32, 6};
+
+// packed FP32 parameter offsets of layer l: W then b
+__host__ __device__ constexpr int w_count(int l) { return COUT_REAL[l] * CIN_REAL[l] * 9; }
+__host__ __device__ constexpr int p_off(int l) {
+    return l == 0 ? 0 : p_off(l - 1) + w_count(l - 1) + COUT_REAL[l - 1];
+}
+constexpr int NPARAM = p_off(NL);
+// bf16 weight copies: [tap][COUT][CIN] per layer
+__host__ __device__ constexpr int wb_count(int l) { return 9 * COUT[l] * CIN[l]; }
+__host__ __device__ constexpr int wb_off(int l) { return l == 0 ? 0 : wb_off(l - 1) + wb_count(l - 1); }
+constexpr int NWB = wb_off(NL);
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ bf16x4 load4(const unsigned short* p) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    bf16x4 r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// Number of crops: from the device (active tiles of a grid) or the host.
+__device__ __forceinline__ int crop_count(const int* dev, int host) { return dev ? *dev : host; }
+
+// ------------------------------------------------------------------ forward
+// y = act(conv3x3_valid(x) + b); x [n][Sin][Sin][CI] bf16, y [n][Sout][Sout][CO]
+// (bf16 with tanh, or FP32 linear for the last layer).
+template <int CI, int CO, bool LAST>
+__global__ __launch_bounds__(256) void k_conv_fwd(const unsigned short* __restrict__ x, void* __restrict__ y,
+                                                   const unsigned short* __restrict__ wf, const float* __restrict__ bias,
+                                                   int cob, int Sin, const int* cnt_dev, int cnt_host) {
+    constexpr int NT = CO / 16;
+    const int Sout = Sin - 2, P = Sout * Sout, blocks = (P + 15) / 16;
+    const int n = crop_count(cnt_dev, cnt_host);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    for (int item = blockIdx.x * 4 + wv; item < n * blocks; item += gridDim.x * 4) {
+        const int c = item / blocks, p0 = (item % blocks) * 16;
+        const int p = min(p0 + m, P - 1);
+        const int oy = p / Sout, ox = p % Sout;
+        const unsigned short* xc = x + (size_t)c * Sin * Sin * CI;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            const unsigned short* xp = xc + ((oy + dy) * Sin + ox + dx) * CI + 4 * kq;
+#pragma unroll
+            for (int c0 = 0; c0 < CI; c0 += 16) {
+                const bf16x4 a = load4(xp + c0);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const bf16x4 b = load4(wf + (tap * CO + t * 16 + m) * CI + c0 + 4 * kq);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        // lane holds rows (pixels) p0 + 4*kq + i, column (channel) t*16 + m
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int ch = t * 16 + m;
+            const float bb = ch < cob ? bias[ch] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pp = p0 + 4 * kq + i;
+                if (pp >= P) continue;
+                const float v = acc[t][i] + bb;
+                const size_t o = ((size_t)c * P + pp) * CO + ch;
+                if constexpr (LAST) static_cast<float*>(y)[o] = ch < cob ? v : 0.f;
+                else static_cast<unsigned short*>(y)[o] = to_bf16(tanhf(v));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward data
+// g_in = bf16(dL/da_in * (1 - a_in^2)) from g = dL/dz of this layer:
+// dL/da_in[q] = sum_{tap, co} g[q - tap][co] w[co][ci][tap] (zero outside the
+// output plane).  a_in and g_in: [n][Sin][Sin][CI]; g: [n][Sout][Sout][CO].
+template <int CI, int CO>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const unsigned short* __restrict__ g,
+                                                        const unsigned short* __restrict__ a_in,
+                                                        unsigned short* __restrict__ g_in,
+                                                        const unsigned short* __restrict__ wb, int Sin, int n) {
+    constexpr int NT = CI / 16;
+    const int Sout = Sin - 2, P = Sin * Sin, blocks = (P + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    for (int item = blockIdx.x * 4 + wv; item < n * blocks; item += gridDim.x * 4) {
+        const int c = item / blocks, p0 = (item % blocks) * 16;
+        const int p = min(p0 + m, P - 1);
+        const int qy = p / Sin, qx = p % Sin;
+        const unsigned short* gc = g + (size_t)c * Sout * Sout * CO;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int oy = qy - tap / 3, ox = qx - tap % 3;
+            const bool in = oy >= 0 && oy < Sout && ox >= 0 && ox < Sout;
+            const unsigned short* gp = gc + ((in ? oy : 0) * Sout + (in ? ox : 0)) * CO + 4 * kq;
+#pragma unroll
+            for (int c0 = 0; c0 < CO; c0 += 16) {
+                bf16x4 a = load4(gp + c0);
+                if (!in) a = bf16x4{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const bf16x4 b = load4(wb + (tap * CI + t * 16 + m) * CO + c0 + 4 * kq);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int ch = t * 16 + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pp = p0 + 4 * kq + i;
+                if (pp >= P) continue;
+                const size_t o = ((size_t)c * P + pp) * CI + ch;
+                const float a = from_bf16(a_in[o]);
+                g_in[o] = to_bf16(acc[t][i] * (1.f - a * a));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward weights
+// Partial weight and bias gradients of one pixel chunk per block:
+// dW[tap][co][ci] = sum_p g[p][co] a_in[p + tap][ci], db[co] = sum_p g[p][co].
+// The 9 x (CO/16) x (CI/16) output tiles are dealt round-robin to the 4
+// waves; part[block] holds [tap][CO][CI] then [CO] in FP32.
+template <int CI, int CO>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const unsigned short* __restrict__ g,
+                                                     const unsigned short* __restrict__ a_in,
+                                                     float* __restrict__ part, int Sin, int n, int chunk) {
+    constexpr int TCO = CO / 16, TCI = CI / 16, NTILE = 9 * TCO * TCI, PER = (NTILE + 3) / 4;
+    const int Sout = Sin - 2, P = Sout * Sout, total = n * P;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int q0 = blockIdx.x * chunk, q1 = min(total, q0 + chunk);
+    f32x4 acc[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = q0; k0 < q1; k0 += 16) {
+        // K index: pixels k0 + 4*kq + i of the flattened (crop, pixel) range
+        int cc[4], py[4], px[4];
+        bool ok[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = k0 + 4 * kq + i;
+            ok[i] = q < q1;
+            const int qq = ok[i] ? q : q0;
+            cc[i] = qq / P;
+            const int p = qq % P;
+            py[i] = p / Sout;
+            px[i] = p % Sout;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int tile = wv + 4 * j;
+            if (tile >= NTILE) break;
+            const int tap = tile / (TCO * TCI), to = (tile / TCI) % TCO, ti = tile % TCI;
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x4 a, b;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const size_t go = (((size_t)cc[i] * Sout + py[i]) * Sout + px[i]) * CO + to * 16 + m;
+                const size_t ao = (((size_t)cc[i] * Sin + py[i] + dy) * Sin + px[i] + dx) * CI + ti * 16 + m;
+                a[i] = ok[i] ? (short)g[go] : (short)0;
+                b[i] = ok[i] ? (short)a_in[ao] : (short)0;
+            }
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+    }
+    float* out = part + (size_t)blockIdx.x * (9 * CO * CI + CO);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int tile = wv + 4 * j;
+        if (tile >= NTILE) break;
+        const int tap = tile / (TCO * TCI), to = (tile / TCI) % TCO, ti = tile % TCI;
+        // lane holds rows (co) to*16 + 4*kq + i, column (ci) ti*16 + m
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[(tap * CO + to * 16 + 4 * kq + i) * CI + ti * 16 + m] = acc[j][i];
+    }
+    // bias: thread t < CO sums its channel over the chunk
+    if (threadIdx.x < CO) {
+        float s = 0.f;
+        for (int q = q0; q < q1; ++q) s += from_bf16(g[(size_t)q * CO + threadIdx.x]);
+        out[9 * CO * CI + threadIdx.x] = s;
+    }
+}
+
+// Sum the block partials (fixed order) into the packed FP32 gradient of a layer.
+template <int CI, int CO>
+__global__ void k_reduce_w(const float* __restrict__ part, int nblk, float* __restrict__ grad, int ci_real, int co_real) {
+    const int per = 9 * CO * CI + CO;
+    const int wc = co_real * ci_real * 9;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < wc + co_real; k += gridDim.x * blockDim.x) {
+        int src;
+        if (k < wc) {
+            const int co = k / (ci_real * 9), ci = (k / 9) % ci_real, tap = k % 9;
+            src = (tap * CO + co) * CI + ci;
+        } else {
+            src = 9 * CO * CI + (k - wc);
+        }
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * per + src];
+        grad[k] = s;
+    }
+}
+
+// ------------------------------------------------------------------ parameters
+// bf16 copies of the packed FP32 weights in both layouts (zero padding).
+__global__ void k_pack_weights(const float* __restrict__ params, unsigned short* __restrict__ wf,
+                               unsigned short* __restrict__ wb) {
+    for (int l = 0; l < NL; ++l) {
+        const int ci_p = CIN[l], co_p = COUT[l], cir = CIN_REAL[l], cor = COUT_REAL[l];
+        const float* W = params + p_off(l);
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 9 * co_p * ci_p; k += gridDim.x * blockDim.x) {
+            const int tap = k / (co_p * ci_p), co = (k / ci_p) % co_p, ci = k % ci_p;
+            const float v = (co < cor && ci < cir) ? W[(co * cir + ci) * 9 + tap] : 0.f;
+            const unsigned short h = to_bf16(v);
+            wf[wb_off(l) + (tap * co_p + co) * ci_p + ci] = h;
+            wb[wb_off(l) + (tap * ci_p + ci) * co_p + co] = h;
+        }
+    }
+}
+
+// Adam (bias-corrected) on the packed FP32 parameters.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const float gk = g[k];
+        const float mk = b1 * m[k] + (1.f - b1) * gk;
+        const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+        m[k] = mk;
+        v[k] = vk;
+        p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    }
+}
+
+// ------------------------------------------------------------------ loss
+// g = bf16(mask (out - y) / count) for the 6 real channels (zero padding to
+// 16); per-block loss partials 1/2 sum mask (out - y)^2 / count.
+__global__ void k_loss(const float* __restrict__ out, const float* __restrict__ y, const float* __restrict__ mask,
+                       unsigned short* __restrict__ g, int npix, float inv_count, double* __restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npix * 16; k += gridDim.x * blockDim.x) {
+        const int p = k / 16, ch = k % 16;
+        float gv = 0.f;
+        if (ch < 6) {
+            const float d = out[k] - y[p * 6 + ch];
+            const float mk = mask[p * 6 + ch];
+            gv = mk * d * inv_count;
+            s += 0.5 * (double)(mk * d * d) * (double)inv_count;
+        }
+        g[k] = to_bf16(gv);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+}  // namespace lc
+}  // namespace swe
+
+// ------------------------------------------------------------------ coarse grid I/O
+// These need the step kernel's argument block and tile list.
+#include "swe_step.hpp"
+
+namespace swe {
+namespace lc {
+
+// Crop p of the grid's current tile list (all tiles when the grid does not
+// skip dry tiles).
+template <typename real>
+__device__ __forceinline__ int crop_tile(const Args<real>& a, int slot, int p) {
+    return a.skip ? entry_tile(list_entry(a.ctrl, a.lists, a.ntiles, slot, p)) : p;
+}
+
+// Input crops of the active tiles: the six features of every cell of each
+// (S+9)^2 window (mirrored at walls), divided by the input scales, as bf16.
+template <typename real>
+__global__ void k_gather(Args<real> a, int slot, int S, const float* __restrict__ iscale, unsigned short* __restrict__ x,
+                         int* __restrict__ tiles_out) {
+    const int Sin = S + 1 + 2 * HALO, P = Sin * Sin;
+    const int n = a.skip ? a.ctrl->seg_off[slot][NSEG] : a.ntiles;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n * P; k += gridDim.x * blockDim.x) {
+        const int p = k / P, q = k % P;
+        const int tile = crop_tile(a, slot, p);
+        if (tiles_out && q == 0) tiles_out[p] = tile;
+        const int tx = tile % a.ntx, ty = tile / a.ntx;
+        int fx = 0, fy = 0;
+        const int gx = mirror(tx * S - 1 - HALO + q % Sin, a.nx, fx), gy = mirror(ty * S - 1 - HALO + q / Sin, a.ny, fy);
+        const int gi = gy * a.nx + gx;
+        const real H = a.Hi[gi];
+        const bool w = H > a.eps;
+        float f[6];
+        f[0] = (float)H;
+        f[1] = w ? (float)(a.Qxi[gi] / H) : 0.f;
+        f[2] = w ? (float)(a.Qyi[gi] / H) : 0.f;
+        f[3] = (float)a.bed[gi];
+        f[4] = sqrtf((float)a.cf[gi] / (float)a.g_d);
+        f[5] = w ? 1.f : 0.f;
+        unsigned short* o = x + (size_t)k * 16;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = to_bf16(f[c] / iscale[c]);
+    }
+}
+
+// Corrections of the active tiles' cells and of the cell row and column
+// before each tile, from the network output.  A cell shared by two active
+// crops gets the same value from both (same inputs, same summation order).
+template <typename real>
+__global__ void k_scatter(Args<real> a, int slot, int S, const float* __restrict__ oscale, const float* __restrict__ out,
+                          real* __restrict__ corrE, real* __restrict__ corrN) {
+    const int So = S + 1, P = So * So, nc = a.nx * a.ny;
+    const int n = a.skip ? a.ctrl->seg_off[slot][NSEG] : a.ntiles;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n * P; k += gridDim.x * blockDim.x) {
+        const int p = k / P, q = k % P;
+        const int tile = crop_tile(a, slot, p);
+        const int gx = (tile % a.ntx) * S - 1 + q % So, gy = (tile / a.ntx) * S - 1 + q / So;
+        if (gx < 0 || gy < 0 || gx >= a.nx || gy >= a.ny) continue;
+        const int gi = gy * a.nx + gx;
+        const float* o = out + (size_t)k * 16;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            corrE[c * nc + gi] = (real)(o[c] * oscale[c]);
+            corrN[c * nc + gi] = (real)(o[3 + c] * oscale[3 + c]);
+        }
+    }
+}
+
+// Training labels of n crops (coarse tiles tiles[p], (S+1)^2 cells from the
+// row and column before the tile): the correction that
+// makes each coarse face carry the fine solution's flux over one coarse step,
+// (mean of the r fine line taps through the face - the coarse tap) / tau_c,
+// divided by the output scales; mask 1 on interior faces of in-domain cells.
+// Fine taps: ftx [3][r*ny][nx+1], fty [3][ny+1][r*nx]; coarse taps (r = 1):
+// ctx [3][ny][nx+1], cty [3][ny+1][nx] (planes mass, normal, tangential).
+template <typename real>
+__global__ void k_labels(const int* __restrict__ tiles, int n, int S, int ntx, int nx, int ny, int r,
+                         const real* __restrict__ ftx, const real* __restrict__ fty, const real* __restrict__ ctx,
+                         const real* __restrict__ cty, double inv_tau, const float* __restrict__ oscale,
+                         float* __restrict__ y, float* __restrict__ mask, int* __restrict__ mcount) {
+    const int So = S + 1, P = So * So;
+    const size_t pfx = (size_t)r * ny * (nx + 1), pcx = (size_t)ny * (nx + 1);
+    const size_t pfy = (size_t)(ny + 1) * r * nx, pcy = (size_t)(ny + 1) * nx;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n * P; k += gridDim.x * blockDim.x) {
+        const int p = k / P, q = k % P, tile = tiles[p];
+        const int gx = (tile % ntx) * S - 1 + q % So, gy = (tile / ntx) * S - 1 + q / So;
+        float lab[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float msk[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (gx >= 0 && gy >= 0 && gx < nx && gy < ny) {
+            if (gx + 1 < nx) {   // east face = x line I = gx + 1
+                double f[3];
+                for (int c = 0; c < 3; ++c) {
+                    double sum = 0.0;
+                    for (int j = 0; j < r; ++j) sum += (double)ftx[c * pfx + (size_t)(gy * r + j) * (nx + 1) + gx + 1];
+                    f[c] = (sum / r - (double)ctx[c * pcx + (size_t)gy * (nx + 1) + gx + 1]) * inv_tau;
+                }
+                lab[0] = (float)f[0]; lab[1] = (float)f[1]; lab[2] = (float)f[2];
+                msk[0] = msk[1] = msk[2] = 1.f;
+            }
+            if (gy + 1 < ny) {   // north face = y line J = gy + 1
+                double f[3];
+                for (int c = 0; c < 3; ++c) {
+                    double sum = 0.0;
+                    for (int i = 0; i < r; ++i) sum += (double)fty[c * pfy + (size_t)(gy + 1) * r * nx + gx * r + i];
+                    f[c] = (sum / r - (double)cty[c * pcy + (size_t)(gy + 1) * nx + gx]) * inv_tau;
+                }
+                lab[3] = (float)f[0]; lab[4] = (float)f[2]; lab[5] = (float)f[1];   // world x, y momentum
+                msk[3] = msk[4] = msk[5] = 1.f;
+            }
+        }
+        int cnt = 0;
+        for (int c = 0; c < 6; ++c) {
+            y[(size_t)k * 6 + c] = lab[c] / oscale[c];
+            mask[(size_t)k * 6 + c] = msk[c];
+            cnt += msk[c] > 0.f;
+        }
+        if (cnt) atomicAdd(&mcount[p], cnt);
+    }
+}
+
+// Minibatch: crops idx[b] of the data set into the network's input, label
+// and mask buffers.
+__global__ void k_batch_copy(const int* __restrict__ idx, int nb, int So, const unsigned short* __restrict__ X,
+                             const float* __restrict__ Y, const float* __restrict__ M, unsigned short* __restrict__ x,
+                             float* __restrict__ y, float* __restrict__ m) {
+    const int Sin = So + 2 * HALO;
+    const size_t px = (size_t)Sin * Sin * 16, py = (size_t)So * So * 6;
+    const size_t total = (size_t)nb * (px + 2 * py);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+        if (k < (size_t)nb * px) {
+            const size_t b = k / px, o = k % px;
+            x[k] = X[(size_t)idx[b] * px + o];
+        } else if (k < (size_t)nb * (px + py)) {
+            const size_t kk = k - (size_t)nb * px, b = kk / py, o = kk % py;
+            y[kk] = Y[(size_t)idx[b] * py + o];
+        } else {
+            const size_t kk = k - (size_t)nb * (px + py), b = kk / py, o = kk % py;
+            m[kk] = M[(size_t)idx[b] * py + o];
+        }
+    }
+}
+
+// Labels of the data set re-expressed in new output scales: y *= old / new.
+__global__ void k_rescale(float* __restrict__ y, size_t n, const float* __restrict__ ratio) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        y[k] *= ratio[k % 6];
+}
+
+}  // namespace lc
+}  // namespace swe

@@ -108,7 +108,22 @@ struct Args {
     int hold, ntap;
     const int* tap_rect;
     real* tap;
+    // learned flux corrections through the east and north face of each cell,
+    // 3 planes (mass, x-momentum, y-momentum) of nx*ny (CORR kernels only)
+    const real* corrE;
+    const real* corrN;
+    // face taps on the lines of a grid coarsened by tap_r (TAP kernels with
+    // tap_r > 0): tau * flux of the x faces at columns that are multiples of
+    // tap_r, per row, in tapx [3][ny][nx/tap_r + 1], and of the y faces at
+    // rows that are multiples of tap_r, per column, in tapy [3][ny/tap_r + 1][nx]
+    int tap_r;
+    real* tapx;
+    real* tapy;
 };
+
+// Variants of the step kernel: plain, with flux taps (nested grids), with
+// learned flux corrections.
+constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2;
 
 // ---------------------------------------------------------------- math
 
@@ -313,14 +328,15 @@ __device__ void set_next_step(const Args<real>& a, Ctrl* c, double tau) {
     c->sdepth = a.nin_h2 > 0.0 ? (double)(real)(dV / a.nin_h2) : 0.0;
 }
 
-// Bookkeeping of a new layer with maximum speed S: its CFL step, and unless
-// a nest sets the steps (hold), the next step's scalars.
+// Bookkeeping of a new layer with maximum speed S: its CFL step and the next
+// step's scalars (with hold, the step length set from outside is kept).
 template <typename real>
 __device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
     const double tau = cfl_tau_of(a, S);
     c->speed = S;
     c->tau_cfl = tau;
-    if (!a.hold) set_next_step(a, c, tau);
+    // a held step keeps its length; its hydrograph volume moves with the clock
+    set_next_step(a, c, a.hold ? c->tau : tau);
 }
 
 // Prefix offsets of the list segments of `slot` from their counters.
@@ -451,12 +467,51 @@ __device__ void fill_ghosts(int tx0, int ty0, int nx, int ny, int x0, int x1, in
 
 // bits: 1 own wet, 2 W edge, 4 E edge, 8 S edge, 16 N edge (layer n+1),
 // 32 ring wet (layer n+1), 64 K1-active at layer n
-template <typename real, int TX, int TY, int NT, int LIM, bool EDGE, bool TAP>
+// Line taps: cell (gx, gy) adds tau * flux of its west face when gx is a
+// multiple of tap_r and of its south face when gy is (planes: depth, normal
+// momentum, tangential momentum, as for tap rectangles).
+template <typename real>
+__device__ __forceinline__ void tap_lines(const Args<real>& a, int gx, int gy, real tau, real xH, real xN, real xT,
+                                          real yH, real yN, real yT) {
+    const int r = a.tap_r;
+    if (gx % r == 0) {
+        const int w = a.nx / r + 1, pl = a.ny * w, k = gy * w + gx / r;
+        a.tapx[k] += tau * xH;
+        a.tapx[pl + k] += tau * xN;
+        a.tapx[2 * pl + k] += tau * xT;
+    }
+    if (gy % r == 0) {
+        const int pl = (a.ny / r + 1) * a.nx, k = (gy / r) * a.nx + gx;
+        a.tapy[k] += tau * yH;
+        a.tapy[pl + k] += tau * yN;
+        a.tapy[2 * pl + k] += tau * yT;
+    }
+}
+
+// Learned flux correction of one face (mass, x-momentum, y-momentum planes of
+// corr at cell index k): the mass part only where its upwind cell (lo side for
+// a positive correction, else hi side) is wet after the Lagrangian stage, the
+// momentum part only where both cells are.  A face dry on both sides takes
+// none, so the dry-wave shortcuts of the flux passes stay exact.
+template <typename real>
+__device__ __forceinline__ void add_correction(const Args<real>& a, const real* corr, int k, real Hlo, real Hhi,
+                                               real& FH, real& Fn, real& Ft, bool xface) {
+    const int n = a.nx * a.ny;
+    const real dH = corr[k], dX = corr[n + k], dY = corr[2 * n + k];
+    const real Hd = dH > real(0) ? Hlo : Hhi;
+    const bool both = Hlo > a.eps && Hhi > a.eps;
+    FH += Hd > a.eps ? dH : real(0);
+    Fn += both ? (xface ? dX : dY) : real(0);
+    Ft += both ? (xface ? dY : dX) : real(0);
+}
+
+template <typename real, int TX, int TY, int NT, int LIM, bool EDGE, int MODE>
 __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, int ty0,
                           real tau, real sdep, real& vmax, bool& bad, double& msum, double& lsum,
                           int& bits) {
     using G = Geo<TX, TY>;
     constexpr int W = G::W;
+    constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR;
     const int tid = threadIdx.x, nx = a.nx, ny = a.ny;
     const real eps = a.eps, half_tau = real(0.5) * tau, r = tau * a.ih;
     // normalised cubic-B-spline SPH gradient weights (smoothing length h):
@@ -697,6 +752,12 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             for (int f = 0; f < RUN; ++f) {
                 real FH, Fn, Ft;
                 riemann<real>(a.g, hi[f], lo[f + 1], FH, Fn, Ft);
+                if constexpr (CORR) {
+                    // face between cells gx-1 and gx: the east face of gx-1
+                    const int gx = tx0 + x0 + f, gy = ty0 + y;
+                    if (gx >= 1 && gx < nx && gy >= 0 && gy < ny)
+                        add_correction(a, a.corrE, gy * nx + gx - 1, cl[f + 1].H, cl[f + 2].H, FH, Fn, Ft, true);
+                }
                 const int s = G::at(x0 + f, y);
                 L.HX[s] = FH; L.HY[s] = Fn; L.H[s] = Ft;
             }
@@ -711,6 +772,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
         // (x face) or north (y face) of it
         bool tap_here = false;
         if constexpr (TAP) {
+            tap_here = a.tap_r > 0;
             for (int q = 0; q < a.ntap; ++q) {
                 const int* R = a.tap_rect + 5 * q;
                 const bool xs = ty0 < R[3] && ty0 + TY > R[1] &&
@@ -738,7 +800,16 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 for (int i = 0; i < RUN + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
                 // recon index i is cell y0 - 1 + i; face y0 + f between cells f and f+1
 #pragma unroll
-                for (int f = 0; f < RUN + 1; ++f) riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
+                for (int f = 0; f < RUN + 1; ++f) {
+                    riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
+                    if constexpr (CORR) {
+                        // face between cells gy-1 and gy: the north face of gy-1
+                        const int gx = tx0 + x, gy = ty0 + y0 + f;
+                        if (gy >= 1 && gy < ny && gx >= 0 && gx < nx)
+                            add_correction(a, a.corrN, (gy - 1) * nx + gx, cl[f + 1].H, cl[f + 2].H, FH[f], Fn[f],
+                                           Ft[f], false);
+                    }
+                }
             } else {   // dry on both sides of every face of the run: zero fluxes
 #pragma unroll
                 for (int f = 0; f < RUN + 1; ++f) { FH[f] = real(0); Fn[f] = real(0); Ft[f] = real(0); }
@@ -769,8 +840,12 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     lsum += (double)(Hc - Hn);
                     bad |= !finite(Hn) || !finite(qx) || !finite(qy);
                     if constexpr (TAP) {
-                        if (tap_here)
-                            tap_faces(a, tx0 + x, ty0 + y, tau, L.HX[s], L.HY[s], L.H[s], FH[i], Fn[i], Ft[i]);
+                        if (tap_here) {
+                            if (a.tap_r > 0)
+                                tap_lines(a, tx0 + x, ty0 + y, tau, L.HX[s], L.HY[s], L.H[s], FH[i], Fn[i], Ft[i]);
+                            else
+                                tap_faces(a, tx0 + x, ty0 + y, tau, L.HX[s], L.HY[s], L.H[s], FH[i], Fn[i], Ft[i]);
+                        }
                     }
                 }
             }
@@ -840,7 +915,7 @@ template <typename real> constexpr int waves_per_simd() {
     return sizeof(real) == 4 ? SWE_WAVES_PER_SIMD_F32 : SWE_WAVES_PER_SIMD_F64;
 }
 
-template <typename real, int TX, int TY, int NT, int LIM, bool TAP>
+template <typename real, int TX, int TY, int NT, int LIM, int MODE>
 __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
@@ -872,9 +947,9 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         int bits = 0;
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, TAP>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
         else
-            tile_step<real, TX, TY, NT, LIM, false, TAP>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
         // block reductions: flags, volume and ledger partials
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
@@ -1039,6 +1114,43 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
     }
 }
 
+// Set the length of the next step (held steps; tau <= 0: the recorded CFL
+// step of the current layer) and its hydrograph scalars.  The tile list is
+// left alone.
+template <typename real>
+__global__ void k_set_dt(Args<real> a, double tau) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        set_next_step(a, a.ctrl, tau > 0.0 ? (double)(real)tau : a.ctrl->tau_cfl);
+}
+
+// Coarse layer = means of r x r fine cells (H, Qx, Qy), written to both
+// coarse buffers.
+template <typename real>
+__global__ void k_restrict(const real* __restrict__ H, const real* __restrict__ Qx, const real* __restrict__ Qy,
+                           int nxf, int r, real* H0, real* Qx0, real* Qy0, real* H1, real* Qx1, real* Qy1,
+                           int nxc, int nyc) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nxc * nyc; k += gridDim.x * blockDim.x) {
+        const int I = k % nxc, J = k / nxc;
+        double sh = 0.0, sx = 0.0, sy = 0.0;
+        for (int jj = 0; jj < r; ++jj)
+            for (int ii = 0; ii < r; ++ii) {
+                const int f = (J * r + jj) * nxf + I * r + ii;
+                sh += (double)H[f];
+                sx += (double)Qx[f];
+                sy += (double)Qy[f];
+            }
+        const double inv = 1.0 / (double)(r * r);
+        H0[k] = H1[k] = (real)(sh * inv);
+        Qx0[k] = Qx1[k] = (real)(sx * inv);
+        Qy0[k] = Qy1[k] = (real)(sy * inv);
+    }
+}
+
+template <typename real>
+__global__ void k_fill(real* p, long n, real v) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
 template <typename real>
 __global__ void k_prepare_finish(Args<real> a) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -1104,9 +1216,9 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
         int bits = 0;
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
         else
-            tile_step<real, TX, TY, NT, LIM, false, false>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         bits |= __any(bad) ? 128 : 0;

@@ -1,0 +1,127 @@
+"""Learned coarse-grid flux correction: training data from fine runs of the
+solver, training, and the comparison against the fine solve.
+
+Host orchestration only: every step of the solver, the labels, the network
+and its training run in the library's kernels (swe_lc_*); this module picks
+time steps, seeds and minibatch sizes and reads back a few scalars.
+
+The coarse grid is the fine grid coarsened by r: bed and Manning n are the
+means of r x r fine cells, the state is the restriction of the fine state.
+A coarse interval tau_c = min(coarse CFL step, m * fine CFL step) is one
+coarse step and m fine steps.
+"""
+import time
+
+import numpy as np
+
+from . import swe
+
+IN_SCALE = np.array([5.0, 1.0, 1.0, 10.0, 0.05, 1.0])
+
+
+def coarsen(sc, r):
+    """Coarse scenario of a fine one: means of r x r cells; no inlet cells are
+    dropped (the inlet rectangle is scaled by 1/r and must align)."""
+    ny, nx = sc["ny"] // r, sc["nx"] // r
+    R = lambda a: np.asarray(a, dtype=np.float64)[:ny * r, :nx * r].reshape(ny, r, nx, r).mean(axis=(1, 3))
+    p = dict(sc["params"])
+    if p.get("inlet"):
+        i0, j0, ni, nj = p["inlet"]
+        p["inlet"] = (i0 // r, j0 // r, max(ni // r, 1), max(nj // r, 1))
+    return dict(name=sc["name"] + "-coarse%d" % r, nx=nx, ny=ny, h=sc["h"] * r, b=R(sc["b"]),
+                n_manning=R(sc["n_manning"]), solid=None, H0=R(sc["H0"]), Qx0=R(sc["Qx0"]), Qy0=R(sc["Qy0"]),
+                params=p)
+
+
+def make_net(tile, max_crops, out_scale=None):
+    return swe.Net(tile, max_crops, IN_SCALE, np.ones(6) if out_scale is None else out_scale)
+
+
+def collect(net, fine_sc, r, m, intervals, skip=0):
+    """Run the fine scenario and add the crops and labels of `intervals`
+    coarse intervals (after `skip` fine CFL steps) to the network's data set."""
+    f = swe.Solver(fine_sc)
+    if skip:
+        f.run(skip)
+    f.enable_line_taps(r)
+    c = swe.Solver(coarsen(fine_sc, r))
+    c.enable_line_taps(1)
+    taus = []
+    for _ in range(intervals):
+        taus.append(net.collect(f, c, r, m))
+    f.close()
+    c.close()
+    return taus
+
+
+def label_scale(net):
+    """Per-channel RMS of the collected labels (in current output units)."""
+    n = net.data_count()
+    _, y, mask, _ = net.get_data(0, n)
+    num = (y * y * mask).sum(axis=(0, 1, 2))
+    den = np.maximum(mask.sum(axis=(0, 1, 2)), 1.0)
+    return np.sqrt(num / den) * net.out_scale
+
+
+def compare(net, fine_sc, r, m, intervals, skip=0):
+    """Fine solve, plain coarse and learned coarse over the same coarse
+    intervals from the same restricted layer; relative L1 depth error of
+    both coarse runs against the restricted fine solution at the end."""
+    f = swe.Solver(fine_sc)
+    if skip:
+        f.run(skip)
+    csc = coarsen(fine_sc, r)
+    plain = swe.Solver(csc)
+    lrn = swe.Solver(csc)
+    plain.restrict_from(f, r)
+    lrn.restrict_from(f, r)
+    net.attach(lrn)
+    for _ in range(intervals):
+        tau_c = min(plain.next_dt(), lrn.next_dt(), m * f.next_dt())
+        tau_f = tau_c / m
+        f.hold_dt(tau_f)
+        f.run(m)
+        f.hold_dt(0.0)
+        for g in (plain, lrn):
+            g.hold_dt(tau_f * m)
+            g.run(1)
+            g.hold_dt(0.0)
+    ref = swe.Solver(csc)
+    ref.restrict_from(f, r)
+    Hr = ref.state()[0]
+    Hp, Hl = plain.state()[0], lrn.state()[0]
+    net.detach(lrn)
+    out = dict(time=f.time(), err_plain=float(np.abs(Hp - Hr).sum() / np.abs(Hr).sum()),
+               err_learned=float(np.abs(Hl - Hr).sum() / np.abs(Hr).sum()))
+    for g in (f, plain, lrn, ref):
+        g.close()
+    return out
+
+
+def timing(net, fine_sc, r, sim_seconds, skip=0):
+    """Wall time of the fine solve and of the learned coarse solve (network
+    included) over the same simulated interval, each with its own CFL steps
+    and hipGraph replays."""
+    import torch
+    f = swe.Solver(fine_sc)
+    if skip:
+        f.run(skip)
+    csc = coarsen(fine_sc, r)
+    g = swe.Solver(csc)
+    g.restrict_from(f, r)
+    net.attach(g)
+    res = {}
+    for name, s in (("fine", f), ("learned", g)):
+        t0 = s.time()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        steps = 0
+        while s.time() - t0 < sim_seconds:
+            s.run(32)
+            steps += 32
+        torch.cuda.synchronize()
+        res[name] = dict(wall=time.perf_counter() - w0, steps=steps, sim=s.time() - t0)
+    net.detach(g)
+    f.close()
+    g.close()
+    return res

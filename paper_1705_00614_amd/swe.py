@@ -90,6 +90,32 @@ EXPORTS = {
     "swe_nest_get_coarse": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_nest_get_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]),
     "swe_nest_destroy": (None, [ctypes.c_void_p]),
+    "swe_set_correction": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
+    "swe_hold_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "swe_enable_line_taps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "swe_zero_line_taps": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_get_line_taps": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
+    "swe_restrict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "swe_lc_nparams": (ctypes.c_int, []),
+    "swe_lc_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_void_p]),
+    "swe_lc_destroy": (None, [ctypes.c_void_p]),
+    "swe_lc_set_params": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "swe_lc_get_params": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "swe_lc_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp]),
+    "swe_lc_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]),
+    "swe_lc_get_grads": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "swe_lc_get_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
+    "swe_lc_attach": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "swe_lc_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "swe_lc_set_out_scale": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "swe_lc_data_count": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_lc_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                      _dp]),
+    "swe_lc_get_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
+                                       ctypes.POINTER(ctypes.c_int)]),
+    "swe_lc_fit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong,
+                                  _dp]),
+    "swe_lc_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int)]),
     "swe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -278,6 +304,38 @@ class Solver:
             _check(cnt)
         return np.sort(np.array(buf[:cnt], dtype=np.int64))
 
+    def hold_dt(self, tau):
+        """Hold the step length at tau from the next step on (0 releases)."""
+        _check(load().swe_hold_dt(self._h, float(tau)))
+
+    def enable_line_taps(self, r):
+        self.tap_r = int(r)
+        _check(load().swe_enable_line_taps(self._h, self.tap_r))
+
+    def zero_line_taps(self):
+        _check(load().swe_zero_line_taps(self._h))
+
+    def line_taps(self):
+        r = self.tap_r
+        tx = np.empty((3, self.ny, self.nx // r + 1))
+        ty = np.empty((3, self.ny // r + 1, self.nx))
+        _check(load().swe_get_line_taps(self._h, _ptr(tx), _ptr(ty)))
+        return tx, ty
+
+    def restrict_from(self, fine, r):
+        """This (coarse) grid's layer = r x r means of fine's layer."""
+        _check(load().swe_restrict(fine._h, self._h, int(r)))
+
+    def set_correction(self, dE, dN):
+        """Flux corrections (3, ny, nx) through the east and north faces, or None."""
+        if dE is None and dN is None:
+            _check(load().swe_set_correction(self._h, None, None))
+            return
+        shp = (3, self.ny, self.nx)
+        dE = _f64(np.zeros(shp) if dE is None else dE, shp)
+        dN = _f64(np.zeros(shp) if dN is None else dN, shp)
+        _check(load().swe_set_correction(self._h, _ptr(dE), _ptr(dN)))
+
 
 class Batch:
     """Scenarios of uneven grid sizes advanced together by one launch per step
@@ -439,3 +497,137 @@ class Nest:
         H, Qx, Qy = (np.empty(shp) for _ in range(3))
         _check(load().swe_nest_get_patch(self._h, int(k), _ptr(H), _ptr(Qx), _ptr(Qy)))
         return H, Qx, Qy
+
+
+LC_LAYERS = ((6, 32), (32, 32), (32, 32), (32, 6))
+
+
+def lc_pack(W, b):
+    """Packed parameter vector from per-layer W (out, in, 3, 3) and b (out)."""
+    return np.concatenate([np.concatenate([np.asarray(w, np.float64).ravel(), np.asarray(v, np.float64).ravel()])
+                           for w, v in zip(W, b)])
+
+
+def lc_unpack(p):
+    W, b, k = [], [], 0
+    for ci, co in LC_LAYERS:
+        n = co * ci * 9
+        W.append(p[k:k + n].reshape(co, ci, 3, 3))
+        k += n
+        b.append(p[k:k + co].copy())
+        k += co
+    return W, b
+
+
+class Net:
+    """The learned flux-correction network (``swe_lc_*``) for tiles of S cells."""
+
+    def __init__(self, tile, max_crops, in_scale, out_scale, stream="torch"):
+        L = load()
+        st = current_stream() if stream == "torch" else stream
+        self.S = int(tile)
+        self.So = self.S + 1            # outputs: the tile and the cell row and column before it
+        self.in_scale = np.ascontiguousarray(in_scale, dtype=np.float64)
+        self.out_scale = np.ascontiguousarray(out_scale, dtype=np.float64)
+        self._h = L.swe_lc_create(self.S, int(max_crops), _ptr(self.in_scale), _ptr(self.out_scale), st)
+        if not self._h:
+            raise SweError(SWE_EINVAL, last_error())
+        self.nparams = L.swe_lc_nparams()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_lc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        assert p.shape == (self.nparams,)
+        _check(load().swe_lc_set_params(self._h, _ptr(p)))
+
+    def params(self):
+        p = np.empty(self.nparams)
+        _check(load().swe_lc_get_params(self._h, _ptr(p)))
+        return p
+
+    def grads(self):
+        p = np.empty(self.nparams)
+        _check(load().swe_lc_get_grads(self._h, _ptr(p)))
+        return p
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = x.shape[0]
+        out = np.empty((n, self.So, self.So, 6))
+        _check(load().swe_lc_forward(self._h, n, _ptr(x), _ptr(out)))
+        return out
+
+    def train_step(self, x, y, mask, lr):
+        x, y, mask = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, mask))
+        loss = ctypes.c_double()
+        _check(load().swe_lc_train_step(self._h, x.shape[0], _ptr(x), _ptr(y), _ptr(mask), float(lr),
+                                        ctypes.byref(loss)))
+        return loss.value
+
+    def attach(self, solver):
+        """Correct every later step of `solver` with this network (None detaches)."""
+        if solver is None:
+            raise ValueError("use detach(solver)")
+        _check(load().swe_lc_attach(self._h, solver._h))
+
+    @staticmethod
+    def detach(solver):
+        _check(load().swe_lc_attach(None, solver._h))
+
+    def gather(self, solver):
+        """Crops (n, S+9, S+9, 6) of the solver's active tiles and their tile indices."""
+        nt = solver.work()["ntiles"]
+        x = np.empty((nt, self.So + 8, self.So + 8, 6))
+        tiles = (ctypes.c_int * nt)()
+        n = load().swe_lc_gather(self._h, solver._h, _ptr(x), tiles)
+        if n < 0:
+            _check(n)
+        return x[:n], np.array(tiles[:n], dtype=np.int64)
+
+    def set_out_scale(self, scale):
+        self.out_scale = np.ascontiguousarray(scale, dtype=np.float64)
+        _check(load().swe_lc_set_out_scale(self._h, _ptr(self.out_scale)))
+
+    def data(self, capacity):
+        _check(load().swe_lc_data(self._h, int(capacity)))
+
+    def data_count(self):
+        return load().swe_lc_data_count(self._h)
+
+    def collect(self, fine, coarse, r, m):
+        """Add one coarse interval of training crops; returns its tau_c."""
+        tau = ctypes.c_double()
+        _check(load().swe_lc_collect(self._h, fine._h, coarse._h, int(r), int(m), ctypes.byref(tau)))
+        return tau.value
+
+    def get_data(self, first, n):
+        So = self.So
+        x = np.empty((n, So + 8, So + 8, 6))
+        y = np.empty((n, So, So, 6))
+        m = np.empty((n, So, So, 6))
+        t = (ctypes.c_int * max(n, 1))()
+        _check(load().swe_lc_get_data(self._h, int(first), int(n), _ptr(x), _ptr(y), _ptr(m), t))
+        return x, y, m, np.array(t[:n], dtype=np.int64)
+
+    def fit(self, iters, batch, lr, seed=0):
+        losses = np.empty(max(int(iters), 1))
+        _check(load().swe_lc_fit(self._h, int(iters), int(batch), float(lr), int(seed), _ptr(losses)))
+        return losses[:iters]
+
+    def layer(self, which, n):
+        """Stored bf16 values of the last forward/backward (see swe_lc_get_layer)."""
+        l = which % 4
+        if which < 4:
+            side, c = self.So + 8 - 2 * l, LC_LAYERS[l][0]
+        else:
+            side, c = self.So + 6 - 2 * l, LC_LAYERS[l][1]
+        out = np.empty((n, side, side, c))
+        _check(load().swe_lc_get_layer(self._h, int(which), _ptr(out)))
+        return out

@@ -1,0 +1,416 @@
+"""The learned flux-correction network on the GPU (bf16 MFMA, FP32
+accumulation) against the FP64 oracle of oracle/learned.py.
+
+Each layer is checked from the GPU's own stored inputs, so bf16 rounding
+decisions upstream do not propagate: a pre-activation computed in FP32 from K
+products differs from the exact sum by at most K * 2^-24 * sum|products|
+(with margin: 3e-5 * sum|products| for K <= 288), so every stored bf16
+activation must lie between the roundings of tanh at the two ends of that
+interval, every FP32 output within it, and every weight gradient within the
+same bound of its exact sum.  Adam: FP32 against FP64 on the same gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import learned as LN
+
+pytestmark = pytest.mark.gpu
+
+swe = pytest.importorskip("paper_1705_00614_amd.swe")
+
+REL = 3e-5
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu] %s" % request.node.nodeid, flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _setup(S=8, n=3, seed=0):
+    rng = np.random.default_rng(seed)
+    W, b = LN.init_params(seed)
+    W[-1] = W[-1] * 10.0
+    b = [rng.normal(scale=0.1, size=v.shape) for v in b]
+    x = rng.normal(size=(n, S + 9, S + 9, 6))
+    net = swe.Net(S, 4, np.ones(6), np.ones(6))
+    net.set_params(swe.lc_pack(W, b))
+    Wb = [LN.bf16(w) for w in W]
+    return net, W, Wb, b, x, rng
+
+
+def _within_tanh(a_gpu, z, bound):
+    lo = LN.bf16(np.tanh(z - bound))
+    hi = LN.bf16(np.tanh(z + bound))
+    return np.all((a_gpu >= lo) & (a_gpu <= hi))
+
+
+def test_forward_layers_match_oracle():
+    net, W, Wb, b, x, _ = _setup()
+    n = x.shape[0]
+    out = net.forward(x)
+    a = [net.layer(l, n) for l in range(4)]
+    assert np.array_equal(a[0], LN.bf16(x))
+    for l in range(3):
+        z = LN.conv3x3(a[l], Wb[l], b[l])
+        bound = REL * LN.conv3x3(np.abs(a[l]), np.abs(Wb[l]), np.zeros_like(b[l])) + 1e-7
+        assert _within_tanh(a[l + 1], z, bound), l
+    z = LN.conv3x3(a[3], Wb[3], b[3])
+    bound = REL * LN.conv3x3(np.abs(a[3]), np.abs(Wb[3]), np.zeros_like(b[3])) + 1e-7
+    assert np.all(np.abs(out - z) <= bound)
+    # and the whole network stays close to the all-FP64 oracle
+    ref, _ = LN.forward(x, W, b, bf=True)
+    assert np.abs(out - ref).max() <= 0.05 * np.abs(ref).max()
+
+
+def test_backward_matches_oracle():
+    net, W, Wb, b, x, rng = _setup(seed=1)
+    n, So = x.shape[0], 9
+    y = rng.normal(size=(n, So, So, 6))
+    mask = (rng.uniform(size=y.shape) > 0.2).astype(float)
+    net.train_step(x, y, mask, 0.0)
+    grads = net.grads()
+    dW, db = swe.lc_unpack(grads)
+    a = [net.layer(l, n) for l in range(4)]
+    g = [net.layer(4 + l, n) for l in range(4)]
+    out = net.forward(x)
+    _, g3 = LN.loss_and_grad(out, y, mask)
+    assert np.all(np.abs(g[3] - LN.bf16(g3)) <= 2 ** -8 * np.abs(g3) + 1e-30)
+    for l in range(3, -1, -1):
+        dx, dw, dbb = LN.conv3x3_grads(a[l], Wb[l], g[l])
+        adx, adw, adb = LN.conv3x3_grads(np.abs(a[l]), np.abs(Wb[l]), np.abs(g[l]))
+        assert np.all(np.abs(dW[l] - dw) <= REL * adw + 1e-9), l
+        assert np.all(np.abs(db[l] - dbb) <= REL * adb + 1e-9), l
+        if l > 0:
+            d = 1.0 - a[l] ** 2
+            lo = LN.bf16((dx - REL * adx) * d)
+            hi = LN.bf16((dx + REL * adx) * d)
+            assert np.all((g[l - 1] >= np.minimum(lo, hi)) & (g[l - 1] <= np.maximum(lo, hi))), l
+
+
+def test_adam_step_matches_oracle():
+    net, W, Wb, b, x, rng = _setup(seed=2)
+    n, So = x.shape[0], 9
+    y = rng.normal(size=(n, So, So, 6))
+    mask = np.ones_like(y)
+    p0 = net.params()
+    net.train_step(x, y, mask, 1e-3)
+    G = net.grads()
+    p1 = net.params()
+    ref = LN.Adam([p0], lr=1e-3).step([p0], [G])[0]
+    assert np.abs(p1 - ref).max() <= 2e-6
+
+
+def test_training_fits_a_teacher():
+    S, n = 8, 4
+    rng = np.random.default_rng(3)
+    Wt, bt = LN.init_params(11)
+    Wt[-1] = Wt[-1] * 10.0
+    x = rng.normal(size=(n, S + 9, S + 9, 6))
+    y, _ = LN.forward(x, Wt, bt, bf=False)
+    net = swe.Net(S, n, np.ones(6), np.ones(6))
+    W0, b0 = LN.init_params(5)
+    net.set_params(swe.lc_pack(W0, b0))
+    mask = np.ones_like(y)
+    first = net.train_step(x, y, mask, 3e-3)
+    for _ in range(300):
+        last = net.train_step(x, y, mask, 3e-3)
+    assert last < 0.1 * first, (first, last)
+
+
+def _corr_fields(sc, seed, amp):
+    """Smooth seeded correction fields (a few long waves per plane): random
+    per-face noise makes the corrected flow itself unstable, which would
+    measure that instability rather than the kernels."""
+    rng = np.random.default_rng(seed)
+    ny, nx = sc["ny"], sc["nx"]
+    y, x = np.mgrid[0:ny, 0:nx] / max(nx, ny)
+    out = []
+    for _ in range(2):
+        f = np.zeros((3, ny, nx))
+        for c in range(3):
+            for _ in range(4):
+                kx, ky = rng.integers(1, 4, size=2)
+                f[c] += np.sin(2 * np.pi * (kx * x + ky * y) + rng.uniform(0, 6.3))
+        out.append(amp * f / 4)
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+def test_corrected_step_matches_oracle(prec, tol):
+    from oracle import oracle as orc
+    from paper_1705_00614_amd import scenarios as S
+    sc = S.floodplain(n=96, h=50.0, seed=7, q_peak=2000.0, t_peak=200.0, sigma_t=150.0, inlet_cells=6,
+                      precision=prec)
+    dE, dN = _corr_fields(sc, 3, 0.02)
+    # the case is well conditioned: 1e-14 in the initial depth stays ~1e-14
+    import copy
+    sc2 = copy.deepcopy(sc)
+    sc2["H0"] = sc["H0"] * (1 + 1e-14 * np.random.default_rng(1).standard_normal(sc["H0"].shape))
+    a, b2 = orc.OracleSim(sc), orc.OracleSim(sc2)
+    a.set_correction(dE, dN)
+    b2.set_correction(dE, dN)
+    a.run(40)
+    b2.run(40)
+    assert np.abs(a.state()[1] - b2.state()[1]).sum() <= 1e-12 * np.abs(a.state()[1]).sum()
+    g = swe.Solver(sc)
+    g.set_correction(dE, dN)
+    o = orc.OracleSim(sc)
+    o.set_correction(dE, dN)
+    g.run(40)                       # one graph of 32 steps plus single launches
+    o.run(40)
+    (H, Qx, Qy), (Ho, Qxo, Qyo) = g.state(), o.state()
+    assert np.abs(H - Ho).sum() <= tol * np.abs(Ho).sum()
+    assert np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum() <= tol * (np.abs(Qxo).sum() + np.abs(Qyo).sum())
+    # the corrections moved water: the uncorrected run differs
+    p = swe.Solver(sc)
+    p.run(40)
+    assert np.abs(p.state()[0] - H).max() > 1e-6
+    # switching them off returns to the plain kernel
+    g.set_correction(None, None)
+    o.set_correction(None, None)
+    g.run(8)
+    o.run(8)
+    assert np.abs(g.state()[0] - o.state()[0]).sum() <= tol * np.abs(o.state()[0]).sum()
+
+
+IN_SCALE = np.array([5.0, 1.0, 1.0, 10.0, 0.05, 1.0])
+OUT_SCALE = np.array([0.02, 0.05, 0.05, 0.02, 0.05, 0.05])
+
+
+def _flood32(n=128, seed=8):
+    from paper_1705_00614_amd import scenarios as S
+    return S.floodplain(n=n, h=50.0, seed=seed, q_peak=3000.0, t_peak=300.0, sigma_t=200.0, inlet_cells=8,
+                        precision=32)
+
+
+def test_gather_matches_oracle_crops():
+    sc = _flood32()
+    g = swe.Solver(sc)
+    g.run(30)
+    net = swe.Net(32, g.work()["ntiles"], IN_SCALE, OUT_SCALE)
+    x, tiles = net.gather(g)
+    assert 0 < len(tiles) < g.work()["ntiles"]
+    H, Qx, Qy = g.state()
+    f = LN.features(H, Qx, Qy, sc["b"].astype(np.float32).astype(np.float64),
+                    sc["n_manning"], sc["params"]["eps"], IN_SCALE)
+    ntx = sc["nx"] // 32
+    ref = LN.bf16(LN.crops(f, [(t % ntx, t // ntx) for t in tiles], 32))
+    # features in FP32 on the GPU: equal after bf16 rounding except at rounding ties
+    diff = np.abs(x - ref)
+    assert np.all(diff <= 2 ** -8 * np.abs(ref) + 1e-30)
+    assert (diff > 0).mean() < 1e-3
+
+
+def test_attached_network_matches_oracle():
+    from oracle import oracle as orc
+    sc = _flood32()
+    rng = np.random.default_rng(9)
+    W, b = LN.init_params(21)
+    b = [rng.normal(scale=0.05, size=v.shape) for v in b]
+    # corrections of the size a trained network gives (label RMS ~1e-3)
+    out_scale = OUT_SCALE * 0.1
+    g = swe.Solver(sc)
+    net = swe.Net(32, g.work()["ntiles"], IN_SCALE, out_scale)
+    net.set_params(swe.lc_pack(W, b))
+    net.attach(g)
+    o = orc.OracleSim(sc)
+    ntx, nty = sc["nx"] // 32, sc["ny"] // 32
+    tiles = [(tx, ty) for ty in range(nty) for tx in range(ntx)]
+    steps = 24
+    for _ in range(steps):
+        H, Qx, Qy = o.state()
+        f = LN.features(H, Qx, Qy, sc["b"], sc["n_manning"], sc["params"]["eps"], IN_SCALE)
+        out, _ = LN.forward(LN.crops(f, tiles, 32), W, b, bf=True)
+        dE, dN = LN.corrections(out, tiles, 32, sc["ny"], sc["nx"], out_scale)
+        o.set_correction(dE, dN)
+        o.step()
+    g.run(steps)
+    (Hg, Qxg, Qyg), (Ho, Qxo, Qyo) = g.state(), o.state()
+    assert np.abs(Hg - Ho).sum() <= 1e-4 * np.abs(Ho).sum()
+    assert np.abs(Qxg - Qxo).sum() + np.abs(Qyg - Qyo).sum() <= 1e-4 * (np.abs(Qxo).sum() + np.abs(Qyo).sum())
+    # the corrections matter: a plain run differs
+    p = swe.Solver(sc)
+    p.run(steps)
+    assert np.abs(p.state()[0] - Hg).sum() > 1e-5 * np.abs(Ho).sum()
+    net.detach(g)
+
+
+# ---------------------------------------------------------------- training data
+
+def test_line_taps_match_oracle_faces():
+    from oracle import oracle as orc
+    from paper_1705_00614_amd import scenarios as S
+    sc = S.random_state(64, 48, seed=13, wet_frac=0.8, precision=64)
+    r = 2
+    g = swe.Solver(sc)
+    g.enable_line_taps(r)
+    o = orc.OracleSim(sc)
+    accx = [np.zeros((48, 65)) for _ in range(3)]
+    accy = [np.zeros((49, 64)) for _ in range(3)]
+    for _ in range(3):
+        tau = o.next_tau()
+        o.step()
+        for c, f in enumerate(o.faces(0)):
+            accx[c] += tau * f
+        for c, f in enumerate(o.faces(1)):
+            accy[c] += tau * f
+    g.run(3)
+    tx, ty = g.line_taps()
+    for c in range(3):
+        ref = accx[c][:, 0:64:r]
+        s = np.abs(ref).max()
+        assert np.abs(tx[c, :, :32] - ref).max() <= 1e-12 * s
+        assert np.all(tx[c, :, 32] == 0.0)
+        refy = accy[c][0:48:r, :]
+        assert np.abs(ty[c, :24, :] - refy).max() <= 1e-12 * np.abs(refy).max()
+        assert np.all(ty[c, 24, :] == 0.0)
+
+
+def test_restrict_and_held_steps():
+    from oracle import oracle as orc
+    from paper_1705_00614_amd import scenarios as S
+    fine = S.random_state(64, 64, seed=14, wet_frac=0.8, precision=64)
+    coarse = dict(fine, nx=32, ny=32, h=2 * fine["h"],
+                  b=fine["b"].reshape(32, 2, 32, 2).mean(axis=(1, 3)),
+                  n_manning=fine["n_manning"].reshape(32, 2, 32, 2).mean(axis=(1, 3)),
+                  H0=np.zeros((32, 32)), Qx0=np.zeros((32, 32)), Qy0=np.zeros((32, 32)))
+    f = swe.Solver(fine)
+    c = swe.Solver(coarse)
+    f.run(5)
+    c.restrict_from(f, 2)
+    H, Qx, Qy = f.state()
+    Hc, Qxc, Qyc = c.state()
+    for a, b in ((H, Hc), (Qx, Qxc), (Qy, Qyc)):
+        assert np.abs(a.reshape(32, 2, 32, 2).mean(axis=(1, 3)) - b).max() <= 1e-14 * max(1.0, np.abs(a).max())
+    assert c.time() == f.time()
+    # held step length against the oracle's fixed steps, then back to CFL steps
+    o = orc.OracleSim(fine)
+    g = swe.Solver(fine)
+    tau = 0.5 * o.next_tau()
+    g.hold_dt(tau)
+    for _ in range(6):
+        o.step(tau)
+    g.run(6)
+    assert abs(g.time() - 6 * tau) <= 1e-12 * g.time()
+    assert np.abs(g.state()[0] - o.state()[0]).sum() <= 1e-10 * np.abs(o.state()[0]).sum()
+    g.hold_dt(0.0)
+    assert abs(g.next_dt() - o.next_tau()) <= 1e-12 * o.next_tau()
+
+
+def _oracle_labels(fine_sc, coarse_sc, r, m):
+    """Labels of one coarse interval from the oracle: restricted layer, one
+    coarse step of tau_c, m fine steps of tau_c/m."""
+    from oracle import oracle as orc
+    f = orc.OracleSim(fine_sc)
+    H, Qx, Qy = f.state()
+    ny, nx = coarse_sc["ny"], coarse_sc["nx"]
+    R = lambda a: a.reshape(ny, r, nx, r).mean(axis=(1, 3))
+    c = orc.OracleSim(dict(coarse_sc, H0=R(H), Qx0=R(Qx), Qy0=R(Qy)))
+    tau_c = min(c.next_tau(), m * f.next_tau())
+    tau_f = tau_c / m
+    tau_c = tau_f * m
+    cx = [np.zeros((ny, nx + 1)) for _ in range(3)]
+    cy = [np.zeros((ny + 1, nx)) for _ in range(3)]
+    c.step(tau_c)
+    for k, a in enumerate(c.faces(0)):
+        cx[k] = tau_c * a
+    for k, a in enumerate(c.faces(1)):
+        cy[k] = tau_c * a
+    fx = [np.zeros((r * ny, r * nx + 1)) for _ in range(3)]
+    fy = [np.zeros((r * ny + 1, r * nx)) for _ in range(3)]
+    for _ in range(m):
+        f.step(tau_f)
+        for k, a in enumerate(f.faces(0)):
+            fx[k] += tau_f * a
+        for k, a in enumerate(f.faces(1)):
+            fy[k] += tau_f * a
+    E = np.zeros((ny, nx, 3))
+    N = np.zeros((ny, nx, 3))
+    for k in range(3):
+        mean_x = fx[k][:, ::r].reshape(ny, r, nx + 1).mean(axis=1)      # coarse x lines
+        mean_y = fy[k][::r, :].reshape(ny + 1, nx, r).mean(axis=2)      # coarse y lines
+        E[:, :nx - 1, k] = (mean_x[:, 1:nx] - cx[k][:, 1:nx]) / tau_c
+        N[:ny - 1, :, k] = (mean_y[1:ny, :] - cy[k][1:ny, :]) / tau_c
+    # y-face planes are (mass, y-momentum, x-momentum): world order for the labels
+    N = N[..., [0, 2, 1]]
+    return np.concatenate([E, N], axis=-1), tau_c, R(H), R(Qx), R(Qy)
+
+
+def test_collected_labels_match_oracle():
+    from paper_1705_00614_amd import scenarios as S
+    r, m = 2, 2
+    fine = S.floodplain(n=64, h=25.0, seed=15, q_peak=500.0, t_peak=100.0, sigma_t=80.0, inlet_cells=4, precision=64)
+    fine["H0"] = np.maximum(fine["H0"], np.where(fine["b"] < np.percentile(fine["b"], 40),
+                                                 np.percentile(fine["b"], 40) - fine["b"], 0.0))
+    fine["params"]["inlet"] = None
+    fine["params"]["q_peak"] = 0.0
+    coarse = dict(fine, nx=32, ny=32, h=2 * fine["h"],
+                  b=fine["b"].reshape(32, 2, 32, 2).mean(axis=(1, 3)),
+                  n_manning=fine["n_manning"].reshape(32, 2, 32, 2).mean(axis=(1, 3)),
+                  H0=np.zeros((32, 32)), Qx0=np.zeros((32, 32)), Qy0=np.zeros((32, 32)))
+    labels, tau_c, Hr, Qxr, Qyr = _oracle_labels(fine, coarse, r, m)
+    f = swe.Solver(fine)
+    f.enable_line_taps(r)
+    c = swe.Solver(coarse)
+    c.enable_line_taps(1)
+    S16 = c.work()["tile"][0]
+    net = swe.Net(S16, c.work()["ntiles"], IN_SCALE, OUT_SCALE)
+    net.data(64)
+    t = net.collect(f, c, r, m)
+    assert abs(t - tau_c) <= 1e-12 * tau_c
+    n = net.data_count()
+    assert n > 0
+    x, y, mask, tiles = net.get_data(0, n)
+    ntx = 32 // S16
+    # labels of cells -1 .. 31: a zero row and column in front for cell -1
+    padded = np.zeros((33, 33, 6))
+    padded[1:, 1:] = labels
+    for k, tile in enumerate(tiles):
+        tx, ty = tile % ntx, tile // ntx
+        ref = padded[ty * S16:ty * S16 + S16 + 1, tx * S16:tx * S16 + S16 + 1] / OUT_SCALE
+        got = y[k]
+        msk = mask[k] > 0
+        scale = np.abs(ref).max() + 1e-30
+        # labels are stored in FP32: relative 2^-24 of each value
+        assert np.abs((got - ref)[msk]).max() <= 1e-6 * scale
+        # wall faces and cells outside the grid are masked out
+        if tx == ntx - 1:
+            assert np.all(mask[k, :, -1, :3] == 0.0)
+        if ty == 32 // S16 - 1:
+            assert np.all(mask[k, -1, :, 3:] == 0.0)
+        if tx == 0:
+            assert np.all(mask[k, :, 0, :] == 0.0)
+        if ty == 0:
+            assert np.all(mask[k, 0, :, :] == 0.0)
+    # crops are the restricted layer's features
+    feat = LN.features(Hr, Qxr, Qyr, coarse["b"], np.sqrt(np.asarray(coarse["n_manning"]) ** 2),
+                       coarse["params"]["eps"], IN_SCALE)
+    ref = LN.bf16(LN.crops(feat, [(t_ % ntx, t_ // ntx) for t_ in tiles], S16))
+    assert np.all(np.abs(x - ref) <= 2 ** -8 * np.abs(ref) + 1e-30)
+
+
+def test_learned_correction_gains_over_plain_coarse():
+    """Train on fine runs of the solver, then a coarse grid with the network
+    tracks the restricted fine solution more closely than without it."""
+    from paper_1705_00614_amd import learned as LC
+    from paper_1705_00614_amd import scenarios as S
+    sc = S.floodplain(n=512, h=25.0, seed=31, q_peak=6000.0, t_peak=1800.0, sigma_t=600.0, inlet_cells=40,
+                      precision=32)
+    r, m = 4, 4
+    net = LC.make_net(32, 64)
+    net.data(4000)
+    LC.collect(net, sc, r, m, intervals=120)
+    assert net.data_count() > 100
+    net.set_out_scale(np.maximum(LC.label_scale(net), 1e-6))
+    W, b = LN.init_params(1)
+    net.set_params(swe.lc_pack(W, b))
+    losses = net.fit(600, 32, 1e-3, seed=1)
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() < 0.7 * losses[:50].mean(), (losses[:50].mean(), losses[-50:].mean())
+    res = LC.compare(net, sc, r, m, intervals=60)
+    print("learned-coarse comparison", res, flush=True)
+    assert res["err_learned"] < res["err_plain"], res

@@ -156,13 +156,35 @@ def test_crops_mirror_and_scatter_roundtrip():
     rng = np.random.default_rng(4)
     feat = rng.normal(size=(10, 12, 6))
     c = LN.crops(feat, [(0, 0), (2, 1)], 4)
-    assert c.shape == (2, 12, 12, 6)
-    assert np.array_equal(c[0, 4:8, 4:8], feat[0:4, 0:4])
-    assert np.array_equal(c[0, 3, 4:8], feat[0, 0:4])          # mirror: cell -1 shows cell 0
-    assert np.array_equal(c[0, 0, 4:8], feat[3, 0:4])          # cell -4 shows cell 3
-    assert np.array_equal(c[1, 4:8, 4:8], feat[4:8, 8:12])
-    assert np.array_equal(c[1, 4:8, 8], feat[4:8, 11])          # cell 12 shows 11
-    out = rng.normal(size=(2, 4, 4, 6))
+    assert c.shape == (2, 13, 13, 6)
+    # window starts 1 + 4 cells before the tile
+    assert np.array_equal(c[0, 5:9, 5:9], feat[0:4, 0:4])
+    assert np.array_equal(c[0, 4, 5:9], feat[0, 0:4])          # mirror: cell -1 shows cell 0
+    assert np.array_equal(c[0, 0, 5:9], feat[4, 0:4])          # cell -5 shows cell 4
+    assert np.array_equal(c[1, 4:9, 4:9], feat[3:8, 7:12])     # tile (2, 1): cells 7.. and 3..
+    assert np.array_equal(c[1, 5:9, 9], feat[4:8, 11])          # cell 12 shows 11
+    out = rng.normal(size=(2, 5, 5, 6))
     dE, dN = LN.corrections(out, [(0, 0), (2, 1)], 4, 10, 12, np.ones(6))
-    assert np.array_equal(dE[1, 4:8, 8:12], out[1, :, :, 1])
-    assert np.array_equal(dN[2, 0:4, 0:4], out[0, :, :, 5])
+    assert np.array_equal(dE[1, 3:8, 7:12], out[1, :, :, 1])
+    assert np.array_equal(dN[2, 0:4, 0:4], out[0, 1:, 1:, 5])
+
+
+def test_momentum_correction_needs_both_cells_wet():
+    sc = _wet_basin()
+    n = sc["nx"]
+    sc["H0"][:, 0] = 0.0
+    sc["Qx0"][:, 0] = 0.0
+    sc["Qy0"][:, 0] = 0.0
+    a, b = orc.OracleSim(sc), orc.OracleSim(sc)
+    tau = 0.2 * a.next_tau()
+    dE = np.zeros((3, n, n))
+    dE[1, 5, 0] = 0.05            # x-momentum through the face between dry (5, 0) and wet (5, 1)
+    dE[2, 7, 3] = 0.05            # y-momentum through a wet-wet face
+    b.set_correction(dE, None)
+    a.step(tau)
+    b.step(tau)
+    r = tau / sc["h"]
+    dQx = b.state()[1] - a.state()[1]
+    dQy = b.state()[2] - a.state()[2]
+    assert dQx[5, 1] == 0.0 and dQx[5, 0] == 0.0
+    assert abs(dQy[7, 3] + r * 0.05) <= 1e-14 and abs(dQy[7, 4] - r * 0.05) <= 1e-14
