@@ -33,6 +33,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -46,7 +48,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9900)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", choices=["floodplain", "wet"], default="floodplain")
+    ap.add_argument("--workload", choices=["floodplain", "wet", "nest", "ensemble", "learned"],
+                    default="floodplain")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--no-cpu", action="store_true")
@@ -114,6 +117,12 @@ def main():
               "(the multi-GPU decomposition is a design, not a measured path)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "nest":
+        return bench_nest(args)
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     import torch
 
     from paper_1705_00614_amd import scenarios as S
@@ -198,6 +207,131 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_nest(args):
+    """Hierarchical grids: a 2048^2 floodplain at 50 m with two 512^2-cell
+    boxes refined by 4 (two 2048^2 patches at 12.5 m) on channel bends."""
+    import torch
+    from paper_1705_00614_amd import scenarios as S
+    from paper_1705_00614_amd import swe
+    nd = S.nest_floodplain(n=2048, h=50.0, seed=1, r=4, box=512)
+    steps = args.steps if args.steps != 9900 else 5000
+    warm = args.warmup
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        N = swe.Nest(nd)
+        q0 = N.query()
+        N.run(warm)
+        w0 = N.work()
+        kms = N.run_timed(steps)
+        w1 = N.work()
+        q1 = N.query()
+    cells = (w1["coarse_cells"] - w0["coarse_cells"]) + (w1["fine_cells"] - w0["fine_cells"])
+    secs = kms * 1e-3
+    _line("nested grids: cell-updates/s (coarse active + fine patch substeps)", cells / secs / 1e9,
+          "Gcell-updates/s", steps, warm, kms / steps, "f32",
+          {"workload": "nest: floodplain 2048x2048 at 50 m + 2 patches 2048x2048 at 12.5 m (r=4), coarse steps "
+                       "%d..%d" % (warm, warm + steps),
+           "coarse_cell_updates": w1["coarse_cells"] - w0["coarse_cells"],
+           "fine_cell_updates": w1["fine_cells"] - w0["fine_cells"],
+           "simulated_seconds": q1["time"] - q0["time"],
+           "timing": "HIP events around each coarse step (all its launches)",
+           "volume_balance_rel": abs(q1["volume"] - q0["volume"] - q1["inflow"] - q1["ledger"]) / q1["volume"]},
+          roofline={"bound": "hbm", "achieved": 32.0 * cells / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": 32.0 * cells / secs / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "whole coarse step (k_step coarse and patches, frame, feedback, time step)"})
+
+
+def bench_ensemble(args):
+    """Batched ensemble: 256 floodplain scenarios, sides log-uniform in
+    [256, 2048], hydrographs and gate settings drawn per scenario."""
+    import torch
+    from paper_1705_00614_amd import scenarios as S
+    from paper_1705_00614_amd import swe
+    ens = S.ensemble(n=256)
+    steps = args.steps if args.steps != 9900 else 2000
+    warm = args.warmup if args.warmup != 100 else 20
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = swe.Batch(ens)
+        q0 = b.query()
+        b.run(warm)
+        w0 = b.work()
+        kms = b.run_timed(steps)
+        w1 = b.work()
+        q1 = b.query()
+    cells = w1["cell_steps"] - w0["cell_steps"]
+    secs = kms * 1e-3
+    total = sum(sc["nx"] * sc["ny"] for sc in ens)
+    bal = np.max(np.abs(q1["mass"] - q0["mass"] - q1["inflow"] - q1["ledger"]) / q1["mass"])
+    _line("batched ensemble: active cell-updates/s over all scenarios", cells / secs / 1e9, "Gcell-updates/s",
+          steps, warm, kms / steps, "f32",
+          {"workload": "ensemble: 256 floodplain scenarios, sides 256..2048 log-uniform (%d cells), steps %d..%d"
+                       % (total, warm, warm + steps),
+           "active_tile_fraction": (w1["tile_steps"] - w0["tile_steps"]) / steps / w1["total_tiles"],
+           "grid_cell_updates_per_s": total * steps / secs / 1e9,
+           "timing": "per-launch HIP events (one launch per step for all scenarios)",
+           "volume_balance_rel_max": float(bal)},
+          roofline={"bound": "hbm", "achieved": 32.0 * cells / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": 32.0 * cells / secs / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "swe::k_batch_step<float,32,32>", "mean_launch_us": kms * 1e3 / steps})
+
+
+def bench_learned(args):
+    """Learned coarse correction: train on fine 4096^2 runs (25 m), coarse
+    1024^2 (100 m), ratio 4; error and speed against the fine solve on
+    held-out seeds."""
+    import torch
+    from paper_1705_00614_amd import learned as LC
+    from paper_1705_00614_amd import scenarios as S
+    from paper_1705_00614_amd import swe
+    n, r, m = args.n, 4, 4
+    ntrain, nheld = 8, 4
+    mk = lambda seed: S.floodplain(n=n, h=25.0, seed=seed, q_peak=3.0e4, t_peak=1800.0, sigma_t=600.0)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        ntiles = (n // r // 32) ** 2
+        net = LC.make_net(32, max(ntiles, 64))
+        net.data(100000)
+        for k in range(ntrain):
+            LC.collect(net, mk(2000 + k), r, m, intervals=60, gap=24)
+            print("learned: collected seed %d, %d crops" % (2000 + k, net.data_count()), file=sys.stderr, flush=True)
+        count = net.data_count()
+        net.set_out_scale(np.maximum(LC.label_scale(net), 1e-6))
+        net.set_params(LC.initial_params(1))
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        losses = net.fit(2000, 64, 1e-3, seed=1)
+        torch.cuda.synchronize()
+        fit_s = time.perf_counter() - f0
+        print("learned: fit %.1f s, loss %.3g -> %.3g" % (fit_s, np.mean(losses[:50]), np.mean(losses[-50:])),
+              file=sys.stderr, flush=True)
+        errs = []
+        for k in range(nheld):
+            errs.append(LC.compare(net, mk(3000 + k), r, m, intervals=150))
+            print("learned: held-out seed %d %s" % (3000 + k, errs[-1]), file=sys.stderr, flush=True)
+        tim = LC.timing(net, mk(3000), r, sim_seconds=900.0)
+    speed = (tim["fine"]["wall"] / tim["fine"]["sim"]) / (tim["learned"]["wall"] / tim["learned"]["sim"])
+    _line("learned coarse: speedup over the fine solve (same simulated time)", speed, "x", tim["learned"]["steps"],
+          0, tim["learned"]["wall"] * 1e3 / tim["learned"]["steps"], "bf16/f32",
+          {"workload": "floodplain %dx%d at 25 m (fine) vs %dx%d at 100 m + network; %d training runs, %d held out"
+                       % (n, n, n // r, n // r, ntrain, nheld),
+           "training_crops": count, "fit_iterations": 2000, "fit_seconds": fit_s,
+           "loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
+           "depth_error_plain_coarse": [e["err_plain"] for e in errs],
+           "depth_error_learned_coarse": [e["err_learned"] for e in errs],
+           "fine_wall_s": tim["fine"]["wall"], "learned_wall_s": tim["learned"]["wall"],
+           "simulated_seconds": tim["fine"]["sim"], "total_wall_s": time.perf_counter() - t0})
 
 
 if __name__ == "__main__":

@@ -1769,6 +1769,22 @@ int swe_nest_query(swe_nest_t* n, double* t, double* volume, double* inflow, dou
     return 0;
 }
 
+int swe_nest_work(swe_nest_t* n, long long* coarse_cells, long long* fine_cells) {
+    if (!n) { set_err("swe_nest_work: NULL handle"); return SWE_EINVAL; }
+    Ctrl c;
+    int rc = sync_ctrl(n->c, &c);
+    if (rc) return rc;
+    long long fine = 0;
+    for (swe_t* q : n->p) {
+        Ctrl f;
+        if ((rc = sync_ctrl(q, &f))) return rc;
+        fine += f.cells;
+    }
+    if (coarse_cells) *coarse_cells = c.cells;
+    if (fine_cells) *fine_cells = fine;
+    return 0;
+}
+
 int swe_nest_get_coarse(swe_nest_t* n, double* H, double* Qx, double* Qy) {
     if (!n) { set_err("swe_nest_get_coarse: NULL handle"); return SWE_EINVAL; }
     return swe_get_state(n->c, H, Qx, Qy);

@@ -20,11 +20,14 @@ IN_SCALE = np.array([5.0, 1.0, 1.0, 10.0, 0.05, 1.0])
 
 
 def coarsen(sc, r):
-    """Coarse scenario of a fine one: means of r x r cells; no inlet cells are
-    dropped (the inlet rectangle is scaled by 1/r and must align)."""
+    """Coarse scenario of a fine one: means of r x r cells; the inlet
+    rectangle is scaled by 1/r; the step cap tau_max grows with the cell size
+    (same cap in Courant units)."""
     ny, nx = sc["ny"] // r, sc["nx"] // r
     R = lambda a: np.asarray(a, dtype=np.float64)[:ny * r, :nx * r].reshape(ny, r, nx, r).mean(axis=(1, 3))
     p = dict(sc["params"])
+    if p.get("tau_max"):
+        p["tau_max"] = p["tau_max"] * r      # same cap in Courant units
     if p.get("inlet"):
         i0, j0, ni, nj = p["inlet"]
         p["inlet"] = (i0 // r, j0 // r, max(ni // r, 1), max(nj // r, 1))
@@ -37,9 +40,22 @@ def make_net(tile, max_crops, out_scale=None):
     return swe.Net(tile, max_crops, IN_SCALE, np.ones(6) if out_scale is None else out_scale)
 
 
-def collect(net, fine_sc, r, m, intervals, skip=0):
+def initial_params(seed=0):
+    """Packed starting weights: uniform in +-sqrt(6 / (9 in + 9 out)) per
+    layer (Glorot), the output layer scaled by 0.1, biases zero."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    parts = []
+    for k, (ci, co) in enumerate(swe.LC_LAYERS):
+        lim = np.sqrt(6.0 / (9.0 * (ci + co))) * (0.1 if k == len(swe.LC_LAYERS) - 1 else 1.0)
+        parts.append(rng.uniform(-lim, lim, size=co * ci * 9))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts)
+
+
+def collect(net, fine_sc, r, m, intervals, skip=0, gap=0):
     """Run the fine scenario and add the crops and labels of `intervals`
-    coarse intervals (after `skip` fine CFL steps) to the network's data set."""
+    coarse intervals (after `skip` fine CFL steps, and `gap` more between
+    intervals) to the network's data set."""
     f = swe.Solver(fine_sc)
     if skip:
         f.run(skip)
@@ -47,7 +63,9 @@ def collect(net, fine_sc, r, m, intervals, skip=0):
     c = swe.Solver(coarsen(fine_sc, r))
     c.enable_line_taps(1)
     taus = []
-    for _ in range(intervals):
+    for k in range(intervals):
+        if gap and k:
+            f.run(gap)
         taus.append(net.collect(f, c, r, m))
     f.close()
     c.close()

@@ -195,11 +195,13 @@ def ensemble(n=256, seed0=1000, side_min=256, side_max=2048, h=25.0, gates_max=1
     return out
 
 
-def _bilinear_up(z, r):
-    """Cell-centred bilinear upsampling by r with edge clamping."""
+def _bilinear_window(z, r, fi0, fj0, nxf, nyf):
+    """Cell-centred bilinear interpolation of the coarse field z at the fine
+    cells [fi0, fi0+nxf) x [fj0, fj0+nyf) of a grid refined by r (edge
+    clamping)."""
     ny, nx = z.shape
-    x = (np.arange(nx * r) + 0.5) / r - 0.5
-    y = (np.arange(ny * r) + 0.5) / r - 0.5
+    x = (np.arange(fi0, fi0 + nxf) + 0.5) / r - 0.5
+    y = (np.arange(fj0, fj0 + nyf) + 0.5) / r - 0.5
     x0 = np.clip(np.floor(x).astype(int), 0, nx - 1)
     y0 = np.clip(np.floor(y).astype(int), 0, ny - 1)
     x1 = np.clip(x0 + 1, 0, nx - 1)
@@ -214,7 +216,8 @@ def _bilinear_up(z, r):
 def nest(coarse, boxes, r=4, seed=0, detail=0.5):
     """Nested-grid inputs: a coarse scenario and refined patches over the
     coarse boxes (ci0, cj0, cw, ch).  The fine bed is the bilinear
-    upsampling of the coarse bed plus fBm detail of `detail` metres; each
+    upsampling of the coarse bed plus fBm detail of `detail` metres (drawn
+    per patch window); each
     covered coarse cell takes the mean of its r x r fine bed cells, so that
     the coarse grid sees the fine bed's volume.  Fine initial water fills to
     the parent coarse cell's level where that cell is wet (still water); the
@@ -225,21 +228,20 @@ def nest(coarse, boxes, r=4, seed=0, detail=0.5):
     G = NEST_FRAME
     c = dict(coarse)
     bc = np.array(coarse["b"], dtype=np.float64)
+    b_orig = bc.copy()
     Hc = np.array(coarse["H0"], dtype=np.float64)
     Qxc = np.array(coarse["Qx0"], dtype=np.float64)
     Qyc = np.array(coarse["Qy0"], dtype=np.float64)
     nmc = np.asarray(coarse["n_manning"], dtype=np.float64)
-    up = _bilinear_up(bc, r)
     rng = _rng(seed)
-    d = fbm(up.shape[0], up.shape[1], 0.8, rng.integers(2**63), detail)
-    bf_all = up + d - 0.5 * detail
     eta_c = np.where(Hc > 0.0, Hc + bc, -np.inf)
     patches = []
     for (ci0, cj0, cw, ch) in boxes:
-        # extended fine window in global fine indices
+        # extended fine window in global fine indices; fBm detail of its own
         fi0, fj0 = ci0 * r - G, cj0 * r - G
         nxf, nyf = cw * r + 2 * G, ch * r + 2 * G
-        bf = bf_all[fj0:fj0 + nyf, fi0:fi0 + nxf].copy()
+        d = fbm(nyf, nxf, 0.8, rng.integers(2**63), detail)
+        bf = _bilinear_window(b_orig, r, fi0, fj0, nxf, nyf) + d - 0.5 * detail
         par_i = np.floor_divide(np.arange(nxf) + fi0, r)
         par_j = np.floor_divide(np.arange(nyf) + fj0, r)
         PJ, PI = np.meshgrid(par_j, par_i, indexing="ij")
@@ -262,3 +264,33 @@ def nest(coarse, boxes, r=4, seed=0, detail=0.5):
 # Frame width of a patch in fine cells: one more than the reach of one step
 # of the scheme (4 cells).
 NEST_FRAME = 5
+
+
+def nest_floodplain(n=2048, h=50.0, seed=1, r=4, box=512, precision=32):
+    """Nested-grid workload: an n^2 floodplain at h metres with two refined
+    patches of box^2 coarse cells (ratio r) centred on the two bends of the
+    channel with the largest curvature (away from the inlet)."""
+    sc = floodplain(n=n, h=h, seed=seed, precision=precision)
+    _, _, _, yc = floodplain_terrain(n, h, seed)
+    x = np.arange(n)
+    curv = np.abs(np.gradient(np.gradient(yc)))
+    i0_min = sc["params"]["inlet"][0] + sc["params"]["inlet"][2] + 2
+    order = np.argsort(curv)[::-1]
+    m = -(-NEST_FRAME // r)
+    half = box // 2
+    centres = []
+    for i in order:
+        if i - half < max(i0_min, m) or i + half + m > n:
+            continue
+        if any(abs(i - c) < box + 1 for c in centres):
+            continue
+        centres.append(int(i))
+        if len(centres) == 2:
+            break
+    boxes = []
+    for i in sorted(centres):
+        j = int(np.clip(yc[i] / h - half, m, n - box - m))
+        boxes.append((i - half, j, box, box))
+    out = nest(sc, boxes, r=r, seed=seed + 7)
+    out["coarse"]["name"] = "nest-floodplain-%d-r%d" % (n, r)
+    return out

@@ -90,6 +90,8 @@ EXPORTS = {
     "swe_nest_get_coarse": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_nest_get_patch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]),
     "swe_nest_destroy": (None, [ctypes.c_void_p]),
+    "swe_nest_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(ctypes.c_longlong)]),
     "swe_set_correction": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "swe_hold_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "swe_enable_line_taps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -491,6 +493,11 @@ class Nest:
         H, Qx, Qy = (np.empty(self.shape) for _ in range(3))
         _check(load().swe_nest_get_coarse(self._h, _ptr(H), _ptr(Qx), _ptr(Qy)))
         return H, Qx, Qy
+
+    def work(self):
+        c, f = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(load().swe_nest_work(self._h, ctypes.byref(c), ctypes.byref(f)))
+        return dict(coarse_cells=c.value, fine_cells=f.value)
 
     def patch_state(self, k):
         shp = self.pshapes[k]
