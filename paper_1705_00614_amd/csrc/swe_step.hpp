@@ -523,22 +523,42 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
         return gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     };
 
-    // ---- load tile + 5
+    // ---- load tile + 5: every load of the thread is issued before any is
+    // used (one memory round trip, not one per row of the loop); c_f goes to
+    // LM, where P1 reads it and leaves its friction factor
     {
-        constexpr int RW = TX + 2 * HALO, NL = RW * G::H;
-        int act = 0;
-        for (int k = tid; k < NL; k += NT) {
+        constexpr int RW = TX + 2 * HALO, NL = RW * G::H, J = (NL + NT - 1) / NT;
+        real vH[J], vX[J], vY[J], vB[J], vC[J];
+        int vf[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * NT;
+            if (k >= NL) continue;
             const int x = k % RW - HALO, y = k / RW - HALO;
             int gx = tx0 + x, gy = ty0 + y, fx = 0, fy = 0;
             if constexpr (EDGE) { gx = mirror(gx, nx, fx); gy = mirror(gy, ny, fy); }
             const int gi = gy * nx + gx;
-            const real H = a.Hi[gi];
-            real qx = a.Qxi[gi], qy = a.Qyi[gi];
-            if constexpr (EDGE) { if (fx & 1) qx = -qx; if (fy & 1) qy = -qy; }
+            vH[j] = a.Hi[gi];
+            vX[j] = a.Qxi[gi];
+            vY[j] = a.Qyi[gi];
+            vB[j] = a.bed[gi];
+            vC[j] = a.cf[gi];
+            vf[j] = (fx & 1) | ((fy & 1) << 1);
+        }
+        int act = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * NT;
+            if (k >= NL) continue;
+            const int x = k % RW - HALO, y = k / RW - HALO;
+            const real H = vH[j];
+            real qx = vX[j], qy = vY[j];
+            if constexpr (EDGE) { if (vf[j] & 1) qx = -qx; if (vf[j] & 2) qy = -qy; }
             const bool w = H > eps;
             const int s = G::at(x, y);
             L.H[s] = H;
-            L.B[s] = a.bed[gi];
+            L.B[s] = vB[j];
+            L.LM[s] = vC[j];
             L.UX[s] = w ? Mth<real>::div(qx, H) : real(0);
             L.UY[s] = w ? Mth<real>::div(qy, H) : real(0);
             // K1 rule at layer n: own cells and outer face neighbours (no corners)
@@ -607,7 +627,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real Gy = (al * (e[2][1] - e[0][1]) + be * ((e[2][2] - e[0][2]) + (e[2][0] - e[0][0]))) * a.ih;
                 const int gx = tx0 + x0 + i, gy = ty0 + y;
                 const bool ins = inside(x0 + i, y);
-                const real cf = ins ? a.cf[gy * nx + gx] : real(0);
+                const real cf = ins ? L.LM[G::at(x0 + i, y)] : real(0);
                 const real lam0 = Mth<real>::friction(cf, wc ? Hc : real(1));
                 Nb4<real> nb;
                 nb.ux[0] = ux[c - 1]; nb.uy[0] = uy[c - 1]; nb.w[0] = He[1][c - 1] > real(0);
