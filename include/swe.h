@@ -139,11 +139,18 @@ int    swe_run_timed(swe_t* s, long nsteps, double* kernel_ms);
 /* Flux corrections added to the stage III fluxes (Sec. 2.3) of every later
  * step, before the final update: dE through the east face and dN through the
  * north face of each cell, each 3 planes of nx*ny (mass, x-momentum,
- * y-momentum) row-major, FP64 on the host, copied.  The mass part is dropped
- * where the face's upwind cell is dry after the Lagrangian stage, the
- * momentum part unless both cells are wet; wall faces take none.  One of them NULL means zeros there; both NULL switch the
+ * y-momentum) row-major, FP64 on the host, copied.  After the Lagrangian
+ * stage, the mass part needs the face's upwind cell to be deeper than the
+ * correction depth (eps unless set, see below), the momentum part both
+ * cells; wall faces take none.  One of them NULL means zeros there; both NULL switch the
  * corrections off.  Default tile shapes only; not for grids of a nest. */
 int    swe_set_correction(swe_t* s, const double* dE, const double* dN);
+
+/* Correction depth (default and minimum: eps).  A cell just above eps that
+ * takes a momentum correction, or loses water to a mass correction but keeps
+ * its momentum, gets a velocity Q/H that can set an arbitrarily small CFL
+ * step. */
+int    swe_set_correction_depth(swe_t* s, double hmin);
 
 /* Hold the step length at tau > 0 from the next step on (the CFL step is
  * still recorded but not used; the hydrograph volume follows the clock);
@@ -266,6 +273,10 @@ int    swe_nest_run_timed(swe_nest_t* n, long coarse_steps, double* kernel_ms);
  * time steps of the next coarse step and substeps [s].  Any may be NULL. */
 int    swe_nest_query(swe_nest_t* n, double* t, double* volume, double* inflow, double* ledger,
                       long* steps, double* dt_coarse, double* dt_fine);
+
+/* Processed cell-steps so far: coarse grid (active tiles) and all patch
+ * substeps (every cell of the extended patches).  Either may be NULL. */
+int    swe_nest_work(swe_nest_t* n, long long* coarse_cells, long long* fine_cells);
 
 /* Host FP64 copy of the coarse state (nx*ny each) or of patch k's interior
  * ((r*ch) x (r*cw) each); any may be NULL. */

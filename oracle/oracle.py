@@ -79,6 +79,7 @@ def lib():
                                     _c_double_p, _c_double_p]
         L.orc_cell_speeds.argtypes = [ctypes.c_void_p, _c_double_p]
         L.orc_set_correction.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p]
+        L.orc_set_correction_depth.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_tau_from_speed.restype = ctypes.c_double
         L.orc_tau_from_speed.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_hydrograph_volume.restype = ctypes.c_double
@@ -175,6 +176,10 @@ class OracleSim:
             rc = lib().orc_set_correction(self._h, _dp(self._corr[0]), _dp(self._corr[1]))
         if rc:
             raise RuntimeError("orc_set_correction failed: %d" % rc)
+
+    def set_correction_depth(self, hmin):
+        if lib().orc_set_correction_depth(self._h, float(hmin)):
+            raise ValueError("invalid correction depth")
 
     def tau_from_speed(self, smax):
         return lib().orc_tau_from_speed(self._h, float(smax))

@@ -59,6 +59,7 @@ struct orc_sim {
     double *FxH, *FxQn, *FxQt;      /* x-faces (nx+1)*ny */
     double *FyH, *FyQn, *FyQt;      /* y-faces nx*(ny+1) */
     double *corrE, *corrN;          /* flux corrections (3 planes of nx*ny) or NULL */
+    double corr_hmin;               /* depth both cells need for momentum corrections */
     double t, tau_last, ledger, inflow;
     long steps;
 };
@@ -532,17 +533,20 @@ static void riemann(double g, face_state L, face_state R,
 /* Learned flux correction (added to the stage III fluxes before the final
  * update): planes [mass, x-momentum, y-momentum] of the correction through
  * the east (or north) face of cell k, which lies between cells cl and cr.
- * The mass correction is dropped where its donor (upwind) cell is dry after
- * the Lagrangian stage, the momentum correction unless both cells are wet (a
- * film would otherwise gain momentum without water); wall faces take none. */
+ * With the correction depth hc = max(eps, corr_hmin) after the Lagrangian
+ * stage, the mass correction needs a donor (upwind) cell deeper than hc, the
+ * momentum correction two cells deeper than hc (a film would otherwise gain
+ * momentum without water, or lose water but keep its momentum); wall faces
+ * take none. */
 static void add_correction(const orc_sim* s, const double* corr, long k, long cl, long cr,
                            double* fH, double* fN, double* fT, int xface)
 {
     const long n = (long)s->nx * s->ny;
     const double dH = corr[k], dX = corr[n + k], dY = corr[2 * n + k];
     const long donor = dH > 0.0 ? cl : cr;
-    if (s->wett[donor]) *fH += dH;
-    if (s->wett[cl] && s->wett[cr]) {
+    const double hm = s->corr_hmin > s->p.eps ? s->corr_hmin : s->p.eps;
+    if (s->Ht[donor] > hm) *fH += dH;
+    if (s->Ht[cl] > hm && s->Ht[cr] > hm) {
         *fN += xface ? dX : dY;
         *fT += xface ? dY : dX;
     }
@@ -765,6 +769,13 @@ int orc_get_faces(const orc_sim* s, int dir, double* FH, double* Fqn, double* Fq
     if (FH) memcpy(FH, a, (size_t)n * sizeof(double));
     if (Fqn) memcpy(Fqn, b, (size_t)n * sizeof(double));
     if (Fqt) memcpy(Fqt, c, (size_t)n * sizeof(double));
+    return 0;
+}
+
+int orc_set_correction_depth(orc_sim* s, double hmin)
+{
+    if (!s || !(hmin >= 0.0)) return ORC_EINVAL;
+    s->corr_hmin = hmin;
     return 0;
 }
 

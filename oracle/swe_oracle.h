@@ -78,11 +78,13 @@ double orc_next_tau(orc_sim* s);
 int    orc_cell_speeds(orc_sim* s, double* out);
 /* Flux corrections added to every later step's stage III fluxes: dE through
  * the east face and dN through the north face of each cell, 3 planes of
- * nx*ny each (mass, x-momentum, y-momentum); the mass part is dropped where
- * the upwind cell is dry after the Lagrangian stage, the momentum part
- * unless both cells are wet; wall faces take none.
+ * nx*ny each (mass, x-momentum, y-momentum); after the Lagrangian stage the
+ * mass part needs an upwind cell deeper than the correction depth (eps
+ * unless set), the momentum part two such cells; wall faces take none.
  * Both NULL clears them. */
 int    orc_set_correction(orc_sim* s, const double* dE, const double* dN);
+/* Correction depth (default and minimum: eps). */
+int    orc_set_correction_depth(orc_sim* s, double hmin);
 double orc_tau_from_speed(const orc_sim* s, double smax);
 
 double orc_mass(const orc_sim* s);      /* h^2 * sum H, compensated FP64 sum */

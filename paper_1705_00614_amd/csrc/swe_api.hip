@@ -172,6 +172,7 @@ struct swe_s {
     void* corrE = nullptr;
     void* corrN = nullptr;
     bool corr = false;
+    double corr_hmin = 0.0;
     // line taps (training labels): coarsening factor and buffers
     int tap_r = 0;
     void* tapx = nullptr;
@@ -234,6 +235,7 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->tap = (real*)s->tap;
     a->corrE = (const real*)s->corrE;
     a->corrN = (const real*)s->corrN;
+    a->corr_hmin = (real)(s->corr_hmin > p.eps ? s->corr_hmin : p.eps);
     a->tap_r = s->tap_r;
     a->tapx = (real*)s->tapx;
     a->tapy = (real*)s->tapy;
@@ -878,6 +880,14 @@ static int ensure_corr_buffers(swe_t* s) {
     HIPCHK(hipMemsetAsync(s->corrE, 0, n * s->rsize, s->stream));
     HIPCHK(hipMemsetAsync(s->corrN, 0, n * s->rsize, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    build_args(s);
+    drop_graph(s);
+    return 0;
+}
+
+int swe_set_correction_depth(swe_t* s, double hmin) {
+    if (!s || !(hmin >= 0.0) || !std::isfinite(hmin)) { set_err("swe_set_correction_depth: invalid arguments"); return SWE_EINVAL; }
+    s->corr_hmin = hmin;
     build_args(s);
     drop_graph(s);
     return 0;

@@ -112,6 +112,7 @@ struct Args {
     // 3 planes (mass, x-momentum, y-momentum) of nx*ny (CORR kernels only)
     const real* corrE;
     const real* corrN;
+    real corr_hmin;      // correction depth (>= eps): upwind cell for mass, both cells for momentum
     // face taps on the lines of a grid coarsened by tap_r (TAP kernels with
     // tap_r > 0): tau * flux of the x faces at columns that are multiples of
     // tap_r, per row, in tapx [3][ny][nx/tap_r + 1], and of the y faces at
@@ -489,18 +490,19 @@ __device__ __forceinline__ void tap_lines(const Args<real>& a, int gx, int gy, r
 }
 
 // Learned flux correction of one face (mass, x-momentum, y-momentum planes of
-// corr at cell index k): the mass part only where its upwind cell (lo side for
-// a positive correction, else hi side) is wet after the Lagrangian stage, the
-// momentum part only where both cells are.  A face dry on both sides takes
-// none, so the dry-wave shortcuts of the flux passes stay exact.
+// corr at cell index k), with the correction depth corr_hmin (>= eps) after
+// the Lagrangian stage: the mass part only where its upwind cell (lo side for
+// a positive correction, else hi side) is deeper, the momentum part only
+// where both cells are.  A face dry on both sides takes none, so the dry-wave
+// shortcuts of the flux passes stay exact.
 template <typename real>
 __device__ __forceinline__ void add_correction(const Args<real>& a, const real* corr, int k, real Hlo, real Hhi,
                                                real& FH, real& Fn, real& Ft, bool xface) {
     const int n = a.nx * a.ny;
     const real dH = corr[k], dX = corr[n + k], dY = corr[2 * n + k];
     const real Hd = dH > real(0) ? Hlo : Hhi;
-    const bool both = Hlo > a.eps && Hhi > a.eps;
-    FH += Hd > a.eps ? dH : real(0);
+    const bool both = Hlo > a.corr_hmin && Hhi > a.corr_hmin;
+    FH += Hd > a.corr_hmin ? dH : real(0);
     Fn += both ? (xface ? dX : dY) : real(0);
     Ft += both ? (xface ? dY : dX) : real(0);
 }

@@ -17,6 +17,9 @@ import numpy as np
 from . import swe
 
 IN_SCALE = np.array([5.0, 1.0, 1.0, 10.0, 0.05, 1.0])
+# depth both cells of a face need before the network's momentum correction
+# applies: below it a cell would gain momentum without the water to carry it
+CORR_DEPTH = 0.05
 
 
 def coarsen(sc, r):
@@ -94,6 +97,7 @@ def compare(net, fine_sc, r, m, intervals, skip=0):
     plain.restrict_from(f, r)
     lrn.restrict_from(f, r)
     net.attach(lrn)
+    lrn.set_correction_depth(CORR_DEPTH)
     for _ in range(intervals):
         tau_c = min(plain.next_dt(), lrn.next_dt(), m * f.next_dt())
         tau_f = tau_c / m
@@ -128,6 +132,7 @@ def timing(net, fine_sc, r, sim_seconds, skip=0):
     g = swe.Solver(csc)
     g.restrict_from(f, r)
     net.attach(g)
+    g.set_correction_depth(CORR_DEPTH)
     res = {}
     for name, s in (("fine", f), ("learned", g)):
         t0 = s.time()

@@ -93,6 +93,7 @@ EXPORTS = {
     "swe_nest_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.POINTER(ctypes.c_longlong)]),
     "swe_set_correction": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
+    "swe_set_correction_depth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "swe_hold_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "swe_enable_line_taps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "swe_zero_line_taps": (ctypes.c_int, [ctypes.c_void_p]),
@@ -327,6 +328,9 @@ class Solver:
     def restrict_from(self, fine, r):
         """This (coarse) grid's layer = r x r means of fine's layer."""
         _check(load().swe_restrict(fine._h, self._h, int(r)))
+
+    def set_correction_depth(self, hmin):
+        _check(load().swe_set_correction_depth(self._h, float(hmin)))
 
     def set_correction(self, dE, dN):
         """Flux corrections (3, ny, nx) through the east and north faces, or None."""

@@ -139,8 +139,8 @@ def _corr_fields(sc, seed, amp):
     return out
 
 
-@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
-def test_corrected_step_matches_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,hmin", [(64, 1e-10, 0.0), (64, 1e-10, 0.5), (32, 1e-4, 0.0)])
+def test_corrected_step_matches_oracle(prec, tol, hmin):
     from oracle import oracle as orc
     from paper_1705_00614_amd import scenarios as S
     sc = S.floodplain(n=96, h=50.0, seed=7, q_peak=2000.0, t_peak=200.0, sigma_t=150.0, inlet_cells=6,
@@ -160,6 +160,9 @@ def test_corrected_step_matches_oracle(prec, tol):
     g.set_correction(dE, dN)
     o = orc.OracleSim(sc)
     o.set_correction(dE, dN)
+    if hmin:
+        g.set_correction_depth(hmin)
+        o.set_correction_depth(hmin)
     g.run(40)                       # one graph of 32 steps plus single launches
     o.run(40)
     (H, Qx, Qy), (Ho, Qxo, Qyo) = g.state(), o.state()

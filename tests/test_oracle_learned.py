@@ -188,3 +188,37 @@ def test_momentum_correction_needs_both_cells_wet():
     dQy = b.state()[2] - a.state()[2]
     assert dQx[5, 1] == 0.0 and dQx[5, 0] == 0.0
     assert abs(dQy[7, 3] + r * 0.05) <= 1e-14 and abs(dQy[7, 4] - r * 0.05) <= 1e-14
+
+
+def test_momentum_correction_depth_threshold():
+    sc = _wet_basin()
+    n = sc["nx"]
+    sc["H0"][7, 4] = 0.01          # wet but shallow
+    a, b = orc.OracleSim(sc), orc.OracleSim(sc)
+    b.set_correction_depth(0.05)
+    tau = 0.1 * a.next_tau()
+    dE = np.zeros((3, n, n))
+    dE[1, 7, 3] = 0.05             # face between (7, 3) (deep) and (7, 4) (shallow): dropped
+    dE[1, 2, 3] = 0.05             # deep-deep face: kept
+    dE[0, 7, 3] = 0.01             # mass from the deep (7, 3) into the shallow (7, 4): kept
+    dE2 = np.zeros((3, n, n))
+    dE2[0, 7, 4] = 0.01            # mass out of the shallow (7, 4) through its east face: dropped
+    a.set_correction(dE, None)
+    b.set_correction(dE, None)
+    a.step(tau)
+    b.step(tau)
+    r = tau / sc["h"]
+    c = orc.OracleSim(sc)
+    c.step(tau)
+    dQa = a.state()[1] - c.state()[1]
+    dQb = b.state()[1] - c.state()[1]
+    assert abs(dQa[7, 3] + r * 0.05) <= 1e-14          # eps threshold: applied
+    assert abs(dQb[7, 3]) <= 1e-14 and abs(dQb[7, 4]) <= 1e-14
+    assert abs(dQb[2, 3] + r * 0.05) <= 1e-14
+    dHb = b.state()[0] - c.state()[0]
+    assert abs(dHb[7, 3] + r * 0.01) <= 1e-14
+    d = orc.OracleSim(sc)
+    d.set_correction_depth(0.05)
+    d.set_correction(dE2, None)
+    d.step(tau)
+    assert np.array_equal(d.state()[0], c.state()[0])
