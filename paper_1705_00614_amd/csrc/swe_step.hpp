@@ -319,7 +319,7 @@ __device__ double cfl_tau_of(const Args<real>& a, double S) {
 
 // Time step tau of the next step and its hydrograph volume and source depth.
 template <typename real>
-__device__ void set_next_step(const Args<real>& a, Ctrl* c, double tau) {
+__device__ __forceinline__ void set_next_step(const Args<real>& a, Ctrl* c, double tau) {
     if (!(tau >= a.tau_min) || !(tau < __builtin_inf())) c->err = -5;
     c->tau = tau;
     double dV = 0.0;
@@ -332,7 +332,7 @@ __device__ void set_next_step(const Args<real>& a, Ctrl* c, double tau) {
 // Bookkeeping of a new layer with maximum speed S: its CFL step and the next
 // step's scalars (with hold, the step length set from outside is kept).
 template <typename real>
-__device__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
+__device__ __forceinline__ void next_step_scalars(const Args<real>& a, Ctrl* c, double S) {
     const double tau = cfl_tau_of(a, S);
     c->speed = S;
     c->tau_cfl = tau;
@@ -346,6 +346,17 @@ __device__ __forceinline__ void close_segments(Ctrl* c, int* hot, int slot) {
     c->seg_off[slot][0] = 0;
     for (int g = 0; g < NSEG; ++g) {
         off += hot[hot_seg(slot, g)];
+        c->seg_off[slot][g + 1] = off;
+    }
+}
+
+// The same from segment counters already read (stores only).
+__device__ __forceinline__ void close_segments_from(Ctrl* c, const int (&n)[NSEG], int slot) {
+    int off = 0;
+    c->seg_off[slot][0] = 0;
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g) {
+        off += n[g];
         c->seg_off[slot][g + 1] = off;
     }
 }
@@ -375,6 +386,18 @@ __device__ __forceinline__ void append_tiles(int cand, int sid, int tile_base, i
     base = __shfl(base, 0, 64);
     if (ok) lists[(slot * NSEG + grp) * cap + base + __popcll(m & ((1ull << lane) - 1ull))] = pack_entry(sid, cand);
 }
+
+// Next-list bookkeeping of the tile being stepped (grids that skip dry
+// tiles).  Its atomics are interleaved with the stages of the tile so that
+// their latency hides behind the arithmetic: a tile K1-active at layer n
+// appends itself right after the load stage, and the stamps of its four
+// neighbours are read before the last flux pass, so that at the end only
+// neighbours not yet in the list cost an atomic.
+struct ListCtx {
+    int* stamp; int* lists; int* hot;
+    int cap, slot, grp, gen, sid, tile_base, tile, ntx, nty;
+    bool on;
+};
 
 template <typename real>
 __device__ __forceinline__ bool is_src(const Args<real>& a, int gx, int gy) {
@@ -510,7 +533,7 @@ __device__ __forceinline__ void add_correction(const Args<real>& a, const real* 
 template <typename real, int TX, int TY, int NT, int LIM, bool EDGE, int MODE>
 __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, int ty0,
                           real tau, real sdep, real& vmax, bool& bad, double& msum, double& lsum,
-                          int& bits) {
+                          int& bits, const ListCtx& lx, int& nbst) {
     using G = Geo<TX, TY>;
     constexpr int W = G::W;
     constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR;
@@ -570,6 +593,11 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
         }
         if (__syncthreads_or(act)) bits |= 64;
     }
+    // self-append of a tile K1-active at layer n: stamp now, slot after P1,
+    // entry after P2 (thread 0)
+    const bool early = lx.on && tid == 0 && (bits & 64);
+    int e_old = lx.gen, e_base = 0;
+    if (early) e_old = atomicMax(&lx.stamp[lx.tile_base + lx.tile], lx.gen);
 
     // ---- P1: forces at t_n and predictor on tile + 4, runs of 4 along x
     {
@@ -652,6 +680,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
         }
         __syncthreads();
+        if (early && e_old < lx.gen) e_base = atomicAdd(&lx.hot[hot_seg(lx.slot, lx.grp)], 1);
         if constexpr (EDGE) {
             fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -4, TX + 4, -4, TY + 4, L.HX, L.HY, nullptr,
                                           /*sgx*/ 1, /*sgy*/ 2);
@@ -737,6 +766,8 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
         }
         __syncthreads();
+        if (early && e_old < lx.gen)
+            lx.lists[(lx.slot * NSEG + lx.grp) * lx.cap + e_base] = pack_entry(lx.sid, lx.tile);
         if constexpr (EDGE) {
             fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -3, TX + 3, -3, TY + 3, L.UX, L.UY, L.LM,
                                           /*sgx*/ 2, /*sgy*/ 4);
@@ -785,6 +816,18 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
         }
         __syncthreads();
+    }
+
+    // stamps of the four neighbours (lanes 1..4 of wave 0: W, E, S, N); a
+    // stale value only costs an atomic at the end
+    nbst = lx.gen;
+    if (lx.on && tid >= 1 && tid <= 4) {
+        const int ti = lx.tile % lx.ntx, tj = lx.tile / lx.ntx;
+        const int nb = tid == 1 ? (ti > 0 ? lx.tile - 1 : -1)
+                     : tid == 2 ? (ti < lx.ntx - 1 ? lx.tile + 1 : -1)
+                     : tid == 3 ? (tj > 0 ? lx.tile - lx.ntx : -1)
+                                : (tj < lx.nty - 1 ? lx.tile + lx.ntx : -1);
+        if (nb >= 0) nbst = lx.stamp[lx.tile_base + nb];
     }
 
     // ---- FY + final update: columns -1..TX, runs of 4 cells along y
@@ -966,12 +1009,18 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
         double msum = 0.0, lsum = 0.0;
-        int bits = 0;
+        int bits = 0, nbst = gen;
+        // the tile's clamp ledger is read now and written back at the end
+        const double led = tid == 0 ? a.ledger[tile] : 0.0;
+        const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
+                         a.skip != 0};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
+                                                         lx, nbst);
         else
-            tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
+                                                          lx, nbst);
         // block reductions: flags, volume and ledger partials
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
@@ -987,18 +1036,20 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
                 double ms = 0.0, ls = 0.0;
                 for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; }
                 a.mass[tile] = ms;
-                a.ledger[tile] += ls * a.h_d * a.h_d;
+                a.ledger[tile] = led + ls * a.h_d * a.h_d;
             }
             if (a.skip) {
-                // next list: this tile if K1-active at layer n or n+1, and the
-                // neighbours facing its wet edges (layer n+1)
+                // next list: this tile if K1-active at layer n (appended
+                // already) or n+1, and the neighbours facing its wet edges
+                // (layer n+1) unless their stamps show them listed
                 const int ti = tile % a.ntx, tj = tile / a.ntx;
+                const bool fresh = nbst < gen;
                 int cand = -1;
-                if (lane == 0 && (bb & (1 | 32 | 64))) cand = tile;
-                if (lane == 1 && (bb & 2) && ti > 0) cand = tile - 1;
-                if (lane == 2 && (bb & 4) && ti < a.ntx - 1) cand = tile + 1;
-                if (lane == 3 && (bb & 8) && tj > 0) cand = tile - a.ntx;
-                if (lane == 4 && (bb & 16) && tj < a.nty - 1) cand = tile + a.ntx;
+                if (lane == 0 && !(bb & 64) && (bb & (1 | 32))) cand = tile;
+                if (lane == 1 && (bb & 2) && ti > 0 && fresh) cand = tile - 1;
+                if (lane == 2 && (bb & 4) && ti < a.ntx - 1 && fresh) cand = tile + 1;
+                if (lane == 3 && (bb & 8) && tj > 0 && fresh) cand = tile - a.ntx;
+                if (lane == 4 && (bb & 16) && tj < a.nty - 1 && fresh) cand = tile + a.ntx;
                 append_tiles(cand, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp);
             }
         }
@@ -1035,23 +1086,29 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     if (lane == 0) { red_d[0][wv] = (double)vm; red_l[wv] = cs; }
     __syncthreads();
     if (tid == 0) {
+        // every read of the bookkeeping is issued before the first write, so
+        // the reads cost one memory round trip, not one each
+        Ctrl c = *ctrl;
+        int nseg[NSEG];
+#pragma unroll
+        for (int g = 0; g < NSEG; ++g) nseg[g] = a.skip ? a.hot[hot_seg(a.slot ^ 1, g)] : 0;
         double S = 0.0;
         long long cells = 0;
         for (int q = 0; q < NWAVE; ++q) { S = fmax(S, red_d[0][q]); cells += red_l[q]; }
-        const double tau_done = ctrl->tau;
-        ctrl->t += tau_done;
-        ctrl->inflow += ctrl->dV;
-        ctrl->last_tau = tau_done;
-        ctrl->step += 1;
-        ctrl->tiles += count;
-        ctrl->cells += cells;
-        next_step_scalars(a, ctrl, S);
-        if (a.skip) {
-            close_segments(ctrl, a.hot, a.slot ^ 1);
+        const double tau_done = c.tau;
+        c.t += tau_done;
+        c.inflow += c.dV;
+        c.last_tau = tau_done;
+        c.step += 1;
+        c.tiles += count;
+        c.cells += cells;
+        next_step_scalars(a, &c, S);
+        if (c.err) c.err_gate = c.err;
+        *ctrl = c;
+        if (a.skip) close_segments_from(ctrl, nseg, a.slot ^ 1);
+        if (a.skip)
             for (int g = 0; g < NSEG; ++g) a.hot[hot_seg(a.slot, g)] = 0;
-        }
         for (int g = 0; g <= NSEG; ++g) a.hot[hot_done(g)] = 0;
-        if (ctrl->err) ctrl->err_gate = ctrl->err;
         __threadfence();
     }
 }
@@ -1235,12 +1292,17 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
         real vt = real(0);
         bool bad = false;
         double msum = 0.0, lsum = 0.0;
-        int bits = 0;
+        int bits = 0, nbst = gen;
+        const double led = tid == 0 ? a.ledger[tile] : 0.0;
+        const ListCtx lx{a.stamp, ba.lists, ba.hot, ba.list_cap, ba.slot ^ 1, grp, gen, sid, a.tile_base, tile,
+                         a.ntx, a.nty, a.skip != 0};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits,
+                                                               lx, nbst);
         else
-            tile_step<real, TX, TY, NT, LIM, false, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits);
+            tile_step<real, TX, TY, NT, LIM, false, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits,
+                                                                lx, nbst);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         bits |= __any(bad) ? 128 : 0;
@@ -1257,18 +1319,19 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
                 double ms = 0.0, ls = 0.0, vm = 0.0;
                 for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; vm = fmax(vm, red_d[2][q]); }
                 a.mass[tile] = ms;
-                a.ledger[tile] += ls * a.h_d * a.h_d;
+                a.ledger[tile] = led + ls * a.h_d * a.h_d;
                 if (vm > 0.0) atomic_max_prep(c, (real)vm);
                 if (bb & 128) atomicCAS(&c->err, 0, -4);
             }
             if (a.skip) {
                 const int ti = tile % a.ntx, tj = tile / a.ntx;
+                const bool fresh = nbst < gen;
                 int cand = -1;
-                if (lane == 0 && (bb & (1 | 32 | 64))) cand = tile;
-                if (lane == 1 && (bb & 2) && ti > 0) cand = tile - 1;
-                if (lane == 2 && (bb & 4) && ti < a.ntx - 1) cand = tile + 1;
-                if (lane == 3 && (bb & 8) && tj > 0) cand = tile - a.ntx;
-                if (lane == 4 && (bb & 16) && tj < a.nty - 1) cand = tile + a.ntx;
+                if (lane == 0 && !(bb & 64) && (bb & (1 | 32))) cand = tile;
+                if (lane == 1 && (bb & 2) && ti > 0 && fresh) cand = tile - 1;
+                if (lane == 2 && (bb & 4) && ti < a.ntx - 1 && fresh) cand = tile + 1;
+                if (lane == 3 && (bb & 8) && tj > 0 && fresh) cand = tile - a.ntx;
+                if (lane == 4 && (bb & 16) && tj < a.nty - 1 && fresh) cand = tile + a.ntx;
                 append_tiles(cand, sid, a.tile_base, gen, a.stamp, ba.lists, ba.hot, ba.list_cap, ba.slot ^ 1, grp);
             }
         }
@@ -1294,25 +1357,31 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
     if (lane == 0) red_l[wv] = cs;
     for (int k = tid; k < ba.n; k += NT) {
         const Args<real>& a = ba.scen[k];
-        Ctrl* const c = a.ctrl;
-        if (c->err_gate) continue;
-        const double tau_done = c->tau;
-        c->t += tau_done;
-        c->inflow += c->dV;
-        c->last_tau = tau_done;
-        c->step += 1;
-        next_step_scalars(a, c, prep_speed(c, real(0)));
-        c->prep_speed = 0ull;
-        if (c->err) c->err_gate = c->err;
+        Ctrl c = *a.ctrl;   // all reads first, one write-back
+        if (c.err_gate) continue;
+        const double tau_done = c.tau;
+        c.t += tau_done;
+        c.inflow += c.dV;
+        c.last_tau = tau_done;
+        c.step += 1;
+        next_step_scalars(a, &c, prep_speed(&c, real(0)));
+        c.prep_speed = 0ull;
+        if (c.err) c.err_gate = c.err;
+        *a.ctrl = c;
     }
     __syncthreads();
     if (tid == 0) {
+        Ctrl c = *lc;
+        int nseg[NSEG];
+#pragma unroll
+        for (int g = 0; g < NSEG; ++g) nseg[g] = ba.hot[hot_seg(ba.slot ^ 1, g)];
         long long cells = 0;
         for (int q = 0; q < NWAVE; ++q) cells += red_l[q];
-        lc->step += 1;
-        lc->tiles += count;
-        lc->cells += cells;
-        close_segments(lc, ba.hot, ba.slot ^ 1);
+        c.step += 1;
+        c.tiles += count;
+        c.cells += cells;
+        *lc = c;
+        close_segments_from(lc, nseg, ba.slot ^ 1);
         for (int g = 0; g < NSEG; ++g) ba.hot[hot_seg(ba.slot, g)] = 0;
         for (int g = 0; g <= NSEG; ++g) ba.hot[hot_done(g)] = 0;
     }
