@@ -8,14 +8,19 @@ forces and CFL time step, Lagrangian predictor-corrector, TVD Riemann fluxes,
 final update, plus the wet-tile bookkeeping of K1) over the whole grid, with
 the inputs resident in HBM.  W untimed steps advance the flood, then exactly
 K steps are timed, bracketed by torch.cuda.synchronize() and HIP events on
-the stream the library launches on.  Prints ONE JSON line.
+the stream the library launches on; the steps run as the library runs them
+(replays of captured hipGraphs of the single-step kernel).  Prints ONE JSON
+line.
 
 value        active-cell updates per second: in-domain cells of the tiles the
              step kernel processes (the dry-tile skip removes the rest)
 roofline     the step kernel: algorithmic bytes (32 B per processed FP32 cell:
              reads H, Qx, Qy, b, c_f; writes H, Qx, Qy) per launch over its
-             mean launch duration, from per-launch HIP events over the timed
-             steps, against the 8 TB/s HBM peak
+             mean launch duration against the 8 TB/s HBM peak.  Every step is
+             one launch of that kernel, so the event-bracketed timed region
+             over K is its mean launch duration plus the gaps between
+             launches (an upper bound; --per-launch stamps each launch with
+             its own events instead, which slows the launches themselves)
              traffic: HBM bytes per launch of the same kernel on the same
              workload and steps from rocprofv3 FETCH_SIZE and WRITE_SIZE
              counters scaled by a plain copy of known size (a summary under
@@ -57,8 +62,11 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     ap.add_argument("--warmup-launches", action="store_true",
                     help="run the warm-up as single launches (no hipGraph), e.g. under counter collection")
-    ap.add_argument("--graph", action="store_true",
-                    help="time hipGraph replays instead of per-launch events (no roofline)")
+    ap.add_argument("--progress", type=int, default=0, metavar="N",
+                    help="run the timed steps in chunks of N with a progress line on stderr after each "
+                         "(long profiler passes)")
+    ap.add_argument("--per-launch", action="store_true",
+                    help="time each step kernel with its own HIP event pair instead of graph replays")
     return ap.parse_args()
 
 
@@ -155,16 +163,24 @@ def main():
         torch.cuda.synchronize()
         c0 = time.perf_counter()
         e0.record(stream)
-        if args.graph:
-            g.run(args.steps)
-            kernel_ms = None
-        else:
-            kernel_ms = g.run_timed(args.steps)
+        chunk = args.progress if args.progress > 0 else args.steps
+        kernel_ms, done = 0.0, 0
+        while done < args.steps:
+            c = min(chunk, args.steps - done)
+            if args.per_launch:
+                kernel_ms += g.run_timed(c)
+            else:
+                g.run(c)
+            done += c
+            if args.progress > 0:
+                print("bench: %d/%d steps" % (done, args.steps), file=sys.stderr, flush=True)
         e1.record(stream)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
         w1, t_sim1 = g.work(), g.time()
         ev_ms = e0.elapsed_time(e1)
+        if not args.per_launch:
+            kernel_ms = ev_ms
         V, inflow, ledger = g.mass(), g.inflow(), g.ledger()
     wall = c1 - c0
     secs = max(ev_ms * 1e-3, 1e-12)
@@ -189,21 +205,21 @@ def main():
             "grid_cell_updates_per_s": grid_cells / secs / 1e9,
             "simulated_seconds": t_sim1 - t_sim0,
             "wall_seconds": wall,
-            "timing": "hipGraph replay" if args.graph else "per-launch HIP events",
+            "timing": "per-launch HIP events" if args.per_launch else
+                      "hipGraph replays of the single-step kernel; HIP events around the timed region",
             "volume_balance_rel": abs(V - V0 - inflow - ledger) / max(V, 1e-300),
         },
     }
-    if kernel_ms is not None:
-        alg_bytes = BYTES_PER_CELL[prec] * cells
-        achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-        key = "%s n=%d tile=%s warmup=%d steps=%d" % (args.workload, args.n, args.tile, args.warmup, args.steps)
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(key),
-                           "traffic_unit": "HBM bytes per launch",
-                           "kernel": "swe::k_step<%s,%d,%d>" % ("float" if prec == 32 else "double",
-                                                                w1["tile"][0], w1["tile"][1]),
-                           "mean_launch_us": kernel_ms * 1e3 / args.steps,
-                           "bytes_per_launch": alg_bytes / args.steps}
+    alg_bytes = BYTES_PER_CELL[prec] * cells
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    key = "%s n=%d tile=%s warmup=%d steps=%d" % (args.workload, args.n, args.tile, args.warmup, args.steps)
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(key),
+                       "traffic_unit": "HBM bytes per launch",
+                       "kernel": "swe::k_step<%s,%d,%d>" % ("float" if prec == 32 else "double",
+                                                            w1["tile"][0], w1["tile"][1]),
+                       "mean_launch_us": kernel_ms * 1e3 / args.steps,
+                       "bytes_per_launch": alg_bytes / args.steps}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out), flush=True)
