@@ -1885,10 +1885,16 @@ int grid_for(long long items, int per_block) {
 }
 
 // Forward over n crops already in act[0]; the count may come from the device.
+// The forward kernels loop over their items with the weights held in
+// registers: at most 512 workgroups (two waves per SIMD, all resident).
 hipError_t lc_forward(swe_lc_t* c, int n, const int* cnt_dev, hipStream_t st) {
     const int S = c->S;
     // worst-case items for the grid size: n crops x 16-pixel blocks
-    auto items = [&](int l) { const int so = lc_in(c, l) - 2; return (long long)n * ((so * so + 15) / 16); };
+    auto items = [&](int l) {
+        const int so = lc_in(c, l) - 2;
+        const long long it = (long long)n * ((so * so + 15) / 16);
+        return it < 4 * 512 ? it : 4 * 512;
+    };
     hipLaunchKernelGGL((L_::k_conv_fwd<16, 32, false>), dim3(grid_for(items(0), 4)), dim3(256), 0, st,
                        c->act[0], (void*)c->act[1], c->wf + L_::wb_off(0), c->params + L_::p_off(0) + L_::w_count(0),
                        32, lc_in(c, 0), cnt_dev, n);

@@ -70,52 +70,110 @@ __device__ __forceinline__ int crop_count(const int* dev, int host) { return dev
 // ------------------------------------------------------------------ forward
 // y = act(conv3x3_valid(x) + b); x [n][Sin][Sin][CI] bf16, y [n][Sout][Sout][CO]
 // (bf16 with tanh, or FP32 linear for the last layer).
+//
+// A wave keeps its B operands (the layer's weights for every tap and output
+// tile) in registers for all its items, and loads the A operands of its next
+// 16-pixel item while the MFMAs of the current one run.  With 32 input
+// channels a tap is one 16x16x32 bf16 MFMA (lane group kq holds channels
+// 8kq..8kq+7 of A and B, one 16-byte load each); with 16 input channels a
+// tap is one 16x16x16 MFMA.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 as8(const uint4& q) { return __builtin_bit_cast(bf16x8, q); }
+
+// tanh of the hidden activations (stored as bf16): an odd Taylor polynomial
+// below 1/16, else 1 - 2 / (e^(2|x|) + 1) from the hardware base-2 exponential
+// and reciprocal; relative error about 1e-6, far below the bf16 spacing.
+__device__ __forceinline__ float tanh_act(float x) {
+    const float ax = __builtin_fabsf(x), x2 = x * x;
+    const float small = x * (1.f + x2 * (-0.333333343f + x2 * 0.133333340f));
+    const float e = __builtin_amdgcn_exp2f(2.88539008f * ax);
+    const float big = __builtin_copysignf(1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f), x);
+    return ax < 0.0625f ? small : big;
+}
+
+template <int CI> struct AFrag;
+template <> struct AFrag<16> { typedef uint2 Q; Q v[9]; };
+template <> struct AFrag<32> { typedef uint4 Q; Q v[9]; };
+
+__device__ __forceinline__ bf16x4 as4(const uint2& q) {
+    bf16x4 r;
+    r[0] = (short)(q.x & 0xFFFFu); r[1] = (short)(q.x >> 16); r[2] = (short)(q.y & 0xFFFFu); r[3] = (short)(q.y >> 16);
+    return r;
+}
+
+template <int CI>
+__device__ __forceinline__ void load_a(AFrag<CI>& f, const unsigned short* __restrict__ x, int item, int blocks,
+                                       int Sin, int Sout, int P, int m, int kq) {
+    const int c = item / blocks, p = min((item % blocks) * 16 + m, P - 1);
+    const int oy = p / Sout, ox = p % Sout;
+    const unsigned short* xc = x + (size_t)c * Sin * Sin * CI;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const unsigned short* xp = xc + ((oy + tap / 3) * Sin + ox + tap % 3) * CI;
+        if constexpr (CI == 32) f.v[tap] = *reinterpret_cast<const uint4*>(xp + 8 * kq);
+        else f.v[tap] = *reinterpret_cast<const uint2*>(xp + 4 * kq);
+    }
+}
+
 template <int CI, int CO, bool LAST>
 __global__ __launch_bounds__(256) void k_conv_fwd(const unsigned short* __restrict__ x, void* __restrict__ y,
                                                    const unsigned short* __restrict__ wf, const float* __restrict__ bias,
                                                    int cob, int Sin, const int* cnt_dev, int cnt_host) {
+    static_assert(CI == 16 || CI == 32, "input channels");
     constexpr int NT = CO / 16;
     const int Sout = Sin - 2, P = Sout * Sout, blocks = (P + 15) / 16;
     const int n = crop_count(cnt_dev, cnt_host);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    for (int item = blockIdx.x * 4 + wv; item < n * blocks; item += gridDim.x * 4) {
-        const int c = item / blocks, p0 = (item % blocks) * 16;
-        const int p = min(p0 + m, P - 1);
-        const int oy = p / Sout, ox = p % Sout;
-        const unsigned short* xc = x + (size_t)c * Sin * Sin * CI;
+    const int total = n * blocks, stride = gridDim.x * 4;
+    int item = blockIdx.x * 4 + wv;
+    if (item >= total) return;
+    // B operands: lane (m, kq) holds w[tap][t*16 + m][k] for its k of each
+    // chunk, as A holds x[pixel m][k]
+    typename AFrag<CI>::Q B[9][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            B[tap][t] = *reinterpret_cast<const typename AFrag<CI>::Q*>(wf + (tap * CO + t * 16 + m) * CI +
+                                                                         (CI / 4) * kq);
+    float bb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bb[t] = t * 16 + m < cob ? bias[t * 16 + m] : 0.f;
+    AFrag<CI> cur, nxt;
+    load_a<CI>(cur, x, item, blocks, Sin, Sout, P, m, kq);
+    for (; item < total; item += stride) {
+        const int item2 = item + stride;
+        if (item2 < total) load_a<CI>(nxt, x, item2, blocks, Sin, Sout, P, m, kq);
         f32x4 acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
-            const unsigned short* xp = xc + ((oy + dy) * Sin + ox + dx) * CI + 4 * kq;
+        for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-            for (int c0 = 0; c0 < CI; c0 += 16) {
-                const bf16x4 a = load4(xp + c0);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const bf16x4 b = load4(wf + (tap * CO + t * 16 + m) * CI + c0 + 4 * kq);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-                }
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (CI == 32)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as8(cur.v[tap]), as8(B[tap][t]), acc[t], 0, 0, 0);
+                else
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as4(cur.v[tap]), as4(B[tap][t]), acc[t], 0, 0, 0);
             }
-        }
         // lane holds rows (pixels) p0 + 4*kq + i, column (channel) t*16 + m
+        const int c = item / blocks, p0 = (item % blocks) * 16;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int ch = t * 16 + m;
-            const float bb = ch < cob ? bias[ch] : 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int pp = p0 + 4 * kq + i;
                 if (pp >= P) continue;
-                const float v = acc[t][i] + bb;
+                const float v = acc[t][i] + bb[t];
                 const size_t o = ((size_t)c * P + pp) * CO + ch;
                 if constexpr (LAST) static_cast<float*>(y)[o] = ch < cob ? v : 0.f;
-                else static_cast<unsigned short*>(y)[o] = to_bf16(tanhf(v));
+                else static_cast<unsigned short*>(y)[o] = to_bf16(tanh_act(v));
             }
         }
+        cur = nxt;
     }
 }
 
