@@ -113,11 +113,12 @@ int occupancy(int* blocks) {
 
 // Tile shapes compiled in, each with the three limiters; the first shape of
 // each precision is its default and the one nested grids use.
-// 256 threads per 32 x 32 tile: two workgroups per CU (LDS-bound), a
-// register budget with no spills, and the lowest latency per tile, which
+// 512 threads per 32 x 32 tile: two workgroups per CU (LDS-bound), four
+// waves per SIMD within 128 VGPRs (short runs, no spills), and one pass of
+// the workgroup per stage, which halves the latency of a tile; that latency
 // sets the step time when few tiles are wet.
 #ifndef SWE_F32_THREADS
-#define SWE_F32_THREADS 256
+#define SWE_F32_THREADS 512
 #endif
 const Launcher kLaunchers[] = {
     LAUNCHERS(float, 32, 32, SWE_F32_THREADS, 32, TAP_STEP),

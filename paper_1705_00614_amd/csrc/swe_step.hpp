@@ -20,9 +20,10 @@
 //   epi     CFL speed of layer n+1 on the tile (needs the ring of tile + 1),
 //           wet bits, FP64 volume and clamp partials
 //
-// Work layout: in P1, P2 and FX a thread owns a run of 4 cells along x, in FY
-// a run of 4 cells along y, so neighbour values and limited slopes are loaded
-// and computed once per run instead of once per use.  Lanes of a wave stride
+// Work layout: in P1, P2 and FX a thread owns a run of cells along x, in FY
+// a run along y (2-4 cells, per stage and precision), so neighbour values and
+// limited slopes are loaded and computed once per run instead of once per
+// use.  Lanes of a wave stride
 // LDS rows (row pitch odd) or columns, which keeps LDS accesses free of bank
 // conflicts.  Wet/dry decisions are selects, not branches.
 //
@@ -38,7 +39,6 @@
 namespace swe {
 
 constexpr int HALO = 5;
-constexpr int RUN = 4;
 constexpr double GATE_BED = 1.0e6;
 
 // Tile lists and completion counters.  Same-address device atomics
@@ -542,6 +542,15 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     // normalised cubic-B-spline SPH gradient weights (smoothing length h):
     // al = 1/(12 sqrt2 - 14), be = (3 sqrt2 - 4)/(12 sqrt2 - 14), 2 al + 4 be = 1
     const real al = real(0.33663655161388173), be = real(0.08168172419305914);
+    // Cells per thread along the run of each stage.  FP32 kernels run four
+    // waves per SIMD (128 VGPRs), which short runs fit without spilling:
+    // 2 in P1/P2, 3 in FX/FY where the face count divides, so that one pass
+    // of a 512-thread workgroup covers a 32-wide tile.  FP64 keeps runs of 4.
+    constexpr bool F32 = sizeof(real) == 4;
+    constexpr int RP = F32 ? 2 : 4;
+    constexpr int RFX = F32 ? ((TX + 4) % 3 == 0 ? 3 : 2) : 4;
+    constexpr int RFY = F32 ? 3 : 4;
+    static_assert((TX + 8) % RP == 0 && (TX + 4) % RFX == 0, "run lengths must tile the stage rows");
     auto inside = [&](int x, int y) {
         if constexpr (!EDGE) return true;
         const int gx = tx0 + x, gy = ty0 + y;
@@ -601,27 +610,27 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
     // ---- P1: forces at t_n and predictor on tile + 4, runs of 4 along x
     {
-        constexpr int NRW = (TX + 8) / RUN, NRH = TY + 8, NR = NRW * NRH;
+        constexpr int NRW = (TX + 8) / RP, NRH = TY + 8, NR = NRW * NRH;
         for (int k = tid; k < NR; k += NT) {
-            const int y = k % NRH - 4, x0 = (k / NRH) * RUN - 4;
+            const int y = k % NRH - 4, x0 = (k / NRH) * RP - 4;
             // 3 x 6 patch of effective depth and level: a dry cell shows depth 0
             // and its bed as level
-            real He[3][RUN + 2], Le[3][RUN + 2], Bc[RUN + 2];
+            real He[3][RP + 2], Le[3][RP + 2], Bc[RP + 2];
             bool any = false;
 #pragma unroll
             for (int j = 0; j < 3; ++j)
 #pragma unroll
-                for (int i = 0; i < RUN + 2; ++i) {
+                for (int i = 0; i < RP + 2; ++i) {
                     const int s = G::at(x0 - 1 + i, y - 1 + j);
                     const real H = L.H[s], b = L.B[s];
                     const bool w = H > eps;
                     He[j][i] = w ? H : real(0);
                     Le[j][i] = b + He[j][i];
-                    if (j == 1) { Bc[i] = b; if (i >= 1 && i <= RUN) any |= w; }
+                    if (j == 1) { Bc[i] = b; if (i >= 1 && i <= RP) any |= w; }
                 }
             if (!__any(any)) {   // the whole wave is dry here: U^{n+1/2} = 0
 #pragma unroll
-                for (int i = 0; i < RUN; ++i) {
+                for (int i = 0; i < RP; ++i) {
                     if (!inside(x0 + i, y)) continue;
                     const int s = G::at(x0 + i, y);
                     L.HX[s] = real(0);
@@ -629,20 +638,20 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 }
                 continue;
             }
-            real ux[RUN + 2], uy[RUN + 2], uxs[RUN], uys[RUN], uxn[RUN], uyn[RUN];
+            real ux[RP + 2], uy[RP + 2], uxs[RP], uys[RP], uxn[RP], uyn[RP];
 #pragma unroll
-            for (int i = 0; i < RUN + 2; ++i) {
+            for (int i = 0; i < RP + 2; ++i) {
                 const int s = G::at(x0 - 1 + i, y);
                 ux[i] = L.UX[s]; uy[i] = L.UY[s];
             }
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 const int ss = G::at(x0 + i, y - 1), sn = G::at(x0 + i, y + 1);
                 uxs[i] = L.UX[ss]; uys[i] = L.UY[ss];
                 uxn[i] = L.UX[sn]; uyn[i] = L.UY[sn];
             }
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 const int c = i + 1;
                 const real Hc = He[1][c], bc = Bc[c], ec = Le[1][c];
                 const bool wc = Hc > real(0);
@@ -690,31 +699,31 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
     // ---- P2: forces at t_{n+1/2}, corrector, sources on tile + 3
     {
-        constexpr int NRW = (TX + 8) / RUN, NRH = TY + 6, NR = NRW * NRH;
+        constexpr int NRW = (TX + 8) / RP, NRH = TY + 6, NR = NRW * NRH;
         for (int k = tid; k < NR; k += NT) {
-            const int y = k % NRH - 3, x0 = (k / NRH) * RUN - 4;
-            real hx[RUN + 2], hy[RUN + 2], Hr[RUN + 2];
-            bool wr[RUN + 2];
+            const int y = k % NRH - 3, x0 = (k / NRH) * RP - 4;
+            real hx[RP + 2], hy[RP + 2], Hr[RP + 2];
+            bool wr[RP + 2];
 #pragma unroll
-            for (int i = 0; i < RUN + 2; ++i) {
+            for (int i = 0; i < RP + 2; ++i) {
                 const int s = G::at(x0 - 1 + i, y);
                 hx[i] = L.HX[s]; hy[i] = L.HY[s]; Hr[i] = L.H[s]; wr[i] = Hr[i] > eps;
             }
-            real hxs[RUN], hys[RUN], hxn[RUN], hyn[RUN];
-            bool ws[RUN], wn[RUN];
+            real hxs[RP], hys[RP], hxn[RP], hyn[RP];
+            bool ws[RP], wn[RP];
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 const int ss = G::at(x0 + i, y - 1), sn = G::at(x0 + i, y + 1);
                 hxs[i] = L.HX[ss]; hys[i] = L.HY[ss]; ws[i] = L.H[ss] > eps;
                 hxn[i] = L.HX[sn]; hyn[i] = L.HY[sn]; wn[i] = L.H[sn] > eps;
             }
-            real out[RUN][5];
+            real out[RP][5];
             bool anyw = false;
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) anyw |= wr[i + 1];
+            for (int i = 0; i < RP; ++i) anyw |= wr[i + 1];
             if (!__any(anyw)) {   // the whole wave is dry: no forces, Q_t = 0
 #pragma unroll
-                for (int i = 0; i < RUN; ++i) {
+                for (int i = 0; i < RP; ++i) {
                     const int x = x0 + i;
                     if (!inside(x, y)) continue;
                     const int s = G::at(x, y);
@@ -727,7 +736,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 continue;
             }
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 const int c = i + 1, x = x0 + i;
                 const int s = G::at(x, y);
                 const real Hc = Hr[c];
@@ -755,7 +764,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
             // own-cell stores after all own-cell reads of the run
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 if (!inside(x0 + i, y)) continue;
                 const int s = G::at(x0 + i, y);
                 L.UX[s] = out[i][0];
@@ -777,32 +786,32 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
     // ---- FX: x faces of rows -1..TY, face x between cells x-1 and x
     {
-        constexpr int NRW = (TX + 4) / RUN, NRH = TY + 2, NR = NRW * NRH;
+        constexpr int NRW = (TX + 4) / RFX, NRH = TY + 2, NR = NRW * NRH;
         for (int k = tid; k < NR; k += NT) {
-            const int y = k % NRH - 1, x0 = (k / NRH) * RUN - 1;
-            Cell<real> cl[RUN + 3];
+            const int y = k % NRH - 1, x0 = (k / NRH) * RFX - 1;
+            Cell<real> cl[RFX + 3];
 #pragma unroll
-            for (int i = 0; i < RUN + 3; ++i) {
+            for (int i = 0; i < RFX + 3; ++i) {
                 const int s = G::at(x0 - 2 + i, y);
                 cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.UY[s]; cl[i].ut = L.LM[s];
             }
             bool anyw = false;
 #pragma unroll
-            for (int i = 1; i < RUN + 2; ++i) anyw |= cl[i].H > eps;
+            for (int i = 1; i < RFX + 2; ++i) anyw |= cl[i].H > eps;
             if (!__any(anyw)) {   // dry on both sides of every face: zero fluxes
 #pragma unroll
-                for (int f = 0; f < RUN; ++f) {
+                for (int f = 0; f < RFX; ++f) {
                     const int s = G::at(x0 + f, y);
                     L.HX[s] = real(0); L.HY[s] = real(0); L.H[s] = real(0);
                 }
                 continue;
             }
-            Face<real> lo[RUN + 1], hi[RUN + 1];
+            Face<real> lo[RFX + 1], hi[RFX + 1];
 #pragma unroll
-            for (int i = 0; i < RUN + 1; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
+            for (int i = 0; i < RFX + 1; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
             // recon index i is cell x0 - 1 + i; face x0 + f sits between cells f and f+1
 #pragma unroll
-            for (int f = 0; f < RUN; ++f) {
+            for (int f = 0; f < RFX; ++f) {
                 real FH, Fn, Ft;
                 riemann<real>(a.g, hi[f], lo[f + 1], FH, Fn, Ft);
                 if constexpr (CORR) {
@@ -832,7 +841,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 
     // ---- FY + final update: columns -1..TX, runs of 4 cells along y
     {
-        constexpr int NC = TX + 2, NRY = (TY + 2 + RUN - 1) / RUN, NR = NC * NRY;
+        constexpr int NC = TX + 2, NRY = (TY + 2 + RFY - 1) / RFY, NR = NC * NRY;
         // tap faces in this tile: a face belongs to the tile of the cell east
         // (x face) or north (y face) of it
         bool tap_here = false;
@@ -848,24 +857,24 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
         }
         for (int k = tid; k < NR; k += NT) {
-            const int x = k % NC - 1, y0 = (k / NC) * RUN - 1;
-            Cell<real> cl[RUN + 4];
+            const int x = k % NC - 1, y0 = (k / NC) * RFY - 1;
+            Cell<real> cl[RFY + 4];
 #pragma unroll
-            for (int i = 0; i < RUN + 4; ++i) {
+            for (int i = 0; i < RFY + 4; ++i) {
                 const int s = G::at(x, y0 - 2 + i);
                 cl[i].H = L.UX[s]; cl[i].b = L.B[s]; cl[i].un = L.LM[s]; cl[i].ut = L.UY[s];
             }
-            real FH[RUN + 1], Fn[RUN + 1], Ft[RUN + 1];
+            real FH[RFY + 1], Fn[RFY + 1], Ft[RFY + 1];
             bool anyw = false;
 #pragma unroll
-            for (int i = 1; i < RUN + 3; ++i) anyw |= cl[i].H > eps;
+            for (int i = 1; i < RFY + 3; ++i) anyw |= cl[i].H > eps;
             if (__any(anyw)) {
-                Face<real> lo[RUN + 2], hi[RUN + 2];
+                Face<real> lo[RFY + 2], hi[RFY + 2];
 #pragma unroll
-                for (int i = 0; i < RUN + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
+                for (int i = 0; i < RFY + 2; ++i) recon<real, LIM>(eps, cl[i], cl[i + 1], cl[i + 2], lo[i], hi[i]);
                 // recon index i is cell y0 - 1 + i; face y0 + f between cells f and f+1
 #pragma unroll
-                for (int f = 0; f < RUN + 1; ++f) {
+                for (int f = 0; f < RFY + 1; ++f) {
                     riemann<real>(a.g, hi[f], lo[f + 1], FH[f], Fn[f], Ft[f]);
                     if constexpr (CORR) {
                         // face between cells gy-1 and gy: the north face of gy-1
@@ -877,10 +886,10 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 }
             } else {   // dry on both sides of every face of the run: zero fluxes
 #pragma unroll
-                for (int f = 0; f < RUN + 1; ++f) { FH[f] = real(0); Fn[f] = real(0); Ft[f] = real(0); }
+                for (int f = 0; f < RFY + 1; ++f) { FH[f] = real(0); Fn[f] = real(0); Ft[f] = real(0); }
             }
 #pragma unroll
-            for (int i = 0; i < RUN; ++i) {
+            for (int i = 0; i < RFY; ++i) {
                 const int y = y0 + i;
                 if (y > TY || !inside(x, y)) continue;
                 const int s = G::at(x, y);
@@ -971,7 +980,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
 // lane is 512 / WAVES_PER_SIMD.  A budget below the kernel's live state spills
 // to scratch memory, which every launch then writes and reads through HBM.
 #ifndef SWE_WAVES_PER_SIMD_F32
-#define SWE_WAVES_PER_SIMD_F32 2
+#define SWE_WAVES_PER_SIMD_F32 4
 #endif
 #ifndef SWE_WAVES_PER_SIMD_F64
 #define SWE_WAVES_PER_SIMD_F64 2
