@@ -215,6 +215,26 @@ int    swe_batch_work(swe_batch_t* b, long long* tile_steps, long long* cell_ste
 /* Free the batch and its device memory.  NULL-safe. */
 void   swe_batch_destroy(swe_batch_t* b);
 
+/* ---- tile-shape autotuner -------------------------------------------------
+ * The step kernels are compiled for several tile shapes per precision and
+ * limiter (FP32: 32x32, 64x16, 16x16; FP64: 16x16, 32x16).  Every shape
+ * rounds every cell identically, so the shape changes the speed and nothing
+ * else.  The autotuner builds the grid (or the batch) once per compiled shape
+ * of p's precision and limiter from the given inputs and initial state, runs
+ * `warmup` steps (graph capture included), times the next `nsteps` with HIP
+ * events on its stream, and frees it again.  On return the first
+ * min(count, cap) entries of tile_x, tile_y and ms (ms may be NULL) hold the
+ * shapes and their times [ms], fastest first; the return value is the count
+ * of shapes timed (>= 1) or SWE_E*.  p's own tile_x/tile_y are ignored.
+ * Allocates one grid or batch at a time; synchronises. */
+int    swe_autotune(int nx, int ny, double dx, const double* b, const double* n_M,
+                    const swe_params* p, int warmup, int nsteps, int cap,
+                    int* tile_x, int* tile_y, double* ms);
+int    swe_batch_autotune(int n, const int* nx, const int* ny, const double* dx,
+                          const double* const* b, const double* const* n_M,
+                          const swe_params* p, int warmup, int nsteps, int cap,
+                          int* tile_x, int* tile_y, double* ms);
+
 /* ------------------------------------------------------------------ nests
  * Hierarchical grids (Sec. 2.2: the small-scale flow of zoomed-in areas fed
  * back into the large-scale grid; Sec. 5: a 50 m grid with a 12.5 m local

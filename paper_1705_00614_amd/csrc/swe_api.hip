@@ -1847,6 +1847,7 @@ struct swe_lc_s {
     double* loss_part = nullptr;
     int loss_blocks = 0;
     int last_n = 0;                    // crops of the last forward
+    int fwd_blocks[swe::lc::NL] = {};  // resident workgroups of each forward kernel
     // training data set on the device: crops, labels, masks, tile indices
     int cap = 0, count = 0;
     unsigned short* dX = nullptr;
@@ -1887,14 +1888,14 @@ int grid_for(long long items, int per_block) {
 
 // Forward over n crops already in act[0]; the count may come from the device.
 // The forward kernels loop over their items with the weights held in
-// registers: at most 512 workgroups (two waves per SIMD, all resident).
+// registers: at most as many workgroups as fit on the chip at once.
 hipError_t lc_forward(swe_lc_t* c, int n, const int* cnt_dev, hipStream_t st) {
     const int S = c->S;
     // worst-case items for the grid size: n crops x 16-pixel blocks
     auto items = [&](int l) {
         const int so = lc_in(c, l) - 2;
         const long long it = (long long)n * ((so * so + 15) / 16);
-        return it < 4 * 512 ? it : 4 * 512;
+        return it < 4LL * c->fwd_blocks[l] ? it : 4LL * c->fwd_blocks[l];
     };
     hipLaunchKernelGGL((L_::k_conv_fwd<16, 32, false>), dim3(grid_for(items(0), 4)), dim3(256), 0, st,
                        c->act[0], (void*)c->act[1], c->wf + L_::wb_off(0), c->params + L_::p_off(0) + L_::w_count(0),
@@ -2002,6 +2003,17 @@ swe_lc_t* swe_lc_create(int tile, int max_crops, const double* in_scale, const d
     } while (0)
     if (stream) c->stream = (hipStream_t)stream;
     else { LK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
+    {
+        int dev = 0, cus = 0;
+        LK(hipGetDevice(&dev));
+        LK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        int occ[L_::NL] = {};
+        LK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], L_::k_conv_fwd<16, 32, false>, 256, 0));
+        LK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], L_::k_conv_fwd<32, 32, false>, 256, 0));
+        occ[2] = occ[1];
+        LK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], L_::k_conv_fwd<32, 16, true>, 256, 0));
+        for (int l = 0; l < L_::NL; ++l) c->fwd_blocks[l] = cus * (occ[l] > 0 ? occ[l] : 1);
+    }
     LK(hipMalloc((void**)&c->dscale, sizeof(float) * 12));
     {
         float sc[12];
@@ -2473,3 +2485,102 @@ int swe_lc_set_out_scale(swe_lc_t* c, const double* out_scale) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- tile-shape autotuner
+
+namespace {
+
+// Time `nsteps` steps of a freshly built grid or batch after `warmup` steps
+// (graph capture happens in the warm-up), with HIP events on its stream.
+template <class Run>
+int time_steps(hipStream_t st, Run run, int warmup, int nsteps, double* ms) {
+    int rc = run(warmup);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e != hipSuccess) { (void)hipEventDestroy(e0); if (e1) (void)hipEventDestroy(e1); set_hip_err("autotune", e); return SWE_EHIP; }
+    rc = run(nsteps);
+    float f = 0.f;
+    if (!rc) {
+        e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        if (e != hipSuccess) { set_hip_err("autotune", e); rc = SWE_EHIP; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = f;
+    return rc;
+}
+
+// Shapes compiled for a precision and limiter, in table order.
+int shapes_of(int precision, int limiter, const Launcher** out, int cap) {
+    int n = 0;
+    for (const Launcher& l : kLaunchers)
+        if (l.precision == precision && l.limiter == limiter && n < cap) out[n++] = &l;
+    return n;
+}
+
+// Sort the trials by time (best first) into the caller's arrays.
+int report_shapes(const Launcher* const* sh, const double* t, int n, int cap, int* tx, int* ty, double* ms) {
+    int idx[16];
+    for (int k = 0; k < n; ++k) idx[k] = k;
+    std::sort(idx, idx + n, [&](int a, int b) { return t[a] < t[b]; });
+    for (int k = 0; k < n && k < cap; ++k) {
+        tx[k] = sh[idx[k]]->tx;
+        ty[k] = sh[idx[k]]->ty;
+        if (ms) ms[k] = t[idx[k]];
+    }
+    return n;
+}
+
+}  // namespace
+
+int swe_autotune(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p, int warmup,
+                 int nsteps, int cap, int* tile_x, int* tile_y, double* ms) {
+    g_err.clear();
+    if (!p || !b || warmup < 0 || nsteps < 1 || cap < 1 || !tile_x || !tile_y) {
+        set_err("swe_autotune: invalid arguments"); return SWE_EINVAL;
+    }
+    const Launcher* sh[16];
+    const int n = shapes_of(p->precision, p->limiter, sh, 16);
+    if (n == 0) { set_err("swe_autotune: no tile shape for this precision and limiter"); return SWE_EINVAL; }
+    double t[16];
+    for (int k = 0; k < n; ++k) {
+        swe_params q = *p;
+        q.tile_x = sh[k]->tx;
+        q.tile_y = sh[k]->ty;
+        swe_t* s = swe_create(nx, ny, dx, b, n_M, &q);
+        if (!s) return SWE_EINVAL;
+        const int rc = time_steps(s->stream, [&](int m) { return m > 0 ? swe_run(s, m) : 0; }, warmup, nsteps, &t[k]);
+        swe_destroy(s);
+        if (rc) return rc;
+    }
+    return report_shapes(sh, t, n, cap, tile_x, tile_y, ms);
+}
+
+int swe_batch_autotune(int nb, const int* nx, const int* ny, const double* dx, const double* const* b,
+                       const double* const* n_M, const swe_params* p, int warmup, int nsteps, int cap, int* tile_x,
+                       int* tile_y, double* ms) {
+    g_err.clear();
+    if (nb < 1 || !p || !nx || !ny || !dx || !b || warmup < 0 || nsteps < 1 || cap < 1 || !tile_x || !tile_y) {
+        set_err("swe_batch_autotune: invalid arguments"); return SWE_EINVAL;
+    }
+    const Launcher* sh[16];
+    const int n = shapes_of(p[0].precision, p[0].limiter, sh, 16);
+    if (n == 0) { set_err("swe_batch_autotune: no tile shape for this precision and limiter"); return SWE_EINVAL; }
+    std::vector<swe_params> q(p, p + nb);
+    double t[16];
+    for (int k = 0; k < n; ++k) {
+        for (swe_params& e : q) { e.tile_x = sh[k]->tx; e.tile_y = sh[k]->ty; }
+        swe_batch_t* B = swe_batch_create(nb, nx, ny, dx, b, n_M, q.data());
+        if (!B) return SWE_EINVAL;
+        const int rc = time_steps(B->stream, [&](int m) { return m > 0 ? swe_batch_run(B, m) : 0; }, warmup, nsteps,
+                                  &t[k]);
+        swe_batch_destroy(B);
+        if (rc) return rc;
+    }
+    return report_shapes(sh, t, n, cap, tile_x, tile_y, ms);
+}

@@ -73,6 +73,13 @@ EXPORTS = {
     "swe_batch_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), _dp, ctypes.POINTER(_dp),
                                            ctypes.POINTER(_dp), ctypes.POINTER(SweParams)]),
+    "swe_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.POINTER(SweParams),
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), _dp]),
+    "swe_batch_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                          _dp, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(SweParams),
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), _dp]),
     "swe_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
     "swe_batch_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
     "swe_batch_query": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]),
@@ -211,6 +218,69 @@ def make_params(prm, skip_dry=True, tile=(0, 0), stream=None):
     return p
 
 
+def _grid_inputs(sc, skip_dry, tile, precision, st):
+    """swe_create's bed and Manning pointers and parameter block for a
+    scenario dict, and the arrays they point into (keep them alive)."""
+    shp = (int(sc["ny"]), int(sc["nx"]))
+    prm = dict(sc["params"])
+    if precision is not None:
+        prm["precision"] = precision
+    p = make_params(prm, skip_dry, tile, st)
+    b = _f64(sc["b"], shp)
+    nm = _f64(sc.get("n_manning"), shp)
+    H0, Qx0, Qy0 = (_f64(sc.get(k), shp) for k in ("H0", "Qx0", "Qy0"))
+    solid = sc.get("solid")
+    solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+    p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
+    return (_ptr(b), _ptr(nm), p), [b, nm, H0, Qx0, Qy0, solid]
+
+
+def _batch_inputs(scenarios, tile, precision, st):
+    """swe_batch_create's arguments for a list of scenario dicts, and the
+    arrays they point into."""
+    n = len(scenarios)
+    nx = (ctypes.c_int * n)(*[int(sc["nx"]) for sc in scenarios])
+    ny = (ctypes.c_int * n)(*[int(sc["ny"]) for sc in scenarios])
+    dx = (ctypes.c_double * n)(*[float(sc["h"]) for sc in scenarios])
+    bs = (_dp * n)()
+    nms = (_dp * n)()
+    prm = (SweParams * n)()
+    keep = []
+    for k, sc in enumerate(scenarios):
+        (b, nm, p), kp = _grid_inputs(sc, True, tile, precision, st)
+        keep += kp
+        bs[k], nms[k], prm[k] = b, nm, p
+    return (n, nx, ny, dx, bs, nms, prm), keep
+
+
+def _shape_table(count, tx, ty, ms):
+    if count < 0:
+        _check(count)
+    return [((tx[k], ty[k]), ms[k]) for k in range(min(count, len(ms)))]
+
+
+def autotune(sc, warmup=8, steps=32, skip_dry=True, precision=None, stream="torch"):
+    """Every compiled tile shape of the scenario's precision timed over
+    `steps` steps after `warmup` (swe_autotune): [((tile_x, tile_y), ms)],
+    fastest first."""
+    st = current_stream() if stream == "torch" else stream
+    (b, nm, p), keep = _grid_inputs(sc, skip_dry, (0, 0), precision, st)
+    tx, ty, ms = (ctypes.c_int * 16)(), (ctypes.c_int * 16)(), (ctypes.c_double * 16)()
+    cnt = load().swe_autotune(int(sc["nx"]), int(sc["ny"]), float(sc["h"]), b, nm, ctypes.byref(p), int(warmup),
+                              int(steps), 16, tx, ty, ms)
+    return _shape_table(cnt, tx, ty, ms)
+
+
+def autotune_batch(scenarios, warmup=8, steps=32, precision=None, stream="torch"):
+    """The same for a batch (swe_batch_autotune)."""
+    st = current_stream() if stream == "torch" else stream
+    args, keep = _batch_inputs(scenarios, (0, 0), precision, st)
+    tx, ty, ms = (ctypes.c_int * 16)(), (ctypes.c_int * 16)(), (ctypes.c_double * 16)()
+    cnt = load().swe_batch_autotune(*args, int(warmup), int(steps), 16, tx, ty, ms)
+    return _shape_table(cnt, tx, ty, ms)
+
+
 class Solver:
     """A GPU solver handle built from a scenario dict (keys nx, ny, h, b,
     n_manning, solid, H0, Qx0, Qy0, params)."""
@@ -218,20 +288,9 @@ class Solver:
     def __init__(self, sc, skip_dry=True, tile=(0, 0), precision=None, stream="torch"):
         L = load()
         self.nx, self.ny, self.h = int(sc["nx"]), int(sc["ny"]), float(sc["h"])
-        shp = (self.ny, self.nx)
-        prm = dict(sc["params"])
-        if precision is not None:
-            prm["precision"] = precision
         st = current_stream() if stream == "torch" else stream
-        p = make_params(prm, skip_dry, tile, st)
-        b = _f64(sc["b"], shp)
-        nm = _f64(sc.get("n_manning"), shp)
-        H0, Qx0, Qy0 = (_f64(sc.get(k), shp) for k in ("H0", "Qx0", "Qy0"))
-        solid = sc.get("solid")
-        solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-        p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-        p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
-        self._h = L.swe_create(self.nx, self.ny, self.h, _ptr(b), _ptr(nm), ctypes.byref(p))
+        (b, nm, p), keep = _grid_inputs(sc, skip_dry, tile, precision, st)
+        self._h = L.swe_create(self.nx, self.ny, self.h, b, nm, ctypes.byref(p))
         if not self._h:
             raise SweError(SWE_EINVAL, last_error())
 
@@ -350,36 +409,11 @@ class Batch:
 
     def __init__(self, scenarios, tile=(0, 0), precision=None, stream="torch"):
         L = load()
-        n = len(scenarios)
         st = current_stream() if stream == "torch" else stream
         self.shapes = [(int(sc["ny"]), int(sc["nx"])) for sc in scenarios]
-        self._keep = []
-        nx = (ctypes.c_int * n)(*[int(sc["nx"]) for sc in scenarios])
-        ny = (ctypes.c_int * n)(*[int(sc["ny"]) for sc in scenarios])
-        dx = (ctypes.c_double * n)(*[float(sc["h"]) for sc in scenarios])
-        bs = (_dp * n)()
-        nms = (_dp * n)()
-        prm = (SweParams * n)()
-        for k, sc in enumerate(scenarios):
-            shp = self.shapes[k]
-            pr = dict(sc["params"])
-            if precision is not None:
-                pr["precision"] = precision
-            p = make_params(pr, True, tile, st)
-            b = _f64(sc["b"], shp)
-            nm = _f64(sc.get("n_manning"), shp)
-            H0, Qx0, Qy0 = (_f64(sc.get(q), shp) for q in ("H0", "Qx0", "Qy0"))
-            solid = sc.get("solid")
-            solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-            p.solid = None if solid is None else solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-            p.H0, p.Qx0, p.Qy0 = _ptr(H0), _ptr(Qx0), _ptr(Qy0)
-            self._keep += [b, nm, H0, Qx0, Qy0, solid]
-            bs[k] = _ptr(b)
-            nms[k] = _ptr(nm)
-            prm[k] = p
-        self.n = n
-        self._h = L.swe_batch_create(n, nx, ny, dx, bs, nms, prm)
-        self._keep = None
+        args, keep = _batch_inputs(scenarios, tile, precision, st)
+        self.n = len(scenarios)
+        self._h = L.swe_batch_create(*args)
         if not self._h:
             raise SweError(SWE_EINVAL, last_error())
 

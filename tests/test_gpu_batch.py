@@ -90,3 +90,37 @@ def test_batch_rejects_mixed_precision_and_no_skip():
     ens[1]["params"] = dict(ens[1]["params"], precision=64)
     with pytest.raises(swe.SweError):
         swe.Batch(ens)
+
+
+def test_autotuner_times_every_shape_and_changes_no_result():
+    """swe_autotune / swe_batch_autotune time every compiled tile shape of
+    the precision (fastest first); the chosen shape computes the same state
+    as the default one, bit for bit."""
+    sc = S.floodplain(n=96, seed=21)
+    table = swe.autotune(sc, warmup=2, steps=6)
+    shapes = [t for t, _ in table]
+    assert sorted(shapes) == sorted([(32, 32), (64, 16), (16, 16)])
+    ms = [m for _, m in table]
+    assert all(m > 0 for m in ms) and ms == sorted(ms)
+    best = swe.Solver(sc, tile=shapes[0])
+    ref = swe.Solver(sc)
+    best.run(30)
+    ref.run(30)
+    for x, y in zip(best.state(), ref.state()):
+        assert np.array_equal(x, y)
+    ens = _small_ensemble(n=3, seed0=77)
+    bt = swe.autotune_batch(ens, warmup=1, steps=4)
+    assert sorted(t for t, _ in bt) == sorted(shapes)
+    tuned = swe.Batch(ens, tile=bt[0][0])
+    tuned.run(12)
+    for k, scen in enumerate(ens):
+        g = swe.Solver(scen, tile=bt[0][0])
+        g.run(12)
+        for x, y in zip(tuned.state(k), g.state()):
+            assert np.array_equal(x, y), k
+
+
+def test_autotuner_rejects_bad_arguments():
+    sc = S.floodplain(n=64, seed=22)
+    with pytest.raises(swe.SweError):
+        swe.autotune(sc, warmup=0, steps=0)
