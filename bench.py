@@ -324,14 +324,14 @@ def bench_learned(args):
     from paper_1705_00614_amd import scenarios as S
     from paper_1705_00614_amd import swe
     n, r, m = args.n, 4, 4
-    ntrain, nheld = 8, 4
+    ntrain, nheld, iters = 64, 16, 2000
     mk = lambda seed: S.floodplain(n=n, h=25.0, seed=seed, q_peak=3.0e4, t_peak=1800.0, sigma_t=600.0)
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         ntiles = (n // r // 32) ** 2
         net = LC.make_net(32, max(ntiles, 64))
-        net.data(100000)
+        net.data(450000)
         for k in range(ntrain):
             LC.collect(net, mk(2000 + k), r, m, intervals=60, gap=24)
             print("learned: collected seed %d, %d crops" % (2000 + k, net.data_count()), file=sys.stderr, flush=True)
@@ -340,7 +340,7 @@ def bench_learned(args):
         net.set_params(LC.initial_params(1))
         torch.cuda.synchronize()
         f0 = time.perf_counter()
-        losses = net.fit(2000, 64, 1e-3, seed=1)
+        losses = net.fit(iters, 64, 1e-3, seed=1)
         torch.cuda.synchronize()
         fit_s = time.perf_counter() - f0
         print("learned: fit %.1f s, loss %.3g -> %.3g" % (fit_s, np.mean(losses[:50]), np.mean(losses[-50:])),
@@ -355,7 +355,7 @@ def bench_learned(args):
           0, tim["learned"]["wall"] * 1e3 / tim["learned"]["steps"], "bf16/f32",
           {"workload": "floodplain %dx%d at 25 m (fine) vs %dx%d at 100 m + network; %d training runs, %d held out"
                        % (n, n, n // r, n // r, ntrain, nheld),
-           "training_crops": count, "fit_iterations": 2000, "fit_seconds": fit_s,
+           "training_crops": count, "fit_iterations": iters, "fit_seconds": fit_s,
            "loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
            "depth_error_plain_coarse": [e["err_plain"] for e in errs],
            "depth_error_learned_coarse": [e["err_learned"] for e in errs],

@@ -75,10 +75,14 @@ def collect(net, fine_sc, r, m, intervals, skip=0, gap=0):
     return taus
 
 
-def label_scale(net):
-    """Per-channel RMS of the collected labels (in current output units)."""
+def label_scale(net, max_crops=20000):
+    """Per-channel RMS of the collected labels (in current output units), over
+    at most max_crops crops spread evenly through the data set."""
     n = net.data_count()
-    _, y, mask, _ = net.get_data(0, n)
+    step = max(1, n // max_crops)
+    parts = [net.get_data(k, 1)[1:3] for k in range(0, n, step)] if step > 1 else [net.get_data(0, n)[1:3]]
+    y = np.concatenate([p[0] for p in parts])
+    mask = np.concatenate([p[1] for p in parts])
     num = (y * y * mask).sum(axis=(0, 1, 2))
     den = np.maximum(mask.sum(axis=(0, 1, 2)), 1.0)
     return np.sqrt(num / den) * net.out_scale
