@@ -35,6 +35,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 namespace swe {
 
@@ -51,7 +52,13 @@ constexpr int NSEG = 8;
 constexpr int LINE = 64;   // ints per 256-byte line
 __host__ __device__ constexpr int hot_done(int g) { return g * LINE; }          // g < NSEG; NSEG: all groups
 __host__ __device__ constexpr int hot_seg(int slot, int g) { return (NSEG + 1 + slot * NSEG + g) * LINE; }
-constexpr int HOT_INTS = (NSEG + 1 + 2 * NSEG) * LINE;
+// Completion of a single-grid step, per group g: a 64-bit word that counts
+// arrivals (low 11 bits) and sums processed cells (above), and a 64-bit
+// maximum of the workgroups' speeds (bits of a non-negative double).
+constexpr int CNT_BITS = 11;
+__host__ __device__ constexpr int hot_cnt(int g) { return (NSEG + 1 + 2 * NSEG + g) * LINE; }
+__host__ __device__ constexpr int hot_spd(int g) { return (NSEG + 1 + 3 * NSEG + g) * LINE; }
+constexpr int HOT_INTS = (NSEG + 1 + 4 * NSEG) * LINE;
 
 // Device-resident control block of a simulation.
 struct Ctrl {
@@ -664,7 +671,6 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 // e[j][d]: j = 0 south row, 2 north row; d = 0 west column, 2 east
                 const real Gx = (al * (e[1][2] - e[1][0]) + be * ((e[2][2] - e[2][0]) + (e[0][2] - e[0][0]))) * a.ih;
                 const real Gy = (al * (e[2][1] - e[0][1]) + be * ((e[2][2] - e[0][2]) + (e[2][0] - e[0][0]))) * a.ih;
-                const int gx = tx0 + x0 + i, gy = ty0 + y;
                 const bool ins = inside(x0 + i, y);
                 const real cf = ins ? L.LM[G::at(x0 + i, y)] : real(0);
                 const real lam0 = Mth<real>::friction(cf, wc ? Hc : real(1));
@@ -995,7 +1001,6 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     __shared__ Lds<real, TX, TY> L;
     __shared__ double red_d[2][NWAVE];
     __shared__ int red_i[NWAVE];
-    __shared__ long long red_l[NWAVE];
     __shared__ int s_last;
 
     Ctrl* const ctrl = a.ctrl;
@@ -1064,7 +1069,13 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         }
     }
 
-    // ---- completion: per-workgroup results, two-level counter, last workgroup finalises
+    // ---- completion.  The workgroup's error, speed maximum and cell count go
+    // to its group's words by atomics, each issued only once the previous one
+    // has returned (its result feeds the next one's condition), and its
+    // arrival is counted with the cells: when the count completes, every
+    // workgroup's contributions have been performed, and no memory fence is
+    // needed on the way (the tile outputs and list entries are for the next
+    // launch).  The last arrival of the last group finalises.
     vmax = wave_max(vmax);
     __syncthreads();
     if (lane == 0) red_d[0][wv] = (double)vmax;
@@ -1072,28 +1083,24 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     if (tid == 0) {
         double vm = 0.0;
         for (int q = 0; q < NWAVE; ++q) vm = fmax(vm, red_d[0][q]);
-        a.wg_speed[blockIdx.x] = (real)vm;
-        a.wg_cells[blockIdx.x] = ncells;
-        if (anybad) atomicCAS(&ctrl->err, 0, -4);
-        __threadfence();
+        unsigned long long* const h64 = reinterpret_cast<unsigned long long*>(a.hot);
+        const int err_was = anybad ? atomicCAS(&ctrl->err, 0, -4) : 0;
+        unsigned long long sp = 0;
+        if (err_was != INT_MIN)   // always: waits for the error
+            sp = atomicMax(&h64[hot_spd(grp) / 2], (unsigned long long)__double_as_longlong(vm));
         const int in_grp = (G - grp + NSEG - 1) / NSEG, ngrp = G < NSEG ? G : NSEG;
         bool last = false;
-        if (atomicAdd((unsigned*)&a.hot[hot_done(grp)], 1u) == (unsigned)(in_grp - 1))
-            last = atomicAdd((unsigned*)&a.hot[hot_done(NSEG)], 1u) == (unsigned)(ngrp - 1);
+        if (sp != ~0ull) {        // always (no speed has these bits): waits for the maximum
+            const unsigned long long old =
+                atomicAdd(&h64[hot_cnt(grp) / 2], ((unsigned long long)ncells << CNT_BITS) | 1ull);
+            if ((int)(old & ((1ull << CNT_BITS) - 1)) == in_grp - 1)
+                last = atomicAdd((unsigned*)&a.hot[hot_done(NSEG)], 1u) == (unsigned)(ngrp - 1);
+        }
         s_last = last;
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
-    real vm = real(0);
-    long long cs = 0;
-    for (int k = tid; k < G; k += NT) { vm = rmax(vm, a.wg_speed[k]); cs += a.wg_cells[k]; }
-    vm = wave_max(vm);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cs += __shfl_xor(cs, o, 64);
-    __syncthreads();
-    if (lane == 0) { red_d[0][wv] = (double)vm; red_l[wv] = cs; }
-    __syncthreads();
+    __threadfence();   // acquire: group words, segment counters and errors as performed
     if (tid == 0) {
         // every read of the bookkeeping is issued before the first write, so
         // the reads cost one memory round trip, not one each
@@ -1101,9 +1108,14 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         int nseg[NSEG];
 #pragma unroll
         for (int g = 0; g < NSEG; ++g) nseg[g] = a.skip ? a.hot[hot_seg(a.slot ^ 1, g)] : 0;
+        unsigned long long* const h64 = reinterpret_cast<unsigned long long*>(a.hot);
         double S = 0.0;
         long long cells = 0;
-        for (int q = 0; q < NWAVE; ++q) { S = fmax(S, red_d[0][q]); cells += red_l[q]; }
+#pragma unroll
+        for (int g = 0; g < NSEG; ++g) {
+            S = fmax(S, __longlong_as_double((long long)h64[hot_spd(g) / 2]));
+            cells += (long long)(h64[hot_cnt(g) / 2] >> CNT_BITS);
+        }
         const double tau_done = c.tau;
         c.t += tau_done;
         c.inflow += c.dV;
@@ -1117,8 +1129,8 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         if (a.skip) close_segments_from(ctrl, nseg, a.slot ^ 1);
         if (a.skip)
             for (int g = 0; g < NSEG; ++g) a.hot[hot_seg(a.slot, g)] = 0;
-        for (int g = 0; g <= NSEG; ++g) a.hot[hot_done(g)] = 0;
-        __threadfence();
+        for (int g = 0; g < NSEG; ++g) { h64[hot_cnt(g) / 2] = 0ull; h64[hot_spd(g) / 2] = 0ull; }
+        a.hot[hot_done(NSEG)] = 0;
     }
 }
 
