@@ -181,6 +181,10 @@ struct swe_s {
     // attached network: launched before every step to fill the corrections
     struct swe_lc_s* lc = nullptr;
     hipError_t (*pre_step)(swe_t* s, int par) = nullptr;
+    // tiles stepped every step (patches of a nest), device array, and bounds
+    const int* ring_tiles = nullptr;
+    int nring = 0;
+    int ring_b[4] = {-1, 1 << 30, -1, 1 << 30};
 };
 
 namespace {
@@ -240,6 +244,9 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->tap_r = s->tap_r;
     a->tapx = (real*)s->tapx;
     a->tapy = (real*)s->tapy;
+    a->ring_tiles = s->ring_tiles;
+    a->nring = s->nring;
+    a->ring_x0 = s->ring_b[0]; a->ring_x1 = s->ring_b[1]; a->ring_y0 = s->ring_b[2]; a->ring_y1 = s->ring_b[3];
 }
 
 // Step kernel of a grid: the tapping variant for members of a nest.
@@ -456,6 +463,9 @@ struct GridExtra {
     int hold, ntap;
     const int* tap_rect;
     void* tap;
+    // tiles stepped every step (device array) and their bounds
+    const int* ring_tiles;
+    int nring, ring_x0, ring_x1, ring_y0, ring_y1;
 };
 
 }  // namespace
@@ -510,6 +520,9 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
         s->ntap = ex->ntap;
         s->tap_rect = ex->tap_rect;
         s->tap = ex->tap;
+        s->ring_tiles = ex->ring_tiles;
+        s->nring = ex->nring;
+        s->ring_b[0] = ex->ring_x0; s->ring_b[1] = ex->ring_x1; s->ring_b[2] = ex->ring_y0; s->ring_b[3] = ex->ring_y1;
         if (s->ntap > 0 && !L->step_tap) {
             set_err("nest: the tile shape has no tapping step kernel"); delete s; return nullptr;
         }
@@ -1635,6 +1648,22 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
     for (size_t t = 0; t < forced.size(); ++t)
         if (forced[t]) ints.push_back((int)t);
     n->nforce = (int)(ints.size() - o_force);
+    // tiles of each patch holding frame cells: stepped every substep (the
+    // frame is rewritten from the coarse grid between substeps), never listed
+    std::vector<size_t> o_ring(npatch);
+    std::vector<int> n_ring(npatch), ring_bounds(4 * (size_t)npatch);
+    for (int k = 0; k < npatch; ++k) {
+        const swe_patch& q = patches[k];
+        const int nxe = r * q.cw + 2 * G, nye = r * q.ch + 2 * G;
+        const int ptx = (nxe + L->tx - 1) / L->tx, pty = (nye + L->ty - 1) / L->ty;
+        const int bx0 = (G - 1) / L->tx, bx1 = (nxe - G) / L->tx, by0 = (G - 1) / L->ty, by1 = (nye - G) / L->ty;
+        o_ring[k] = ints.size();
+        for (int tj = 0; tj < pty; ++tj)
+            for (int ti = 0; ti < ptx; ++ti)
+                if (ti <= bx0 || ti >= bx1 || tj <= by0 || tj >= by1) ints.push_back(tj * ptx + ti);
+        n_ring[k] = (int)(ints.size() - o_ring[k]);
+        ring_bounds[4 * k] = bx0; ring_bounds[4 * k + 1] = bx1; ring_bounds[4 * k + 2] = by0; ring_bounds[4 * k + 3] = by1;
+    }
 
     // ---- device buffers
     hipStream_t st = (hipStream_t)p->stream;
@@ -1661,7 +1690,6 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
     pp.inlet_i0 = pp.inlet_j0 = pp.inlet_ni = pp.inlet_nj = 0;
     pp.q_base = pp.q_peak = 0.0;
     pp.solid = nullptr;
-    pp.skip_dry = 0;
     pp.stream = (void*)n->stream;
     for (int k = 0; k < npatch; ++k) {
         const swe_patch& q = patches[k];
@@ -1675,7 +1703,8 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
                 if (q.Qy0) Qy[dst] = q.Qy0[src];
             }
         pp.H0 = H.data(); pp.Qx0 = Qx.data(); pp.Qy0 = Qy.data();
-        GridExtra fx{1, 1, n->ints + o_frect + 5 * k, n->tap};
+        GridExtra fx{1, 1, n->ints + o_frect + 5 * k, n->tap, n->ints + o_ring[k], n_ring[k], ring_bounds[4 * k],
+                     ring_bounds[4 * k + 1], ring_bounds[4 * k + 2], ring_bounds[4 * k + 3]};
         swe_t* g = create_grid(nxe, nye, dx / r, q.b, q.n_M, &pp, &fx);
         if (!g) { std::string m_ = g_err; free_nest(n); delete n; g_err = m_; return nullptr; }
         n->p.push_back(g);

@@ -127,7 +127,21 @@ struct Args {
     int tap_r;
     real* tapx;
     real* tapy;
+    // tiles stepped every step of a skipping grid whatever the list holds
+    // (patches of a nest: the tiles holding the frame, which the nest
+    // rewrites between steps): ring_tiles[nring], and the bounds that make
+    // a tile one of them (column <= ring_x0 or >= ring_x1, row <= ring_y0 or
+    // >= ring_y1); such tiles are never put on the list
+    const int* ring_tiles;
+    int nring, ring_x0, ring_x1, ring_y0, ring_y1;
 };
+
+template <typename real>
+__device__ __forceinline__ bool ring_tile(const Args<real>& a, int tile) {
+    if (a.nring == 0) return false;
+    const int ti = tile % a.ntx, tj = tile / a.ntx;
+    return ti <= a.ring_x0 || ti >= a.ring_x1 || tj <= a.ring_y0 || tj >= a.ring_y1;
+}
 
 // Variants of the step kernel: plain, with flux taps (nested grids), with
 // learned flux corrections.
@@ -1007,7 +1021,8 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     if (ctrl->err_gate) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int G = gridDim.x, grp = blockIdx.x % NSEG;
-    const int count = a.skip ? ctrl->seg_off[a.slot][NSEG] : a.ntiles;
+    const int nlist = a.skip ? ctrl->seg_off[a.slot][NSEG] : a.ntiles;
+    const int count = nlist + (a.skip ? a.nring : 0);   // list entries, then the ring tiles
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
     const int gen = (int)ctrl->step + 2;
@@ -1018,7 +1033,9 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     long long ncells = 0;
 
     for (int p = blockIdx.x; p < count; p += G) {
-        const int tile = a.skip ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p)) : p;
+        const int tile = !a.skip ? p
+                         : p < nlist ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p))
+                                     : a.ring_tiles[p - nlist];
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
@@ -1027,7 +1044,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         // the tile's clamp ledger is read now and written back at the end
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
         const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
-                         a.skip != 0};
+                         a.skip != 0 && !ring_tile(a, tile)};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
             tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
@@ -1064,6 +1081,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
                 if (lane == 2 && (bb & 4) && ti < a.ntx - 1 && fresh) cand = tile + 1;
                 if (lane == 3 && (bb & 8) && tj > 0 && fresh) cand = tile - a.ntx;
                 if (lane == 4 && (bb & 16) && tj < a.nty - 1 && fresh) cand = tile + a.ntx;
+                if (cand >= 0 && ring_tile(a, cand)) cand = -1;
                 append_tiles(cand, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp);
             }
         }
@@ -1209,8 +1227,8 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         int ac0 = 0;
 #pragma unroll
         for (int q = 0; q < NWAVE; ++q) ac0 |= red_i[q];
-        append_tiles(lane == 0 && ac0 ? tile : -1, a.sid, a.tile_base, (int)a.lctrl->step + 1, a.stamp, a.lists,
-                     a.hot, a.list_cap, a.slot, blockIdx.x % NSEG);
+        append_tiles(lane == 0 && ac0 && !ring_tile(a, tile) ? tile : -1, a.sid, a.tile_base, (int)a.lctrl->step + 1,
+                     a.stamp, a.lists, a.hot, a.list_cap, a.slot, blockIdx.x % NSEG);
     }
 }
 
