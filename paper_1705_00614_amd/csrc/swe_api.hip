@@ -250,13 +250,14 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
 }
 
 // Step kernel of a grid: the tapping variant for members of a nest.
-hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                            hipStream_t on = nullptr) {
     if (s->pre_step) {
         const hipError_t e = s->pre_step(s, par);
         if (e != hipSuccess) return e;
     }
     auto f = (s->ntap > 0 || s->tap_r > 0) ? s->L->step_tap : s->corr ? s->L->step_corr : s->L->step;
-    return f(s->args[par].data(), s->grid, s->stream, e0, e1);
+    return f(s->args[par].data(), s->grid, on ? on : s->stream, e0, e1);
 }
 
 void build_args(swe_t* s) {
@@ -1354,12 +1355,20 @@ struct swe_nest_s {
     long long launched = 0;          // coarse steps launched
     hipGraphExec_t graph = nullptr;
     std::vector<unsigned char> nargs;   // NestArgs<real>
+    // patches 1.. step on side streams (default priority), forked from and
+    // joined back into the nest's stream around each substep
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
 };
 
 namespace {
 
 void free_nest(swe_nest_t* n) {
     if (n->graph) (void)hipGraphExecDestroy(n->graph);
+    for (hipStream_t q : n->side) if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
+    if (n->fork) (void)hipEventDestroy(n->fork);
+    for (hipEvent_t e : n->join) if (e) (void)hipEventDestroy(e);
     for (swe_t* q : n->p) if (q) swe_destroy(q);
     if (n->c) swe_destroy(n->c);
     void* ptrs[] = {n->tap, n->ints, n->desc, n->ring_ledger, n->part, n->scalar};
@@ -1429,9 +1438,22 @@ hipError_t nest_step_t(swe_nest_t* n) {
         hipLaunchKernelGGL(swe::k_frame<real>, dim3(blocks_for(na.nframe, 256)), dim3(256), 0, n->stream, na, pf, pc,
                            (real)((double)s / (double)n->r));
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        for (swe_t* q : n->p) {
-            if ((e = launch_grid_step(q, pf)) != hipSuccess) return e;
+        // the patches are independent within a substep: patch 0 on the
+        // nest's stream, the others on side streams between a fork and a join
+        const int np = (int)n->p.size();
+        if (np > 1) {
+            if ((e = hipEventRecord(n->fork, n->stream)) != hipSuccess) return e;
+            for (int k = 1; k < np; ++k)
+                if ((e = hipStreamWaitEvent(n->side[k], n->fork, 0)) != hipSuccess) return e;
+        }
+        for (int k = 0; k < np; ++k) {
+            swe_t* q = n->p[k];
+            if ((e = launch_grid_step(q, pf, nullptr, nullptr, k ? n->side[k] : nullptr)) != hipSuccess) return e;
             q->launched++;
+        }
+        for (int k = 1; k < np; ++k) {
+            if ((e = hipEventRecord(n->join[k], n->side[k])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(n->stream, n->join[k], 0)) != hipSuccess) return e;
         }
     }
     const Args<real>& an = *(const Args<real>*)c->args[pc ^ 1].data();
@@ -1708,6 +1730,15 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
         swe_t* g = create_grid(nxe, nye, dx / r, q.b, q.n_M, &pp, &fx);
         if (!g) { std::string m_ = g_err; free_nest(n); delete n; g_err = m_; return nullptr; }
         n->p.push_back(g);
+    }
+    n->side.assign(npatch, nullptr);
+    n->join.assign(npatch, nullptr);
+    if (npatch > 1) {
+        NK(hipEventCreateWithFlags(&n->fork, hipEventDisableTiming));
+        for (int k = 1; k < npatch; ++k) {
+            NK(hipStreamCreateWithFlags(&n->side[k], hipStreamNonBlocking));
+            NK(hipEventCreateWithFlags(&n->join[k], hipEventDisableTiming));
+        }
     }
     int rc = 0;
     if (n->precision == 32) {
