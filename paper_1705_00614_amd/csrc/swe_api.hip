@@ -1411,6 +1411,8 @@ int upload_desc(swe_nest_t* n, const std::vector<int>& frame_base, const std::ve
         }
         e.bf = (const real*)n->p[k]->bed;
         e.ctrl = n->p[k]->ctrl;
+        e.mass = n->p[k]->mass;
+        e.ntx = n->p[k]->ntx; e.tx = n->p[k]->L->tx; e.ty = n->p[k]->L->ty;
     }
     HIPCHK(hipMemcpyAsync(n->desc, d.data(), sizeof(swe::NestPatch<real>) * n->np, hipMemcpyHostToDevice,
                           n->stream));

@@ -46,6 +46,8 @@ struct NestPatch {
     real* Hf[2]; real* Qxf[2]; real* Qyf[2];
     const real* bf;
     Ctrl* ctrl;
+    const double* mass;            // the patch's per-tile FP64 depth sums
+    int ntx, tx, ty;               // its tile columns and tile shape
 };
 
 template <typename real>
@@ -122,6 +124,17 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
         const NestPatch<real>& d = n.P[k];
         const int m = t - d.cov_base, cy = m / d.cw, cx = m % d.cw;
         const int gc = (d.cj0 + cy) * n.nx + d.ci0 + cx;
+        // a block whose tiles hold no water at all (depth sums exactly 0, so
+        // every depth and discharge is +0) restricts to zero without being read
+        const int fx0 = NEST_FRAME + cx * r, fy0 = NEST_FRAME + cy * r;
+        const int tx0 = fx0 / d.tx, tx1 = (fx0 + r - 1) / d.tx, ty0 = fy0 / d.ty, ty1 = (fy0 + r - 1) / d.ty;
+        if (d.mass[ty0 * d.ntx + tx0] == 0.0 && d.mass[ty0 * d.ntx + tx1] == 0.0 &&
+            d.mass[ty1 * d.ntx + tx0] == 0.0 && d.mass[ty1 * d.ntx + tx1] == 0.0) {
+            n.Hc[po][gc] = real(0);
+            n.Qxc[po][gc] = real(0);
+            n.Qyc[po][gc] = real(0);
+            return;
+        }
         double sH = 0.0, sX = 0.0, sY = 0.0;
         for (int jj = 0; jj < r; ++jj)
             for (int ii = 0; ii < r; ++ii) {
