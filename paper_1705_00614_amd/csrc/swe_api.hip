@@ -2413,6 +2413,33 @@ int swe_lc_data(swe_lc_t* c, int capacity) {
 
 int swe_lc_data_count(swe_lc_t* c) { return c ? c->count : -1; }
 
+// Put the tile list of a grid's current layer in ascending order as one
+// segment.  The set of tiles, and so every result of a step, is unchanged
+// (tiles are independent); what becomes reproducible is the order in which
+// a gather of the list's crops fills the training set (device appends land
+// in the order of their atomics).
+static int sort_tile_list(swe_t* s) {
+    if (!s->p.skip_dry) return 0;
+    Ctrl c;
+    int rc = sync_ctrl(s, &c);
+    if (rc) return rc;
+    const int par = (int)(c.step & 1), n = c.seg_off[par][swe::NSEG];
+    if (n <= 1) return 0;
+    std::vector<int> t(n);
+    rc = swe_active_tiles(s, t.data(), n);
+    if (rc < 0) return rc;
+    std::sort(t.begin(), t.end());
+    int off[swe::NSEG + 1];
+    off[0] = 0;
+    for (int g = 1; g <= swe::NSEG; ++g) off[g] = n;
+    HIPCHK(hipMemcpyAsync(s->lists + (size_t)par * swe::NSEG * s->ntiles, t.data(), sizeof(int) * n,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync((char*)s->ctrl + offsetof(Ctrl, seg_off) + sizeof(int) * (swe::NSEG + 1) * par, off,
+                          sizeof off, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return 0;
+}
+
 int swe_lc_collect(swe_lc_t* c, swe_t* f, swe_t* g, int r, int m, double* tau_out) {
     if (!c || !f || !g || r < 1 || m < 1 || !c->dX) { set_err("swe_lc_collect: invalid arguments or no data set"); return SWE_EINVAL; }
     if (f->tap_r != r || g->tap_r != 1 || f->precision != g->precision || g->L->tx != c->S || g->L->ty != c->S ||
@@ -2422,6 +2449,7 @@ int swe_lc_collect(swe_lc_t* c, swe_t* f, swe_t* g, int r, int m, double* tau_ou
     }
     int rc = swe_restrict(f, g, r);   // coarse layer = restricted fine layer, CFL step recorded
     if (rc) return rc;
+    if ((rc = sort_tile_list(g))) return rc;   // crops in tile order: a reproducible data set
     Ctrl cf, cg;
     if ((rc = sync_ctrl(f, &cf)) || (rc = sync_ctrl(g, &cg))) return rc;
     double tau_c = std::fmin(cg.tau_cfl, (double)m * cf.tau_cfl);
