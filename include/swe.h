@@ -342,6 +342,14 @@ int       swe_lc_get_params(swe_lc_t* c, double* params);
 /* Network output of n host crops; out (n, S+1, S+1, 6) may be NULL. */
 int       swe_lc_forward(swe_lc_t* c, int n, const double* x, double* out);
 
+/* The same network output through the inference path that runs before each
+ * step of a grid with an attached network: all four layers in one launch,
+ * activations kept on chip (blocks of 11 x 11 outputs; S + 1 < 11 takes the
+ * layer-by-layer path).  Keeps no activations: swe_lc_get_layer needs a
+ * swe_lc_forward after it, as after steps of an attached grid.  out
+ * (n, S+1, S+1, 6) is required. */
+int       swe_lc_infer(swe_lc_t* c, int n, const double* x, double* out);
+
 /* One training step on n host crops with labels y and mask (both
  * (n, S+1, S+1, 6)): loss 1/2 sum mask (out - y)^2 / max(sum mask, 1), its
  * gradient by back-propagation, then one Adam step (beta 0.9, 0.999, eps

@@ -1910,6 +1910,7 @@ struct swe_lc_s {
     int loss_blocks = 0;
     int last_n = 0;                    // crops of the last forward
     int fwd_blocks[swe::lc::NL] = {};  // resident workgroups of each forward kernel
+    int net_blocks = 0;                // resident workgroups of the fused inference kernel
     // training data set on the device: crops, labels, masks, tile indices
     int cap = 0, count = 0;
     unsigned short* dX = nullptr;
@@ -1926,6 +1927,8 @@ namespace {
 namespace L_ = swe::lc;
 
 int lc_in(const swe_lc_t* c, int l) { return c->So + 2 * L_::HALO - 2 * l; }   // input side of layer l
+constexpr int NET_T = 11;     // output block side of the fused inference kernel (a 33-wide crop is 3 x 3 blocks)
+constexpr int NET_NTH = 512;  // its threads per workgroup
 
 void free_lc(swe_lc_t* c) {
     void* ptrs[] = {c->params, c->grads, c->m1, c->m2, c->wf, c->wb, c->out, c->y, c->mask, c->part, c->loss_part,
@@ -1972,6 +1975,19 @@ hipError_t lc_forward(swe_lc_t* c, int n, const int* cnt_dev, hipStream_t st) {
                        c->act[3], (void*)c->out, c->wf + L_::wb_off(3), c->params + L_::p_off(3) + L_::w_count(3),
                        6, lc_in(c, 3), cnt_dev, n);
     (void)S;
+    return hipGetLastError();
+}
+
+// Inference only (no activations kept for a backward pass): all four layers
+// in one launch when the output side allows blocks of NET_T, else the
+// layer-by-layer forward.
+hipError_t lc_infer(swe_lc_t* c, int n, const int* cnt_dev, hipStream_t st) {
+    if (c->So < NET_T) return lc_forward(c, n, cnt_dev, st);
+    const int ns = (c->So + NET_T - 1) / NET_T;
+    const long long units = (long long)n * ns * ns;
+    const int grid = (int)(units < c->net_blocks ? units : c->net_blocks);
+    hipLaunchKernelGGL((L_::k_net_fwd<NET_T, NET_NTH>), dim3(grid > 0 ? grid : 1), dim3(NET_NTH), 0, st, c->act[0], c->out, c->wf,
+                       c->params, c->So, cnt_dev, n);
     return hipGetLastError();
 }
 
@@ -2075,6 +2091,9 @@ swe_lc_t* swe_lc_create(int tile, int max_crops, const double* in_scale, const d
         occ[2] = occ[1];
         LK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], L_::k_conv_fwd<32, 16, true>, 256, 0));
         for (int l = 0; l < L_::NL; ++l) c->fwd_blocks[l] = cus * (occ[l] > 0 ? occ[l] : 1);
+        int on = 0;
+        LK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&on, L_::k_net_fwd<NET_T, NET_NTH>, NET_NTH, 0));
+        c->net_blocks = cus * (on > 0 ? on : 1);
     }
     LK(hipMalloc((void**)&c->dscale, sizeof(float) * 12));
     {
@@ -2170,6 +2189,21 @@ int swe_lc_forward(swe_lc_t* c, int n, const double* x, double* out) {
     return 0;
 }
 
+int swe_lc_infer(swe_lc_t* c, int n, const double* x, double* out) {
+    if (!c || !x || !out || n < 1 || n > c->max_crops) { set_err("swe_lc_infer: invalid arguments"); return SWE_EINVAL; }
+    int rc = lc_upload_crops(c, n, x);
+    if (rc) return rc;
+    HIPCHK(lc_infer(c, n, nullptr, c->stream));
+    c->last_n = 0;   // the stored activations no longer belong to one forward
+    const size_t np = (size_t)n * c->So * c->So;
+    std::vector<float> h(np * 16);
+    HIPCHK(hipMemcpyAsync(h.data(), c->out, sizeof(float) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t p = 0; p < np; ++p)
+        for (int k = 0; k < 6; ++k) out[p * 6 + k] = h[p * 16 + k];
+    return 0;
+}
+
 int swe_lc_get_layer(swe_lc_t* c, int which, double* out) {
     if (!c || !out || which < 0 || which >= 2 * L_::NL || c->last_n < 1) {
         set_err("swe_lc_get_layer: invalid arguments or no forward yet"); return SWE_EINVAL;
@@ -2253,7 +2287,8 @@ hipError_t lc_pre_step_t(swe_t* s, int par) {
                        a, slot, S, c->dscale, c->act[0], (int*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = lc_forward(c, nmax, cnt, s->stream)) != hipSuccess) return e;
+    if ((e = lc_infer(c, nmax, cnt, s->stream)) != hipSuccess) return e;
+    c->last_n = 0;
     hipLaunchKernelGGL(L_::k_scatter<real>, dim3(grid_for((long long)nmax * So * So, 256)), dim3(256), 0, s->stream, a,
                        slot, S, c->dscale + 6, c->out, (real*)s->corrE, (real*)s->corrN);
     return hipGetLastError();

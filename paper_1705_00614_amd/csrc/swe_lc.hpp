@@ -177,6 +177,195 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const unsigned short* __restri
     }
 }
 
+// ------------------------------------------------------------------ fused inference
+// All four layers of one T x T block of a crop's output in one workgroup, the
+// intermediate activations in LDS: the block's (T+8)^2 input window comes in
+// from HBM once and only the FP32 output goes out, so an inference costs one
+// launch instead of four and no activation round trips through HBM.  The
+// weights of every layer are staged in LDS once per workgroup; each layer is
+// the same per-pixel MFMA sequence as k_conv_fwd (taps in order, one MFMA per
+// tap and output tile, the same bias, tanh and bf16 rounding), so the output
+// equals the layer-by-layer forward.  A crop of side So is covered by
+// ceil(So / T) blocks per side, the last one shifted back to end at So (its
+// overlap is recomputed and written with the same values).
+template <int T>
+struct alignas(16) NetLds {
+    static constexpr int P16 = 24, P32 = 40;      // pixel strides (bf16): channels + 8 against bank conflicts
+    // a hidden layer's output plane is padded to whole 16-pixel blocks, so
+    // that the rows of a ragged last block are stored without a test (and
+    // never read)
+    static constexpr int blk16(int side) { return ((side * side + 15) / 16) * 16; }
+    static constexpr int A = (T + 8) * (T + 8) * P16 > blk16(T + 4) * P32 ? (T + 8) * (T + 8) * P16
+                                                                           : blk16(T + 4) * P32;
+    static constexpr int B = blk16(T + 6) * P32;
+    unsigned short w[NWB];                        // bf16 weights of all layers, [tap][CO][CI]
+    float bias[NL][32];
+    unsigned short a[A];                          // input window, then layer-1 output
+    unsigned short b[B];                          // layer-0 output, then layer-2 output
+};
+
+// One layer over the LDS plane `in` (side Win, pixel stride PI) into `out`
+// (LDS bf16 with tanh, stride PO) or, for the last layer, into the FP32 crop
+// output in HBM at block origin (oy0, ox0).
+template <int CI, int CO, bool LAST, int Win, int NTH>
+__device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsigned short* out, int PO,
+                                          const unsigned short* w, const float* bias, int cob, float* y, int So,
+                                          int c, int oy0, int ox0) {
+    constexpr int NT = CO / 16, Wout = Win - 2, P = Wout * Wout, blocks = (P + 15) / 16, nw = NTH / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    if (wv >= blocks) return;
+    typename AFrag<CI>::Q B[9][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            B[tap][t] = *reinterpret_cast<const typename AFrag<CI>::Q*>(w + (tap * CO + t * 16 + m) * CI + (CI / 4) * kq);
+    float bb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bb[t] = t * 16 + m < cob ? bias[t * 16 + m] : 0.f;
+    // two blocks per pass (blk and blk + nw): four independent MFMA chains
+    // and sixteen independent activations per lane hide more latency at two
+    // waves per SIMD; a missing second block (wave-uniform) is computed on
+    // clamped pixels and not stored
+    for (int blk = wv; blk < blocks; blk += 2 * nw) {
+        const bool two = blk + nw < blocks;
+        int oy[2], ox[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = min((blk + h * nw) * 16 + m, P - 1);
+            oy[h] = p / Wout;
+            ox[h] = p % Wout;
+        }
+        f32x4 acc[2][NT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[h][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const unsigned short* ip = in + ((oy[h] + tap / 3) * Win + ox[h] + tap % 3) * PI + (CI / 4) * kq;
+                const typename AFrag<CI>::Q av = *reinterpret_cast<const typename AFrag<CI>::Q*>(ip);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if constexpr (CI == 32)
+                        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as8(av), as8(B[tap][t]), acc[h][t], 0, 0, 0);
+                    else
+                        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as4(av), as4(B[tap][t]), acc[h][t], 0, 0,
+                                                                              0);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) break;
+            const int p0 = (blk + h * nw) * 16;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int ch = t * 16 + m;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int pp = p0 + 4 * kq + i;
+                    const float v = acc[h][t][i] + bb[t];
+                    if constexpr (LAST) {
+                        if (pp >= P) continue;
+                        const int gy = oy0 + pp / Wout, gx = ox0 + pp % Wout;
+                        y[(((size_t)c * So + gy) * So + gx) * CO + ch] = ch < cob ? v : 0.f;
+                    } else {
+                        out[pp * PO + ch] = to_bf16(tanh_act(v));   // pp < blocks * 16: inside the padded plane
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The two 16-byte pieces (thread tid and tid + NTH) of unit u's input window:
+// rows oy0 .. oy0+T+7 of its crop, 16 bf16 channels = 2 pieces per pixel.
+template <int T, int NTH>
+__device__ __forceinline__ void net_window(const unsigned short* __restrict__ x, int u, int ns, int So, int Sin,
+                                           int tid, uint4& r0, uint4& r1) {
+    constexpr int W0 = T + 2 * HALO, XV = W0 * W0 * 2;
+    const int c = u / (ns * ns), sub = u % (ns * ns);
+    const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
+    const unsigned short* xc = x + (size_t)c * Sin * Sin * 16;
+    const int k0 = tid, k1 = tid + NTH;   // k0 < XV always (XV > NTH)
+    r0 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k0 >> 1) / W0) * Sin + ox0 + (k0 >> 1) % W0) * 16 +
+                                         8 * (k0 & 1));
+    if (k1 < XV)
+        r1 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k1 >> 1) / W0) * Sin + ox0 + (k1 >> 1) % W0) * 16 +
+                                             8 * (k1 & 1));
+}
+
+// x: crops [n][So+8][So+8][16] bf16; y: [n][So][So][16] FP32 (channels >= 6
+// zero); wf: bf16 weights of all layers; params: packed FP32 parameters (the
+// biases are read from there).  Requires So >= T; n from the device or host.
+template <int T, int NTH>
+__global__ __launch_bounds__(NTH) void k_net_fwd(const unsigned short* __restrict__ x, float* __restrict__ y,
+                                                 const unsigned short* __restrict__ wf,
+                                                 const float* __restrict__ params, int So, const int* cnt_dev,
+                                                 int cnt_host) {
+    __shared__ NetLds<T> L;
+    using N = NetLds<T>;
+    const int n = crop_count(cnt_dev, cnt_host);
+    const int ns = (So + T - 1) / T, units = n * ns * ns;
+    if ((int)blockIdx.x >= units) return;
+    const int tid = threadIdx.x, Sin = So + 2 * HALO;
+    constexpr int W0 = T + 2 * HALO;
+    // every global load of a staging loop is issued before the first store
+    // (one memory round trip per loop, not one per iteration)
+    {
+        constexpr int NV = NWB / 8, J = (NV + NTH - 1) / NTH;
+        uint4 v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = min(tid + j * NTH, NV - 1);   // clamped: the tail re-reads the last piece
+            v[j] = reinterpret_cast<const uint4*>(wf)[k];
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (tid + j * NTH < NV) reinterpret_cast<uint4*>(L.w)[tid + j * NTH] = v[j];
+    }
+    for (int k = tid; k < NL * 32; k += NTH) {
+        const int l = k / 32, ch = k % 32;
+        constexpr int b0 = p_off(0) + w_count(0), b1 = p_off(1) + w_count(1), b2 = p_off(2) + w_count(2),
+                      b3 = p_off(3) + w_count(3);   // bias offsets, folded at compile time
+        const int off = l == 0 ? b0 : l == 1 ? b1 : l == 2 ? b2 : b3;
+        L.bias[l][ch] = ch < (l == NL - 1 ? COUT_REAL[NL - 1] : 32) ? params[off + ch] : 0.f;
+    }
+    // input window of unit u (rows oy0 .. oy0+T+7 of its crop, 16 channels =
+    // 2 x 16 B per pixel) into registers: the next unit's window is loaded
+    // while the current one computes
+    constexpr int XV = W0 * W0 * 2, XJ = (XV + NTH - 1) / NTH;
+    uint4 xr0, xr1;
+    static_assert(XJ == 2, "two 16-byte pieces of the input window per thread");
+    net_window<T, NTH>(x, blockIdx.x, ns, So, Sin, tid, xr0, xr1);
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int c = u / (ns * ns), sub = u % (ns * ns);
+        const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
+        *reinterpret_cast<uint4*>(L.a + (tid >> 1) * N::P16 + 8 * (tid & 1)) = xr0;
+        if (tid + NTH < XV) *reinterpret_cast<uint4*>(L.a + ((tid + NTH) >> 1) * N::P16 + 8 * (tid & 1)) = xr1;
+        __syncthreads();
+        if (u + (int)gridDim.x < units) net_window<T, NTH>(x, u + gridDim.x, ns, So, Sin, tid, xr0, xr1);
+        net_layer<16, 32, false, W0, NTH>(L.a, N::P16, L.b, N::P32, L.w + wb_off(0), L.bias[0], 32, nullptr, So, c,
+                                          0, 0);
+        __syncthreads();
+        net_layer<32, 32, false, W0 - 2, NTH>(L.b, N::P32, L.a, N::P32, L.w + wb_off(1), L.bias[1], 32, nullptr, So,
+                                              c, 0, 0);
+        __syncthreads();
+        net_layer<32, 32, false, W0 - 4, NTH>(L.a, N::P32, L.b, N::P32, L.w + wb_off(2), L.bias[2], 32, nullptr, So,
+                                              c, 0, 0);
+        __syncthreads();
+        net_layer<32, 16, true, W0 - 6, NTH>(L.b, N::P32, nullptr, 0, L.w + wb_off(3), L.bias[3], COUT_REAL[3], y,
+                                             So, c, oy0, ox0);
+        // the next unit's input goes to L.a, last read by layer 2 (before the
+        // barrier above); layer 3 reads L.b, next written after the barrier
+        // that follows the next input
+    }
+}
+
 // ------------------------------------------------------------------ backward data
 // g_in = bf16(dL/da_in * (1 - a_in^2)) from g = dL/dz of this layer:
 // dL/da_in[q] = sum_{tap, co} g[q - tap][co] w[co][ci][tap] (zero outside the

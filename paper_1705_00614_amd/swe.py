@@ -112,6 +112,7 @@ EXPORTS = {
     "swe_lc_set_params": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "swe_lc_get_params": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "swe_lc_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp]),
+    "swe_lc_infer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp]),
     "swe_lc_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]),
     "swe_lc_get_grads": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "swe_lc_get_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
@@ -607,6 +608,15 @@ class Net:
         n = x.shape[0]
         out = np.empty((n, self.So, self.So, 6))
         _check(load().swe_lc_forward(self._h, n, _ptr(x), _ptr(out)))
+        return out
+
+    def infer(self, x):
+        """Network output through the one-launch inference path (the one run
+        before each step of an attached grid)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = x.shape[0]
+        out = np.empty((n, self.So, self.So, 6))
+        _check(load().swe_lc_infer(self._h, n, _ptr(x), _ptr(out)))
         return out
 
     def train_step(self, x, y, mask, lr):

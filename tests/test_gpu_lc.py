@@ -66,6 +66,27 @@ def test_forward_layers_match_oracle():
     assert np.abs(out - ref).max() <= 0.05 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("S,n", [(32, 3), (32, 61), (16, 5), (12, 2), (8, 3)])
+def test_fused_inference_equals_layered_forward(S, n):
+    """One-launch inference (activations in LDS, 11 x 11 output blocks; the
+    last block of a side shifted back when 11 does not divide S + 1) against
+    the layer-by-layer forward: the same MFMAs per pixel, so equal bitwise;
+    61 crops of side 33 are more blocks than resident workgroups.  S = 8 takes
+    the layer-by-layer path itself."""
+    rng = np.random.default_rng(40 + S)
+    W, b = LN.init_params(S)
+    W[-1] = W[-1] * 10.0
+    b = [rng.normal(scale=0.1, size=v.shape) for v in b]
+    x = rng.normal(size=(n, S + 9, S + 9, 6))
+    net = swe.Net(S, n, np.ones(6), np.ones(6))
+    net.set_params(swe.lc_pack(W, b))
+    out = net.forward(x)
+    fused = net.infer(x)
+    assert np.array_equal(fused, out)
+    ref, _ = LN.forward(x, W, b, bf=True)
+    assert np.abs(fused - ref).max() <= 0.05 * np.abs(ref).max()
+
+
 def test_backward_matches_oracle():
     net, W, Wb, b, x, rng = _setup(seed=1)
     n, So = x.shape[0], 9
