@@ -372,6 +372,8 @@ def bench_learned(args):
            "depth_error_plain_coarse": [e["err_plain"] for e in errs],
            "depth_error_learned_coarse": [e["err_learned"] for e in errs],
            "fine_wall_s": tim["fine"]["wall"], "learned_wall_s": tim["learned"]["wall"],
+           "plain_coarse_wall_s": tim["plain"]["wall"],
+           "steps_fine_learned_plain": [tim[k]["steps"] for k in ("fine", "learned", "plain")],
            "simulated_seconds": tim["fine"]["sim"], "total_wall_s": time.perf_counter() - t0})
 
 

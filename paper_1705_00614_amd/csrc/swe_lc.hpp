@@ -243,9 +243,9 @@ __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsi
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[h][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
+        for (int h = 0; h < 2; ++h) {   // block-major: block 0's activations can overlap block 1's MFMAs
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int tap = 0; tap < 9; ++tap) {
                 const unsigned short* ip = in + ((oy[h] + tap / 3) * Win + ox[h] + tap % 3) * PI + (CI / 4) * kq;
                 const typename AFrag<CI>::Q av = *reinterpret_cast<const typename AFrag<CI>::Q*>(ip);
 #pragma unroll

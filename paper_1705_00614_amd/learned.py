@@ -125,9 +125,9 @@ def compare(net, fine_sc, r, m, intervals, skip=0):
 
 
 def timing(net, fine_sc, r, sim_seconds, skip=0):
-    """Wall time of the fine solve and of the learned coarse solve (network
-    included) over the same simulated interval, each with its own CFL steps
-    and hipGraph replays."""
+    """Wall time of the fine solve, of the learned coarse solve (network
+    included) and of the plain coarse solve over the same simulated
+    interval, each with its own CFL steps and hipGraph replays."""
     import torch
     f = swe.Solver(fine_sc)
     if skip:
@@ -135,10 +135,12 @@ def timing(net, fine_sc, r, sim_seconds, skip=0):
     csc = coarsen(fine_sc, r)
     g = swe.Solver(csc)
     g.restrict_from(f, r)
+    p = swe.Solver(csc)
+    p.restrict_from(f, r)
     net.attach(g)
     g.set_correction_depth(CORR_DEPTH)
     res = {}
-    for name, s in (("fine", f), ("learned", g)):
+    for name, s in (("fine", f), ("learned", g), ("plain", p)):
         t0 = s.time()
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -149,6 +151,6 @@ def timing(net, fine_sc, r, sim_seconds, skip=0):
         torch.cuda.synchronize()
         res[name] = dict(wall=time.perf_counter() - w0, steps=steps, sim=s.time() - t0)
     net.detach(g)
-    f.close()
-    g.close()
+    for s in (f, g, p):
+        s.close()
     return res
