@@ -9,6 +9,8 @@ Paper: arXiv 1705.00614, Sec. 2.1 (Eqs. 1-4), Sec. 2.3 (stages I-IV), Sec. 3
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 from scipy.integrate import quad
@@ -479,6 +481,38 @@ def test_k1_rule_matches_brute_force(shape, tile):
             for ti in range(own.shape[1]):
                 blk = wet[tj * tile[1]:(tj + 1) * tile[1], ti * tile[0]:(ti + 1) * tile[0]]
                 assert own[tj, ti] == int(blk.any())
+
+
+def _golden_k1_cases():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "k1_wet_blocks.txt")
+    cases, cur = [], None
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "case":
+            cur = dict(name=f[1], H=np.zeros((8, 12)), src=np.zeros((8, 12), bool))
+            cases.append(cur)
+        elif f[0] == "eps":
+            cur["eps"] = float(f[1])
+        elif f[0] == "cell":
+            cur["H"][int(f[2]), int(f[1])] = float(f[3])
+        elif f[0] == "source":
+            cur["src"][int(f[2]), int(f[1])] = True
+        else:
+            cur[f[0]] = np.array([int(v) for v in f[1:]]).reshape(2, 3)
+    return cases
+
+
+def test_k1_rule_matches_hand_worked_golden_cases():
+    """Two 12 x 8 grids of 4 x 4 tiles whose own and ring flags were worked
+    out by hand from the K1 rule (tests/golden/k1_wet_blocks.txt)."""
+    cases = _golden_k1_cases()
+    assert [c["name"] for c in cases] == ["A", "B"]
+    for c in cases:
+        own, ring = orc.tile_flags(c["H"], 4, 4, c["eps"], c["src"])
+        assert np.array_equal(own, c["own"]), c["name"]
+        assert np.array_equal(ring, c["ring"]), c["name"]
 
 
 def test_dry_cells_away_from_water_are_untouched():
