@@ -83,7 +83,9 @@ typedef struct {
  * b [m] and Manning coefficient n_M (both nx*ny, host FP64; n_M may be NULL
  * for no friction).  Allocates the state in device memory, uploads the
  * inputs, and computes the wet tiles and the first time step from layer 0.
- * Returns NULL on error (see swe_last_error). */
+ * Limits: nx*ny < 2^31 cells and fewer than 2^20 tiles of the tile shape
+ * (with 32 x 32 tiles up to about 1.07e9 cells).  Returns NULL on error
+ * (see swe_last_error). */
 swe_t* swe_create(int nx, int ny, double dx, const double* b, const double* n_M,
                   const swe_params* p);
 

@@ -491,6 +491,10 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
     }
     const Launcher* L = find_launcher(p->precision, p->tile_x, p->tile_y, p->limiter);
     if (!L) { set_err("swe_create: tile shape not available for this precision"); return nullptr; }
+    // a tile-list entry holds the tile index in TILE_BITS bits
+    if ((long long)((nx + L->tx - 1) / L->tx) * ((ny + L->ty - 1) / L->ty) >= (1LL << swe::TILE_BITS)) {
+        set_err("swe_create: grid has too many tiles for the tile list (at most 2^20 - 1)"); return nullptr;
+    }
     const size_t n = (size_t)nx * ny;
     for (size_t i = 0; i < n; ++i) {
         if (!std::isfinite(b[i]) || (n_M && (!std::isfinite(n_M[i]) || n_M[i] < 0.0))) {
