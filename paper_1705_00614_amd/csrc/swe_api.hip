@@ -531,6 +531,9 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
         if (s->ntap > 0 && !L->step_tap) {
             set_err("nest: the tile shape has no tapping step kernel"); delete s; return nullptr;
         }
+        if (s->nring > 0 && s->ntap <= 0) {   // only the tapping step kernel steps ring tiles
+            set_err("nest: a grid with ring tiles must tap its faces"); delete s; return nullptr;
+        }
     }
     if (p->solid) s->solid.assign(p->solid, p->solid + (size_t)nx * ny);
     s->ntx = (nx + L->tx - 1) / L->tx;

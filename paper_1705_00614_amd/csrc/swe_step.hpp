@@ -1021,8 +1021,11 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     if (ctrl->err_gate) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int G = gridDim.x, grp = blockIdx.x % NSEG;
+    // only the patches of a nest (tapping grids) carry ring tiles; the other
+    // variants compile without them (no registers held for their bounds)
+    constexpr bool RING = MODE == MODE_TAP;
     const int nlist = a.skip ? ctrl->seg_off[a.slot][NSEG] : a.ntiles;
-    const int count = nlist + (a.skip ? a.nring : 0);   // list entries, then the ring tiles
+    const int count = nlist + (RING && a.skip ? a.nring : 0);   // list entries, then the ring tiles
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
     const int gen = (int)ctrl->step + 2;
@@ -1034,8 +1037,8 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
 
     for (int p = blockIdx.x; p < count; p += G) {
         const int tile = !a.skip ? p
-                         : p < nlist ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p))
-                                     : a.ring_tiles[p - nlist];
+                         : !RING || p < nlist ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p))
+                                              : a.ring_tiles[p - nlist];
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
@@ -1044,7 +1047,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         // the tile's clamp ledger is read now and written back at the end
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
         const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
-                         a.skip != 0 && !ring_tile(a, tile)};
+                         a.skip != 0 && !(RING && ring_tile(a, tile))};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
             tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
@@ -1081,7 +1084,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
                 if (lane == 2 && (bb & 4) && ti < a.ntx - 1 && fresh) cand = tile + 1;
                 if (lane == 3 && (bb & 8) && tj > 0 && fresh) cand = tile - a.ntx;
                 if (lane == 4 && (bb & 16) && tj < a.nty - 1 && fresh) cand = tile + a.ntx;
-                if (cand >= 0 && ring_tile(a, cand)) cand = -1;
+                if (RING && cand >= 0 && ring_tile(a, cand)) cand = -1;
                 append_tiles(cand, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp);
             }
         }

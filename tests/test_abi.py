@@ -98,7 +98,6 @@ def test_create_rejects_more_tiles_than_a_list_entry_holds():
     """A tile-list entry keeps the tile index in 20 bits: a 32768 x 32768
     grid of 32 x 32 tiles (2^20 tiles) is refused before the inputs are read
     or any device memory is touched (the one-element bed is never read)."""
-    from paper_1705_00614_amd import scenarios as S
     L = swe.load()
     p = swe.make_params(S.dam_break(nx=16, ny=8)["params"])
     b = np.zeros(1)
