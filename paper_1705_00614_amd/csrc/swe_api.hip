@@ -2288,14 +2288,23 @@ hipError_t lc_pre_step_t(swe_t* s, int par) {
     const Args<real>& a = *(const Args<real>*)s->args[par].data();
     const int S = c->S, So = c->So, Sin = So + 2 * L_::HALO;
     const int slot = par;
-    const int* cnt = s->p.skip_dry ? &s->ctrl->seg_off[slot][swe::NSEG] : nullptr;
     const int nmax = s->ntiles;
+    c->last_n = 0;   // the stored activations are not those of one forward
+    if (So >= NET_T) {   // gather, network and scatter in one launch
+        const int ns = (So + NET_T - 1) / NET_T;
+        const long long units = (long long)nmax * ns * ns;
+        const int grid = (int)(units < c->net_blocks ? units : c->net_blocks);
+        hipLaunchKernelGGL((L_::k_net_grid<NET_T, NET_NTH, real>), dim3(grid > 0 ? grid : 1), dim3(NET_NTH), 0,
+                           s->stream, a, slot, S, c->dscale, c->dscale + 6, (real*)s->corrE, (real*)s->corrN, c->wf,
+                           c->params);
+        return hipGetLastError();
+    }
+    const int* cnt = s->p.skip_dry ? &s->ctrl->seg_off[slot][swe::NSEG] : nullptr;
     hipLaunchKernelGGL(L_::k_gather<real>, dim3(grid_for((long long)nmax * Sin * Sin, 256)), dim3(256), 0, s->stream,
                        a, slot, S, c->dscale, c->act[0], (int*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = lc_infer(c, nmax, cnt, s->stream)) != hipSuccess) return e;
-    c->last_n = 0;
+    if ((e = lc_forward(c, nmax, cnt, s->stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(L_::k_scatter<real>, dim3(grid_for((long long)nmax * So * So, 256)), dim3(256), 0, s->stream, a,
                        slot, S, c->dscale + 6, c->out, (real*)s->corrE, (real*)s->corrN);
     return hipGetLastError();

@@ -205,12 +205,14 @@ struct alignas(16) NetLds {
 };
 
 // One layer over the LDS plane `in` (side Win, pixel stride PI) into `out`
-// (LDS bf16 with tanh, stride PO) or, for the last layer, into the FP32 crop
-// output in HBM at block origin (oy0, ox0).
-template <int CI, int CO, bool LAST, int Win, int NTH>
+// (LDS bf16 with tanh, stride PO) or, for the last layer, through the writer
+// `wr(oy, ox, ch, v)` (block-local output pixel, channel, FP32 value).
+struct NoWriter {
+    __device__ __forceinline__ void operator()(int, int, int, float) const {}
+};
+template <int CI, int CO, bool LAST, int Win, int NTH, class Wr>
 __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsigned short* out, int PO,
-                                          const unsigned short* w, const float* bias, int cob, float* y, int So,
-                                          int c, int oy0, int ox0) {
+                                          const unsigned short* w, const float* bias, int cob, const Wr& wr) {
     constexpr int NT = CO / 16, Wout = Win - 2, P = Wout * Wout, blocks = (P + 15) / 16, nw = NTH / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
@@ -271,8 +273,7 @@ __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsi
                     const float v = acc[h][t][i] + bb[t];
                     if constexpr (LAST) {
                         if (pp >= P) continue;
-                        const int gy = oy0 + pp / Wout, gx = ox0 + pp % Wout;
-                        y[(((size_t)c * So + gy) * So + gx) * CO + ch] = ch < cob ? v : 0.f;
+                        wr(pp / Wout, pp % Wout, ch, ch < cob ? v : 0.f);
                     } else {
                         out[pp * PO + ch] = to_bf16(tanh_act(v));   // pp < blocks * 16: inside the padded plane
                     }
@@ -282,40 +283,24 @@ __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsi
     }
 }
 
-// The two 16-byte pieces (thread tid and tid + NTH) of unit u's input window:
-// rows oy0 .. oy0+T+7 of its crop, 16 bf16 channels = 2 pieces per pixel.
-template <int T, int NTH>
-__device__ __forceinline__ void net_window(const unsigned short* __restrict__ x, int u, int ns, int So, int Sin,
-                                           int tid, uint4& r0, uint4& r1) {
-    constexpr int W0 = T + 2 * HALO, XV = W0 * W0 * 2;
-    const int c = u / (ns * ns), sub = u % (ns * ns);
-    const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
-    const unsigned short* xc = x + (size_t)c * Sin * Sin * 16;
-    const int k0 = tid, k1 = tid + NTH;   // k0 < XV always (XV > NTH)
-    r0 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k0 >> 1) / W0) * Sin + ox0 + (k0 >> 1) % W0) * 16 +
-                                         8 * (k0 & 1));
-    if (k1 < XV)
-        r1 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k1 >> 1) / W0) * Sin + ox0 + (k1 >> 1) % W0) * 16 +
-                                             8 * (k1 & 1));
-}
-
-// x: crops [n][So+8][So+8][16] bf16; y: [n][So][So][16] FP32 (channels >= 6
-// zero); wf: bf16 weights of all layers; params: packed FP32 parameters (the
-// biases are read from there).  Requires So >= T; n from the device or host.
-template <int T, int NTH>
-__global__ __launch_bounds__(NTH) void k_net_fwd(const unsigned short* __restrict__ x, float* __restrict__ y,
-                                                 const unsigned short* __restrict__ wf,
-                                                 const float* __restrict__ params, int So, const int* cnt_dev,
-                                                 int cnt_host) {
-    __shared__ NetLds<T> L;
+// All units of n crops through the four layers.  The source `src` (a
+// read-only descriptor; what it fetches is held in three 16-byte registers
+// of the caller, plain locals so that they stay in VGPRs) provides the
+// input windows and the output writers:
+//   src.load(u, q0, q1, q2)    fetch unit u's input window,
+//   src.store(lds, q0, q1, q2) put it into the LDS plane (pixel stride 24),
+//   src.writer(c, oy0, ox0) the last layer's writer for a block of crop c.
+// The next unit's window is fetched while the current one computes.
+template <int T, int NTH, class Src>
+__device__ __forceinline__ void net_run(const Src& src, NetLds<T>& L, const unsigned short* __restrict__ wf,
+                                        const float* __restrict__ params, int So, int n) {
     using N = NetLds<T>;
-    const int n = crop_count(cnt_dev, cnt_host);
     const int ns = (So + T - 1) / T, units = n * ns * ns;
     if ((int)blockIdx.x >= units) return;
-    const int tid = threadIdx.x, Sin = So + 2 * HALO;
+    const int tid = threadIdx.x;
     constexpr int W0 = T + 2 * HALO;
-    // every global load of a staging loop is issued before the first store
-    // (one memory round trip per loop, not one per iteration)
+    // every global load of the weight staging is issued before the first
+    // store (one memory round trip, not one per piece)
     {
         constexpr int NV = NWB / 8, J = (NV + NTH - 1) / NTH;
         uint4 v[J];
@@ -335,35 +320,76 @@ __global__ __launch_bounds__(NTH) void k_net_fwd(const unsigned short* __restric
         const int off = l == 0 ? b0 : l == 1 ? b1 : l == 2 ? b2 : b3;
         L.bias[l][ch] = ch < (l == NL - 1 ? COUT_REAL[NL - 1] : 32) ? params[off + ch] : 0.f;
     }
-    // input window of unit u (rows oy0 .. oy0+T+7 of its crop, 16 channels =
-    // 2 x 16 B per pixel) into registers: the next unit's window is loaded
-    // while the current one computes
-    constexpr int XV = W0 * W0 * 2, XJ = (XV + NTH - 1) / NTH;
-    uint4 xr0, xr1;
-    static_assert(XJ == 2, "two 16-byte pieces of the input window per thread");
-    net_window<T, NTH>(x, blockIdx.x, ns, So, Sin, tid, xr0, xr1);
+    uint4 q0, q1, q2;
+    src.load(blockIdx.x, q0, q1, q2);
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
         const int c = u / (ns * ns), sub = u % (ns * ns);
         const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
-        *reinterpret_cast<uint4*>(L.a + (tid >> 1) * N::P16 + 8 * (tid & 1)) = xr0;
-        if (tid + NTH < XV) *reinterpret_cast<uint4*>(L.a + ((tid + NTH) >> 1) * N::P16 + 8 * (tid & 1)) = xr1;
+        src.store(L.a, q0, q1, q2);
         __syncthreads();
-        if (u + (int)gridDim.x < units) net_window<T, NTH>(x, u + gridDim.x, ns, So, Sin, tid, xr0, xr1);
-        net_layer<16, 32, false, W0, NTH>(L.a, N::P16, L.b, N::P32, L.w + wb_off(0), L.bias[0], 32, nullptr, So, c,
-                                          0, 0);
+        if (u + (int)gridDim.x < units) src.load(u + gridDim.x, q0, q1, q2);
+        const NoWriter nw;
+        net_layer<16, 32, false, W0, NTH>(L.a, N::P16, L.b, N::P32, L.w + wb_off(0), L.bias[0], 32, nw);
         __syncthreads();
-        net_layer<32, 32, false, W0 - 2, NTH>(L.b, N::P32, L.a, N::P32, L.w + wb_off(1), L.bias[1], 32, nullptr, So,
-                                              c, 0, 0);
+        net_layer<32, 32, false, W0 - 2, NTH>(L.b, N::P32, L.a, N::P32, L.w + wb_off(1), L.bias[1], 32, nw);
         __syncthreads();
-        net_layer<32, 32, false, W0 - 4, NTH>(L.a, N::P32, L.b, N::P32, L.w + wb_off(2), L.bias[2], 32, nullptr, So,
-                                              c, 0, 0);
+        net_layer<32, 32, false, W0 - 4, NTH>(L.a, N::P32, L.b, N::P32, L.w + wb_off(2), L.bias[2], 32, nw);
         __syncthreads();
-        net_layer<32, 16, true, W0 - 6, NTH>(L.b, N::P32, nullptr, 0, L.w + wb_off(3), L.bias[3], COUT_REAL[3], y,
-                                             So, c, oy0, ox0);
+        net_layer<32, 16, true, W0 - 6, NTH>(L.b, N::P32, nullptr, 0, L.w + wb_off(3), L.bias[3], COUT_REAL[3],
+                                             src.writer(c, oy0, ox0));
         // the next unit's input goes to L.a, last read by layer 2 (before the
         // barrier above); layer 3 reads L.b, next written after the barrier
         // that follows the next input
     }
+}
+
+// Writer of the last layer into the FP32 crop output y [n][So][So][16].
+struct CropWriter {
+    float* y;
+    int So, c, oy0, ox0;
+    __device__ __forceinline__ void operator()(int oy, int ox, int ch, float v) const {
+        y[(((size_t)c * So + oy0 + oy) * So + ox0 + ox) * 16 + ch] = v;
+    }
+};
+
+// Source of crops already in HBM: x [n][So+8][So+8][16] bf16; each thread
+// moves two 16-byte pieces (tid and tid + NTH) of the window.
+template <int T, int NTH>
+struct CropSource {
+    static constexpr int W0 = T + 2 * HALO, XV = W0 * W0 * 2;
+    static_assert(XV > NTH && XV <= 2 * NTH, "two 16-byte pieces of the input window per thread");
+    const unsigned short* x;
+    float* y;
+    int So, ns, tid;
+    __device__ __forceinline__ void load(int u, uint4& q0, uint4& q1, uint4&) const {
+        const int Sin = So + 2 * HALO, c = u / (ns * ns), sub = u % (ns * ns);
+        const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
+        const unsigned short* xc = x + (size_t)c * Sin * Sin * 16;
+        const int k0 = tid, k1 = tid + NTH;
+        q0 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k0 >> 1) / W0) * Sin + ox0 + (k0 >> 1) % W0) *
+                                                        16 + 8 * (k0 & 1));
+        if (k1 < XV)
+            q1 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k1 >> 1) / W0) * Sin + ox0 + (k1 >> 1) % W0) *
+                                                          16 + 8 * (k1 & 1));
+    }
+    __device__ __forceinline__ void store(unsigned short* a, const uint4& q0, const uint4& q1, const uint4&) const {
+        *reinterpret_cast<uint4*>(a + (tid >> 1) * NetLds<T>::P16 + 8 * (tid & 1)) = q0;
+        if (tid + NTH < XV) *reinterpret_cast<uint4*>(a + ((tid + NTH) >> 1) * NetLds<T>::P16 + 8 * (tid & 1)) = q1;
+    }
+    __device__ __forceinline__ CropWriter writer(int c, int oy0, int ox0) const { return CropWriter{y, So, c, oy0, ox0}; }
+};
+
+// x: crops [n][So+8][So+8][16] bf16; y: [n][So][So][16] FP32 (channels >= 6
+// zero); wf: bf16 weights of all layers; params: packed FP32 parameters (the
+// biases are read from there).  Requires So >= T; n from the device or host.
+template <int T, int NTH>
+__global__ __launch_bounds__(NTH) void k_net_fwd(const unsigned short* __restrict__ x, float* __restrict__ y,
+                                                 const unsigned short* __restrict__ wf,
+                                                 const float* __restrict__ params, int So, const int* cnt_dev,
+                                                 int cnt_host) {
+    __shared__ NetLds<T> L;
+    const CropSource<T, NTH> src{x, y, So, (So + T - 1) / T, (int)threadIdx.x};
+    net_run<T, NTH>(src, L, wf, params, So, crop_count(cnt_dev, cnt_host));
 }
 
 // ------------------------------------------------------------------ backward data
@@ -574,6 +600,35 @@ __device__ __forceinline__ int crop_tile(const Args<real>& a, int slot, int p) {
     return a.skip ? entry_tile(list_entry(a.ctrl, a.lists, a.ntiles, slot, p)) : p;
 }
 
+// Grid cell (mirrored at walls) of pixel (wx, wy) of a tile's (S+9)^2 input
+// window, which starts HALO + 1 cells before the tile.
+template <typename real>
+__device__ __forceinline__ int crop_cell(const Args<real>& a, int tile, int S, int wx, int wy) {
+    int fx = 0, fy = 0;
+    const int gx = mirror((tile % a.ntx) * S - 1 - HALO + wx, a.nx, fx);
+    const int gy = mirror((tile / a.ntx) * S - 1 - HALO + wy, a.ny, fy);
+    return gy * a.nx + gx;
+}
+
+// The stored values of one cell and its six network features (depth,
+// velocity, bed, sqrt(c_f / g) = Manning n, wet flag), divided by the input
+// scales, as bf16.
+template <typename real> struct CellIn { real H, qx, qy, b, cf; };
+template <typename real>
+__device__ __forceinline__ void features(const Args<real>& a, const CellIn<real>& v, const float* iscale,
+                                         unsigned short (&o)[6]) {
+    const bool w = v.H > a.eps;
+    float f[6];
+    f[0] = (float)v.H;
+    f[1] = w ? (float)(v.qx / v.H) : 0.f;
+    f[2] = w ? (float)(v.qy / v.H) : 0.f;
+    f[3] = (float)v.b;
+    f[4] = sqrtf((float)v.cf / (float)a.g_d);
+    f[5] = w ? 1.f : 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o[c] = to_bf16(f[c] / iscale[c]);
+}
+
 // Input crops of the active tiles: the six features of every cell of each
 // (S+9)^2 window (mirrored at walls), divided by the input scales, as bf16.
 template <typename real>
@@ -585,22 +640,13 @@ __global__ void k_gather(Args<real> a, int slot, int S, const float* __restrict_
         const int p = k / P, q = k % P;
         const int tile = crop_tile(a, slot, p);
         if (tiles_out && q == 0) tiles_out[p] = tile;
-        const int tx = tile % a.ntx, ty = tile / a.ntx;
-        int fx = 0, fy = 0;
-        const int gx = mirror(tx * S - 1 - HALO + q % Sin, a.nx, fx), gy = mirror(ty * S - 1 - HALO + q / Sin, a.ny, fy);
-        const int gi = gy * a.nx + gx;
-        const real H = a.Hi[gi];
-        const bool w = H > a.eps;
-        float f[6];
-        f[0] = (float)H;
-        f[1] = w ? (float)(a.Qxi[gi] / H) : 0.f;
-        f[2] = w ? (float)(a.Qyi[gi] / H) : 0.f;
-        f[3] = (float)a.bed[gi];
-        f[4] = sqrtf((float)a.cf[gi] / (float)a.g_d);
-        f[5] = w ? 1.f : 0.f;
+        const int gi = crop_cell(a, tile, S, q % Sin, q / Sin);
+        const CellIn<real> v{a.Hi[gi], a.Qxi[gi], a.Qyi[gi], a.bed[gi], a.cf[gi]};
+        unsigned short f[6];
+        features(a, v, iscale, f);
         unsigned short* o = x + (size_t)k * 16;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) o[c] = to_bf16(f[c] / iscale[c]);
+        for (int c = 0; c < 6; ++c) o[c] = f[c];
     }
 }
 
@@ -625,6 +671,91 @@ __global__ void k_scatter(Args<real> a, int slot, int S, const float* __restrict
             corrN[c * nc + gi] = (real)(o[3 + c] * oscale[3 + c]);
         }
     }
+}
+
+// Writer of the last layer straight into a grid's correction planes (what
+// k_scatter does from the crop output): crop pixel (oy0 + oy, ox0 + ox) is
+// grid cell (x0 + ox, y0 + oy), x0 = tile column * S - 1 + ox0.
+template <typename real>
+struct CorrWriter {
+    real* corrE;
+    real* corrN;
+    const float* oscale;
+    int nx, ny, x0, y0;
+    __device__ __forceinline__ void operator()(int oy, int ox, int ch, float v) const {
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (ch >= 6 || gx < 0 || gy < 0 || gx >= nx || gy >= ny) return;
+        const size_t nc = (size_t)nx * ny, gi = (size_t)gy * nx + gx;
+        if (ch < 3) corrE[ch * nc + gi] = (real)(v * oscale[ch]);
+        else corrN[(ch - 3) * nc + gi] = (real)(v * oscale[ch]);
+    }
+};
+
+// Source of the input windows straight from a grid's current layer (what
+// k_gather does into HBM): thread tid < (T+8)^2 fetches the five stored
+// values of one window pixel and turns them into its features at the store.
+template <int T, int NTH, typename real>
+struct GridSource {
+    static constexpr int W0 = T + 2 * HALO;
+    static_assert(W0 * W0 <= NTH, "one window pixel per thread");
+    static_assert(5 * sizeof(real) <= 48, "five stored values in three 16-byte registers");
+    const Args<real>* a;
+    int slot, S, So, ns, tid;
+    const float* iscale;
+    real* corrE;
+    real* corrN;
+    const float* oscale;
+    __device__ __forceinline__ int origin(int u, int& tile, int& oy0, int& ox0) const {
+        const int c = u / (ns * ns), sub = u % (ns * ns);
+        oy0 = min((sub / ns) * T, So - T);
+        ox0 = min((sub % ns) * T, So - T);
+        tile = crop_tile(*a, slot, c);
+        return c;
+    }
+    __device__ __forceinline__ void load(int u, uint4& q0, uint4& q1, uint4& q2) const {
+        if (tid >= W0 * W0) return;
+        int tile, oy0, ox0;
+        origin(u, tile, oy0, ox0);
+        const int gi = crop_cell(*a, tile, S, ox0 + tid % W0, oy0 + tid / W0);
+        real v[6] = {a->Hi[gi], a->Qxi[gi], a->Qyi[gi], a->bed[gi], a->cf[gi], real(0)};
+        uint4 q[3];
+        static_assert(sizeof v <= sizeof q, "fits");
+        __builtin_memcpy(q, v, sizeof v);
+        q0 = q[0]; q1 = q[1]; q2 = q[2];
+    }
+    __device__ __forceinline__ void store(unsigned short* lds, const uint4& q0, const uint4& q1, const uint4& q2) const {
+        if (tid >= W0 * W0) return;
+        const uint4 q[3] = {q0, q1, q2};
+        real v[6];
+        __builtin_memcpy(v, q, sizeof v);
+        unsigned short f[6];
+        features(*a, CellIn<real>{v[0], v[1], v[2], v[3], v[4]}, iscale, f);
+        const uint4 lo = {f[0] | ((unsigned)f[1] << 16), f[2] | ((unsigned)f[3] << 16), f[4] | ((unsigned)f[5] << 16), 0u};
+        *reinterpret_cast<uint4*>(lds + tid * NetLds<T>::P16) = lo;
+        *reinterpret_cast<uint4*>(lds + tid * NetLds<T>::P16 + 8) = uint4{0u, 0u, 0u, 0u};
+    }
+    __device__ __forceinline__ CorrWriter<real> writer(int c, int oy0, int ox0) const {
+        const int tile = crop_tile(*a, slot, c);
+        return CorrWriter<real>{corrE, corrN, oscale, a->nx, a->ny, (tile % a->ntx) * S - 1 + ox0,
+                                (tile / a->ntx) * S - 1 + oy0};
+    }
+};
+
+// Before a step of a grid with an attached network: crops of the active
+// tiles of list `slot`, the four layers and the corrections of those tiles
+// in one launch (the work of k_gather, the four forward layers and
+// k_scatter, with the same arithmetic per value).  Requires S + 1 >= T.
+template <int T, int NTH, typename real>
+__global__ __launch_bounds__(NTH) void k_net_grid(Args<real> a, int slot, int S, const float* __restrict__ iscale,
+                                                  const float* __restrict__ oscale, real* __restrict__ corrE,
+                                                  real* __restrict__ corrN, const unsigned short* __restrict__ wf,
+                                                  const float* __restrict__ params) {
+    __shared__ NetLds<T> L;
+    const int So = S + 1;
+    const GridSource<T, NTH, real> src{&a, slot, S, So, (So + T - 1) / T, (int)threadIdx.x, iscale, corrE, corrN,
+                                       oscale};
+    const int n = a.skip ? a.ctrl->seg_off[slot][NSEG] : a.ntiles;
+    net_run<T, NTH>(src, L, wf, params, So, n);
 }
 
 // Training labels of n crops (coarse tiles tiles[p], (S+1)^2 cells from the

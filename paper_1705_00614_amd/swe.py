@@ -301,7 +301,10 @@ class Solver:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:   # at interpreter exit the module's globals may already be gone
+            pass
 
     def step(self):
         return _check(load().swe_step(self._h))
@@ -424,7 +427,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:   # at interpreter exit the module's globals may already be gone
+            pass
 
     def run(self, n):
         return _check(load().swe_batch_run(self._h, int(n)))
@@ -506,7 +512,10 @@ class Nest:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:   # at interpreter exit the module's globals may already be gone
+            pass
 
     def run(self, n):
         return _check(load().swe_nest_run(self._h, int(n)))
@@ -586,7 +595,10 @@ class Net:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:   # at interpreter exit the module's globals may already be gone
+            pass
 
     def set_params(self, p):
         p = np.ascontiguousarray(p, dtype=np.float64)

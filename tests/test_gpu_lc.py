@@ -263,6 +263,50 @@ def test_attached_network_matches_oracle():
     net.detach(g)
 
 
+def test_fused_pre_step_equals_gather_forward_scatter():
+    """The one-launch pre-step of an attached grid (crop features, the four
+    layers and the correction write in one kernel) against the same work
+    done in separate calls on a twin grid: its crops (swe_lc_gather), the
+    layer-by-layer forward, the corrections placed on the host exactly as the
+    scatter does (FP32 product of output and scale) and handed over with
+    swe_set_correction.  The two grids stay bitwise equal step by step."""
+    sc = _flood32()
+    W, b = LN.init_params(23)
+    rng = np.random.default_rng(5)
+    b = [rng.normal(scale=0.05, size=v.shape) for v in b]
+    out_scale = OUT_SCALE * 0.1
+    A, B = swe.Solver(sc), swe.Solver(sc)
+    A.run(20)
+    B.run(20)
+    nt = A.work()["ntiles"]
+    net = swe.Net(32, nt, IN_SCALE, out_scale)
+    net.set_params(swe.lc_pack(W, b))
+    net.attach(A)
+    for g in (A, B):
+        g.set_correction_depth(0.01)
+    ny, nx, ntx = sc["ny"], sc["nx"], sc["nx"] // 32
+    os32 = out_scale.astype(np.float32)
+    for step in range(6):
+        x, tiles = net.gather(B)
+        assert len(tiles) > 0
+        out = net.forward(x)
+        dE, dN = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
+        for p, t in enumerate(tiles):
+            gx = (t % ntx) * 32 - 1 + np.arange(33)
+            gy = (t // ntx) * 32 - 1 + np.arange(33)
+            ix, iy = (gx >= 0) & (gx < nx), (gy >= 0) & (gy < ny)
+            v = (out[p].astype(np.float32) * os32).astype(np.float64)[np.ix_(iy, ix)]
+            for c in range(3):
+                dE[c][np.ix_(gy[iy], gx[ix])] = v[..., c]
+                dN[c][np.ix_(gy[iy], gx[ix])] = v[..., 3 + c]
+        B.set_correction(dE, dN)
+        A.run(1)
+        B.run(1)
+        for fa, fb in zip(A.state(), B.state()):
+            assert np.array_equal(fa, fb), step
+    net.detach(A)
+
+
 # ---------------------------------------------------------------- training data
 
 def test_line_taps_match_oracle_faces():
