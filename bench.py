@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--corr-depth", type=float, default=None, metavar="M",
+                    help="learned leg: depth both cells of a face need for a momentum correction")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     ap.add_argument("--warmup-launches", action="store_true",
@@ -337,6 +339,7 @@ def bench_learned(args):
     from paper_1705_00614_amd import swe
     n, r, m = args.n, 4, 4
     ntrain, nheld, iters = 64, 16, 2000
+    cd = LC.CORR_DEPTH if args.corr_depth is None else args.corr_depth
     mk = lambda seed: S.floodplain(n=n, h=25.0, seed=seed, q_peak=3.0e4, t_peak=1800.0, sigma_t=600.0)
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
@@ -359,15 +362,15 @@ def bench_learned(args):
               file=sys.stderr, flush=True)
         errs = []
         for k in range(nheld):
-            errs.append(LC.compare(net, mk(3000 + k), r, m, intervals=150))
+            errs.append(LC.compare(net, mk(3000 + k), r, m, intervals=150, corr_depth=cd))
             print("learned: held-out seed %d %s" % (3000 + k, errs[-1]), file=sys.stderr, flush=True)
-        tim = LC.timing(net, mk(3000), r, sim_seconds=900.0)
+        tim = LC.timing(net, mk(3000), r, sim_seconds=900.0, corr_depth=cd)
     speed = (tim["fine"]["wall"] / tim["fine"]["sim"]) / (tim["learned"]["wall"] / tim["learned"]["sim"])
     _line("learned coarse: speedup over the fine solve (same simulated time)", speed, "x", tim["learned"]["steps"],
           0, tim["learned"]["wall"] * 1e3 / tim["learned"]["steps"], "bf16/f32",
           {"workload": "floodplain %dx%d at 25 m (fine) vs %dx%d at 100 m + network; %d training runs, %d held out"
                        % (n, n, n // r, n // r, ntrain, nheld),
-           "training_crops": count, "fit_iterations": iters, "fit_seconds": fit_s,
+           "training_crops": count, "fit_iterations": iters, "fit_seconds": fit_s, "correction_depth_m": cd,
            "loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
            "depth_error_plain_coarse": [e["err_plain"] for e in errs],
            "depth_error_learned_coarse": [e["err_learned"] for e in errs],
