@@ -123,7 +123,7 @@ def cpu_baseline(sc, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU decomposition is a design, not a measured path)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

@@ -3,7 +3,7 @@
 // A small convolutional network (four 3x3 valid convolutions, 6 -> 32 -> 32
 // -> 32 -> 6 channels, tanh after the first three) reads the state of a
 // coarse grid and predicts corrections of the stage III face fluxes (Sec. 2.3
-// of arXiv 1705.00614; the learned part is an addition of this build, the
+// of arXiv 1705.00614; the learned part is an extension of the method, the
 // paper has none).  The network runs on crops: for an active S x S tile the
 // (S+9)^2 window round the tile and the cell row and column before it
 // (mirrored at walls) gives the (S+1)^2 corrections of those cells, so that
