@@ -143,10 +143,15 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
                 sX += (double)d.Qxf[pf][gf];
                 sY += (double)d.Qyf[pf][gf];
             }
+        // the restricted cell follows the dry rule of every stored layer: no
+        // discharge in a cell with H <= eps (the block mean of a few wet fine
+        // cells can leave a dry coarse cell)
         const double inv = 1.0 / (double)(r * r);
-        n.Hc[po][gc] = (real)(sH * inv);
-        n.Qxc[po][gc] = (real)(sX * inv);
-        n.Qyc[po][gc] = (real)(sY * inv);
+        const real Hm = (real)(sH * inv);
+        const bool w = Hm > n.eps;
+        n.Hc[po][gc] = Hm;
+        n.Qxc[po][gc] = w ? (real)(sX * inv) : real(0);
+        n.Qyc[po][gc] = w ? (real)(sY * inv) : real(0);
         return;
     }
     const int q = t - n.ncov;

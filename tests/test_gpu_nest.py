@@ -171,3 +171,24 @@ def test_patches_skip_dry_tiles_exactly(prec, tol, box):
         O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
         O.run(40)
         _compare(a, O, tol)
+
+
+def test_full_size_nest_first_coarse_steps_match_oracle():
+    """The nested-grid benchmark workload at its full size (2048^2 coarse
+    grid at 50 m with two 2048^2 patches at 12.5 m, dry-tile skipping) for
+    one 8-step graph replay, as the benchmark runs it, against the FP64
+    nested oracle on every cell of the coarse grid and both patches.  The
+    stencil runs in FP64 here so that the bar is the FP64 one (1e-10, as for
+    the small nests); the FP32 configuration is covered by the small FP32
+    nest and the bitwise skip and graph tests.  At this size covered coarse
+    cells occur whose block mean is dry (H <= eps) while some fine cells
+    carry water: they must store no discharge, like every dry cell."""
+    nest = S.nest_floodplain(n=2048, h=50.0, seed=1, r=4, box=512, precision=64)
+    G = swe.Nest(nest)
+    O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
+    G.run(8)
+    O.run(8)
+    _compare(G, O, 1e-10)
+    assert abs(G.query()["time"] - O.time()) <= 1e-12 * O.time()
+    for k in range(2):
+        assert (G.patch_state(k)[0] > 0).any()   # the patches hold water
