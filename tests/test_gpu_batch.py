@@ -124,3 +124,24 @@ def test_autotuner_rejects_bad_arguments():
     sc = S.floodplain(n=64, seed=22)
     with pytest.raises(swe.SweError):
         swe.autotune(sc, warmup=0, steps=0)
+
+
+def test_full_size_ensemble_sampled_scenarios_match_oracle():
+    """The 256-scenario ensemble of the benchmark at its full size (sides
+    256..2048, 2.65e8 cells) in one batch with the 32x32 tile the autotuner
+    picks there, for one 32-step graph replay as the benchmark runs it: the
+    three smallest scenarios (which the oracle steps in seconds) against the
+    FP64 oracle at the FP32 bar, and every scenario advanced 32 steps with a
+    finite, positive clock."""
+    ens = S.ensemble(n=256)
+    B = swe.Batch(ens, tile=(32, 32))
+    B.run(32)
+    for k in np.argsort([sc["nx"] * sc["ny"] for sc in ens], kind="stable")[:3]:
+        o = orc.OracleSim(ens[k])
+        o.run(32)
+        (H, Qx, Qy), (Ho, Qxo, Qyo) = B.state(int(k)), o.state()
+        assert np.abs(H - Ho).sum() <= 1e-4 * np.abs(Ho).sum(), k
+        assert np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum() <= 1e-4 * (np.abs(Qxo).sum() + np.abs(Qyo).sum()), k
+    q = B.query()
+    assert np.all(q["steps"] == 32)
+    assert np.all(np.isfinite(q["time"])) and np.all(q["time"] > 0)
