@@ -263,14 +263,24 @@ def test_attached_network_matches_oracle():
     net.detach(g)
 
 
-def test_fused_pre_step_equals_gather_forward_scatter():
+def _bench_coarse():
+    """The learned benchmark's coarse grid: the 4096^2 floodplain at 25 m
+    (held-out seed 3000) coarsened 4x to 1024^2 at 100 m."""
+    from paper_1705_00614_amd import learned as LC
+    from paper_1705_00614_amd import scenarios as S
+    return LC.coarsen(S.floodplain(n=4096, h=25.0, seed=3000, q_peak=3.0e4, t_peak=1800.0, sigma_t=600.0), 4)
+
+
+@pytest.mark.parametrize("size", ["small", "full"])
+def test_fused_pre_step_equals_gather_forward_scatter(size):
     """The one-launch pre-step of an attached grid (crop features, the four
     layers and the correction write in one kernel) against the same work
     done in separate calls on a twin grid: its crops (swe_lc_gather), the
     layer-by-layer forward, the corrections placed on the host exactly as the
     scatter does (FP32 product of output and scale) and handed over with
-    swe_set_correction.  The two grids stay bitwise equal step by step."""
-    sc = _flood32()
+    swe_set_correction.  The two grids stay bitwise equal step by step, on a
+    128^2 grid and on the learned benchmark's 1024^2 coarse grid."""
+    sc = _flood32() if size == "small" else _bench_coarse()
     W, b = LN.init_params(23)
     rng = np.random.default_rng(5)
     b = [rng.normal(scale=0.05, size=v.shape) for v in b]
