@@ -271,7 +271,7 @@ def _bench_coarse():
     return LC.coarsen(S.floodplain(n=4096, h=25.0, seed=3000, q_peak=3.0e4, t_peak=1800.0, sigma_t=600.0), 4)
 
 
-@pytest.mark.parametrize("size", ["small", "full"])
+@pytest.mark.parametrize("size", ["small", "full", "fp64"])
 def test_fused_pre_step_equals_gather_forward_scatter(size):
     """The one-launch pre-step of an attached grid (crop features, the four
     layers and the correction write in one kernel) against the same work
@@ -279,8 +279,14 @@ def test_fused_pre_step_equals_gather_forward_scatter(size):
     layer-by-layer forward, the corrections placed on the host exactly as the
     scatter does (FP32 product of output and scale) and handed over with
     swe_set_correction.  The two grids stay bitwise equal step by step, on a
-    128^2 grid and on the learned benchmark's 1024^2 coarse grid."""
-    sc = _flood32() if size == "small" else _bench_coarse()
+    128^2 grid, on the learned benchmark's 1024^2 coarse grid, and on an FP64
+    grid (16 x 16 tiles: crops of side 25, two overlapping blocks a side)."""
+    if size == "fp64":
+        from paper_1705_00614_amd import scenarios as S
+        sc = S.floodplain(n=128, h=50.0, seed=8, q_peak=3000.0, t_peak=300.0, sigma_t=200.0, inlet_cells=8,
+                          precision=64)
+    else:
+        sc = _flood32() if size == "small" else _bench_coarse()
     W, b = LN.init_params(23)
     rng = np.random.default_rng(5)
     b = [rng.normal(scale=0.05, size=v.shape) for v in b]
@@ -288,13 +294,13 @@ def test_fused_pre_step_equals_gather_forward_scatter(size):
     A, B = swe.Solver(sc), swe.Solver(sc)
     A.run(20)
     B.run(20)
-    nt = A.work()["ntiles"]
-    net = swe.Net(32, nt, IN_SCALE, out_scale)
+    nt, T = A.work()["ntiles"], A.work()["tile"][0]
+    net = swe.Net(T, nt, IN_SCALE, out_scale)
     net.set_params(swe.lc_pack(W, b))
     net.attach(A)
     for g in (A, B):
         g.set_correction_depth(0.01)
-    ny, nx, ntx = sc["ny"], sc["nx"], sc["nx"] // 32
+    ny, nx, ntx = sc["ny"], sc["nx"], -(-sc["nx"] // T)
     os32 = out_scale.astype(np.float32)
     for step in range(6):
         x, tiles = net.gather(B)
@@ -302,8 +308,8 @@ def test_fused_pre_step_equals_gather_forward_scatter(size):
         out = net.forward(x)
         dE, dN = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
         for p, t in enumerate(tiles):
-            gx = (t % ntx) * 32 - 1 + np.arange(33)
-            gy = (t // ntx) * 32 - 1 + np.arange(33)
+            gx = (t % ntx) * T - 1 + np.arange(T + 1)
+            gy = (t // ntx) * T - 1 + np.arange(T + 1)
             ix, iy = (gx >= 0) & (gx < nx), (gy >= 0) & (gy < ny)
             v = (out[p].astype(np.float32) * os32).astype(np.float64)[np.ix_(iy, ix)]
             for c in range(3):
