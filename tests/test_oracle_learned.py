@@ -222,3 +222,21 @@ def test_momentum_correction_depth_threshold():
     d.set_correction(dE2, None)
     d.step(tau)
     assert np.array_equal(d.state()[0], c.state()[0])
+
+
+def test_coarsen_takes_block_means_and_scales_the_inlet():
+    """Host logic of the learned leg: the coarse scenario of a fine one has
+    the r x r block means of bed, Manning n and state, the cell size times r,
+    the step cap times r (the same cap in Courant units) and the inlet
+    rectangle divided by r (at least one cell)."""
+    from paper_1705_00614_amd import learned as LC
+    sc = S.floodplain(n=64, h=25.0, seed=3, q_peak=500.0, t_peak=100.0, sigma_t=80.0, inlet_cells=6)
+    sc["params"] = dict(sc["params"], tau_max=2.0)
+    c = LC.coarsen(sc, 4)
+    assert (c["nx"], c["ny"], c["h"]) == (16, 16, 100.0)
+    for k in ("b", "n_manning", "H0", "Qx0", "Qy0"):
+        blk = np.asarray(sc[k], dtype=np.float64).reshape(16, 4, 16, 4)
+        assert np.allclose(c[k], blk.mean(axis=(1, 3)), rtol=0, atol=1e-12), k
+    assert c["params"]["tau_max"] == 8.0
+    i0, j0, ni, nj = sc["params"]["inlet"]
+    assert c["params"]["inlet"] == (i0 // 4, j0 // 4, max(ni // 4, 1), max(nj // 4, 1))
