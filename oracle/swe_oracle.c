@@ -359,12 +359,11 @@ static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
  *   U_s = max(|Ux|, |Uy|) + sqrt(g H),
  *   U_p = max(|Ux + sgn(Fx) sqrt(h|Fx|)|, |Uy + sgn(Fy) sqrt(h|Fy|)|),
  * maximum over wet cells, tau = min(tau_max, K h / max(U_s, U_p),
- * h^2/(4 nu)); a bound whose divisor is zero is left out.  Reading: F is the
- * explicitly integrated part of the Eq. (4) force (viscosity, Coriolis,
- * wind).  Friction enters the step through a point-implicit factor that can
- * only slow a particle down, never reverse it, so it sets no explicit limit;
- * counting it would let films just above eps (friction ~ H^(-4/3)) dictate
- * the time step. */
+ * h^2/(4 nu)); a bound whose divisor is zero is left out.  F is the whole
+ * force density of Eq. (4) at layer n without the pressure gradient:
+ * viscosity, Coriolis, wind and bottom friction F_fric = -(lambda/2) U|U|,
+ * lambda/2 = c_f / H^(4/3).  The printed sqrt(h F) is read as
+ * sgn(F) sqrt(h|F|). */
 static double cell_speed(const orc_sim* s, long c)
 {
     const orc_params* p = &s->p;
@@ -372,6 +371,9 @@ static double cell_speed(const orc_sim* s, long c)
     double ux = s->Ux[c], uy = s->Uy[c];
     double fx, fy;
     soft_forces(s, c, s->Ux, s->Uy, &fx, &fy);
+    double fr = s->lam0[c] * sqrt(ux * ux + uy * uy);
+    fx -= fr * ux;
+    fy -= fr * uy;
     double us = fmax(fabs(ux), fabs(uy)) + sqrt(p->g * s->H[c]);
     double upx = fabs(ux + sgn(fx) * sqrt(s->h * fabs(fx)));
     double upy = fabs(uy + sgn(fy) * sqrt(s->h * fabs(fy)));

@@ -1,0 +1,60 @@
+"""How much FP32 storage alone moves the oracle's trajectory.
+
+The oracle is run twice from the same inputs: plainly, and with its stored
+state rounded to FP32 after every step (the error an FP32 state carries, and
+nothing else).  What separates the two runs is a property of the scheme on
+that input, not of any implementation, and it decides which FP32 comparisons
+of the GPU path with the oracle can hold a 1e-4 bar with free time steps:
+
+* random wet/dry states: the CFL step (Sec. 2.3, stage I) counts bottom
+  friction in F, which grows as H^(-4/3) in films just above eps, so a film's
+  rounding moves the step by up to percents and the runs part by >> 1e-4;
+  their FP32 GPU comparisons therefore hold the oracle's steps;
+* the floodplain flood and the dam breaks: the runs agree to ~1e-6, so the
+  GPU is compared with free steps;
+* the fully wet control (a nearly still lake under weak wind): the step is
+  unaffected, but FP32 rounding of the level perturbs the weak forcing, so
+  the discharge itself is ill-conditioned in FP32 (its GPU bar is measured
+  against this perturbed oracle).
+"""
+import numpy as np
+
+from oracle import oracle as orc
+from paper_1705_00614_amd import scenarios as S
+from tests import parity as P
+
+
+def _pair(sc, steps, round_to=np.float32):
+    sc = P.with_precision(sc, 64)
+    a, b = orc.OracleSim(sc), orc.OracleSim(sc)
+    ta, tb = [], []
+    for _ in range(steps):
+        ta.append(a.next_tau())
+        a.step()
+        tb.append(b.next_tau())
+        b.step()
+        b.set_state(*(x.astype(round_to).astype(np.float64) for x in b.state()))
+    return P.errors(b.state(), a.state()), np.abs(np.array(tb) / np.array(ta) - 1.0).max()
+
+
+def test_rounding_harness_is_exact_without_rounding():
+    e, dt = _pair(S.random_state(40, 30, seed=5), 40, round_to=np.float64)
+    assert e == (0.0, 0.0, 0.0, 0.0) and dt == 0.0
+
+
+def test_random_state_time_step_is_set_by_films():
+    e, dt = _pair(S.random_state(70, 45, seed=5), 200)
+    assert dt > 1e-3           # rounding in films moves the CFL step
+    assert e[1] > 1e-4         # and the trajectories part beyond the FP32 bar
+
+
+def test_floodplain_is_well_conditioned():
+    e, dt = _pair(S.floodplain(n=128, seed=1), 200)
+    assert e[0] < 1e-6 and e[1] < 1e-5 and dt < 1e-4
+
+
+def test_wet_control_discharge_is_ill_conditioned_in_fp32():
+    e, dt = _pair(S.floodplain_wet(n=192, seed=0), 100)
+    assert dt < 1e-5           # the step is not the cause
+    assert e[0] < 1e-6         # the depth is well conditioned
+    assert e[1] > 1e-5         # the weak discharge is not

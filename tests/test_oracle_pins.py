@@ -429,11 +429,23 @@ def test_time_step_formula_on_hand_built_states():
     assert abs(sim.next_tau() - K * h / math.sqrt(g * 4.0)) < 1e-14
     sim = orc.OracleSim(_uniform(4, 4, h, 4.0, ux=3.0, uy=-1.0), periodic=True)
     assert abs(sim.next_tau() - K * h / (3.0 + math.sqrt(g * 4.0))) < 1e-14
-    # friction is point-implicit and does not limit the step, even on a film
-    nM = 0.2
-    sim = orc.OracleSim(_uniform(4, 4, h, 0.04, ux=-2.0, n_manning=np.full((4, 4), nM)),
+    # bottom friction is part of F (Eq. 4): F_fric = -(c_f / H^(4/3)) U |U|.
+    # Worked by hand: H = 1, c_f = g n_M^2 = 5, U = (-2, 0), h = 10:
+    # F = (20, 0), U_p = |-2 + sqrt(10 * 20)| = 10 sqrt2 - 2 > U_s = 2 + sqrt g,
+    # tau = K h / U_p = 4 / (10 sqrt2 - 2)
+    sim = orc.OracleSim(_uniform(4, 4, h, 1.0, ux=-2.0, n_manning=np.full((4, 4), math.sqrt(5.0 / g))),
                         periodic=True)
-    assert abs(sim.next_tau() - K * h / (2.0 + math.sqrt(g * 0.04))) < 1e-14
+    assert abs(sim.next_tau() - 4.0 / (10.0 * math.sqrt(2.0) - 2.0)) < 1e-14
+    # H = 1/8 (H^(4/3) = 1/16), c_f = 1/4, U = (0, 3), h = 4: F_y = -4 * 3 * 3 = -36,
+    # U_p = |3 - sqrt(4 * 36)| = 9 (the sign of F counts), U_s = 3 + sqrt(g/8),
+    # tau = 0.4 * 4 / 9
+    nm = np.full((4, 4), math.sqrt(0.25 / g))
+    sim = orc.OracleSim(_uniform(4, 4, 4.0, 0.125, uy=3.0, n_manning=nm), periodic=True)
+    assert abs(sim.next_tau() - 1.6 / 9.0) < 1e-14
+    # the same film moving along x with Coriolis f = 30: F = (-36, -90),
+    # U_p = max(|3 - 12|, |0 - sqrt(4 * 90)|) = sqrt(360), tau = 1.6 / sqrt(360)
+    sim = orc.OracleSim(_uniform(4, 4, 4.0, 0.125, ux=3.0, n_manning=nm, f_cor=30.0), periodic=True)
+    assert abs(sim.next_tau() - 1.6 / math.sqrt(360.0)) < 1e-14
     # wind force F = kappa (W-U)|W-U|/max(H, h_w) enters U_p = |U + sgn(F) sqrt(h|F|)|
     kap, W = 0.05, 30.0
     sim = orc.OracleSim(_uniform(4, 4, h, 0.5, ux=0.5, wind_x=W, wind_kappa=kap), periodic=True)
