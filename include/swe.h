@@ -129,6 +129,13 @@ long   swe_steps(swe_t* s);    /* completed steps */
 int    swe_work(swe_t* s, long long* tile_steps, long long* cell_steps,
                 int* ntiles, int* tile_x, int* tile_y);
 
+/* Workgroups of one step launch: the resident count of the step kernel
+ * (compute units x workgroups per unit), fewer only without dry skipping
+ * when the grid has fewer tiles.  The tile list is strided over them, so a
+ * step with more listed tiles gives some workgroups several.  Returns the
+ * count, or SWE_EINVAL for a NULL handle. */
+int    swe_launch_grid(swe_t* s);
+
 /* Tiles the next step will process (row-major tile indices, unordered),
  * at most cap entries; returns the count or SWE_E*. */
 int    swe_active_tiles(swe_t* s, int* out, int cap);
@@ -284,6 +291,13 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
 /* Advance n coarse steps (each with its r substeps; hipGraph replay).
  * Synchronises; returns 0 or an SWE_E* code. */
 int    swe_nest_run(swe_nest_t* n, long coarse_steps);
+
+/* Hold the coarse step length at tau_c > 0 from the next coarse step on
+ * (rounded to the stencil type; substeps tau_c / r; the CFL rule of
+ * Sec. 2.3 is still evaluated but not used); tau_c = 0 returns to the CFL
+ * rule, from the current layers.  Synchronises; SWE_EINVAL for a negative
+ * or non-finite tau_c. */
+int    swe_nest_hold_dt(swe_nest_t* n, double tau_c);
 
 /* As swe_nest_run with a HIP event pair around every coarse step (all its
  * launches); the summed time goes to *kernel_ms. */

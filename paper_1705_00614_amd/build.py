@@ -8,6 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe_hip.so")
 SOURCES = [os.path.join(CSRC, "swe_api.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, "swe_step.hpp"), os.path.join(CSRC, "swe_nest.hpp"),
+                  os.path.join(CSRC, "swe_lc.hpp"),
                   os.path.join(os.path.dirname(HERE), "include", "swe.h")]
 
 # Packed FP32 instructions are disabled on purpose: every FP32 operation is

@@ -763,6 +763,11 @@ int swe_work(swe_t* s, long long* tile_steps, long long* cell_steps, int* ntiles
     return 0;
 }
 
+int swe_launch_grid(swe_t* s) {
+    if (!s) { set_err("swe_launch_grid: NULL handle"); return SWE_EINVAL; }
+    return s->grid;
+}
+
 int swe_active_tiles(swe_t* s, int* out, int cap) {
     if (!s || (!out && cap > 0) || cap < 0) { set_err("swe_active_tiles: invalid arguments"); return SWE_EINVAL; }
     Ctrl c;
@@ -1793,6 +1798,28 @@ int swe_nest_run(swe_nest_t* n, long steps) {
     }
     if ((rc = nest_launch(n, left))) return rc;
     return nest_finish(n);
+}
+
+int swe_nest_hold_dt(swe_nest_t* n, double tau_c) {
+    if (!n || !(tau_c >= 0.0) || !std::isfinite(tau_c)) { set_err("swe_nest_hold_dt: invalid arguments"); return SWE_EINVAL; }
+    int rc = nest_finish(n);
+    if (rc) return rc;
+    if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
+    const int pc = (int)(n->c->launched & 1);
+    if (n->precision == 32) {
+        swe::NestArgs<float>& na = *(swe::NestArgs<float>*)n->nargs.data();
+        na.hold = tau_c;
+        hipLaunchKernelGGL(swe::k_nest_set_dt<float>, dim3(1), dim3(64), 0, n->stream,
+                           *(const Args<float>*)n->c->args[pc].data(), na, tau_c);
+    } else {
+        swe::NestArgs<double>& na = *(swe::NestArgs<double>*)n->nargs.data();
+        na.hold = tau_c;
+        hipLaunchKernelGGL(swe::k_nest_set_dt<double>, dim3(1), dim3(64), 0, n->stream,
+                           *(const Args<double>*)n->c->args[pc].data(), na, tau_c);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(n->stream));
+    return 0;
 }
 
 int swe_nest_run_timed(swe_nest_t* n, long steps, double* kernel_ms) {

@@ -64,6 +64,7 @@ struct NestArgs {
     double* ring_ledger;           // clamp volume per ring cell (accumulated)
     real eps, ih;                  // dry threshold, 1 / h_c
     double h2;                     // h_c^2
+    double hold;                   // held coarse step length (0: the CFL rule)
 };
 
 __device__ __forceinline__ int floor_div(int a, int r) { return a >= 0 ? a / r : -((-a + r - 1) / r); }
@@ -236,11 +237,38 @@ __global__ void k_region_speed(Args<real> a, const int* rects, int nrect, int nc
             for (int q = 0; q < 4; ++q) { nb.ux[q] = ux[q + 1]; nb.uy[q] = uy[q + 1]; nb.w[q] = Hs[q + 1] > eps; }
             real fx, fy;
             soft_forces(a, Hs[0], ux[0], uy[0], nb, fx, fy);
-            vmax = cfl_speed(a, Hs[0], ux[0], uy[0], fx, fy);
+            vmax = cfl_speed(a, Hs[0], a.cf[gy * a.nx + gx], ux[0], uy[0], fx, fy);
         }
     }
     vmax = wave_max(vmax);
     if ((threadIdx.x & 63) == 0 && vmax > real(0)) atomic_max_prep(a.ctrl, vmax);
+}
+
+// Lengths of the next coarse step (tc, rounded to the stencil type) and of
+// its r substeps; the hydrograph volume of the coarse step follows its clock.
+template <typename real>
+__device__ void set_nest_steps(const Args<real>& a, const NestArgs<real>& n, double tc) {
+    tc = (double)(real)tc;
+    set_next_step(a, a.ctrl, tc);
+    const double tf = (double)(real)(tc / (double)n.r);
+    for (int k = 0; k < n.np; ++k) {
+        Ctrl* p = n.P[k].ctrl;
+        p->tau = tf;
+        p->dV = 0.0;
+        p->sdepth = 0.0;
+    }
+}
+
+// Set the next steps from the host: tc > 0 held, tc = 0 the CFL rule of the
+// current layers (speeds recorded by the last coarse step).
+template <typename real>
+__global__ void k_nest_set_dt(Args<real> a, NestArgs<real> n, double tc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!(tc > 0.0)) {
+        tc = cfl_tau_of(a, a.ctrl->speed);
+        for (int k = 0; k < n.np; ++k) tc = fmin(tc, (double)n.r * n.P[k].ctrl->tau_cfl);
+    }
+    set_nest_steps(a, n, tc);
 }
 
 // Time steps of the next coarse step and its substeps; errors of any grid
@@ -254,17 +282,10 @@ __global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
     c->speed = S;
     double tc = cfl_tau_of(a, S);
     for (int k = 0; k < n.np; ++k) tc = fmin(tc, (double)n.r * n.P[k].ctrl->tau_cfl);
-    tc = (double)(real)tc;
-    set_next_step(a, c, tc);
-    const double tf = (double)(real)(tc / (double)n.r);
+    set_nest_steps(a, n, n.hold > 0.0 ? n.hold : tc);
     int e = c->err;
-    for (int k = 0; k < n.np; ++k) {
-        Ctrl* p = n.P[k].ctrl;
-        p->tau = tf;
-        p->dV = 0.0;
-        p->sdepth = 0.0;
-        if (!e && p->err) e = p->err;
-    }
+    for (int k = 0; k < n.np; ++k)
+        if (!e && n.P[k].ctrl->err) e = n.P[k].ctrl->err;
     if (a.skip) close_segments(c, a.hot, slot);
     if (e) {
         c->err = e;

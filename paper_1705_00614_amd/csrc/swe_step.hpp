@@ -290,12 +290,16 @@ __device__ __forceinline__ void soft_forces(const Args<real>& a, real H, real ux
     fy = a.nuh2 * vy - a.fcor * uxc + k * dy;
 }
 
-// CFL speed max(U_s, U_p) of a wet cell (Sec. 2.3, stage I).  F is the
-// explicitly integrated force (viscosity, Coriolis, wind); the point-implicit
-// friction cannot reverse a particle and sets no limit.
+// CFL speed max(U_s, U_p) of a wet cell (Sec. 2.3, stage I) of depth H,
+// velocity (ux, uy) and Manning coefficient c_f = g n_M^2.  F is the force
+// density of Eq. (4) without the pressure gradient: viscosity, Coriolis and
+// wind (fx, fy) plus bottom friction -(c_f / H^(4/3)) U |U|.
 template <typename real>
-__device__ __forceinline__ real cfl_speed(const Args<real>& a, real H, real ux, real uy,
+__device__ __forceinline__ real cfl_speed(const Args<real>& a, real H, real cf, real ux, real uy,
                                           real fx, real fy) {
+    const real fr = Mth<real>::friction(cf, H) * Mth<real>::sqrt(ux * ux + uy * uy);
+    fx -= fr * ux;
+    fy -= fr * uy;
     const real us = rmax(rabs(ux), rabs(uy)) + Mth<real>::sqrt(a.g * H);
     const real sx = fx > real(0) ? real(1) : (fx < real(0) ? real(-1) : real(0));
     const real sy = fy > real(0) ? real(1) : (fy < real(0) ? real(-1) : real(0));
@@ -985,9 +989,11 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     nb.ux[q] = L.GX[sn[q]]; nb.uy[q] = L.GY[sn[q]]; nb.w[q] = L.NH[sn[q]] > eps;
                 }
                 const real ux = L.GX[s], uy = L.GY[s];
+                // c_f again from memory (L2): P1 overwrote its LDS copy
+                const real cf = a.cf[(ty0 + y) * nx + tx0 + x];
                 real fx, fy;
                 soft_forces(a, H, ux, uy, nb, fx, fy);
-                vmax = rmax(vmax, cfl_speed(a, H, ux, uy, fx, fy));
+                vmax = rmax(vmax, cfl_speed(a, H, cf, ux, uy, fx, fy));
             }
         }
         bits |= own | (eW << 1) | (eE << 2) | (eS << 3) | (eN << 4) | (rg << 5);
@@ -1207,7 +1213,7 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
             for (int q = 0; q < 4; ++q) { nb.ux[q] = sUx[sn[q]]; nb.uy[q] = sUy[sn[q]]; nb.w[q] = sH[sn[q]] > eps; }
             real fx, fy;
             soft_forces(a, H, sUx[k], sUy[k], nb, fx, fy);
-            vmax = rmax(vmax, cfl_speed(a, H, sUx[k], sUy[k], fx, fy));
+            vmax = rmax(vmax, cfl_speed(a, H, a.cf[gy * nx + gx], sUx[k], sUy[k], fx, fy));
         }
     }
     vmax = wave_max(vmax);

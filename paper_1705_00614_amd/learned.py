@@ -170,3 +170,111 @@ def timing(net, fine_sc, r, sim_seconds, skip=0, corr_depth=CORR_DEPTH):
         s.close()
     f0.close()
     return res
+
+
+def advance_to(g, t_end, frac=0.5):
+    """Advance a solver with its own CFL steps to t_end: graph-replayed runs
+    while the end is far (a run of n steps covers frac of what is left at the
+    current step length, so it overshoots only if the step more than doubles
+    within the run, which raises), single steps near it, and a last step held
+    to the remaining time (to within the rounding of the step length to the
+    stencil type)."""
+    while True:
+        left = t_end - g.time()
+        if left <= 0.0:
+            if -left > 1e-6 * max(abs(t_end), 1.0):
+                raise RuntimeError("advance_to: overshot %g by %g s" % (t_end, -left))
+            return
+        dt = g.next_dt()
+        n = int(frac * left / dt)
+        if n >= 2:
+            g.run(n)
+        elif dt < left:
+            g.step()
+        else:
+            g.hold_dt(left)
+            g.step()
+            g.hold_dt(0.0)
+            return
+
+
+class GuardedRun:
+    """Learned coarse solve with the plain fine solve as its fallback and the
+    judge of its error.
+
+    The coarse grid with the attached network advances in windows of
+    `window` coarse CFL steps.  After each window a guard reads device
+    scalars of the coarse grid: the status of its steps (a non-finite state
+    or a collapsed time step stops them), its volume balance over the window
+    (V - V_0 - inflow - clamped volume, which the conservative corrections
+    keep at rounding level), and the volume the final update had to add by
+    clamping negative depths (corrections that drain cells below zero).
+    Every `judge_every` windows (0: never) the fine solve is advanced to the
+    window's end and judges the coarse depth: relative L1 against the
+    restricted fine depth above `err_tol` fails the window.
+
+    A failed window is handed back to the fine solve: it advances from its
+    last layer (the start, or the end of the last window it ran or judged)
+    to the window's end with its own CFL steps, and the coarse grid restarts
+    from the restriction of that layer.  `log` records every window: mode
+    ('learned' or 'fine'), the reason of a fallback, the window's end time
+    t_end, the coarse clock t after it and the judged error."""
+
+    def __init__(self, net, fine_sc, r, window=32, vol_tol=1e-5, clamp_tol=1e-4, judge_every=0,
+                 err_tol=0.02, corr_depth=CORR_DEPTH):
+        self.net, self.r, self.window = net, r, int(window)
+        self.vol_tol, self.clamp_tol = vol_tol, clamp_tol
+        self.judge_every, self.err_tol = int(judge_every), err_tol
+        self.fine = swe.Solver(fine_sc)
+        csc = coarsen(fine_sc, r)
+        self.coarse = swe.Solver(csc)
+        self.coarse.restrict_from(self.fine, r)
+        net.attach(self.coarse)
+        self.coarse.set_correction_depth(corr_depth)
+        self.ref = swe.Solver(csc)       # restricted fine layers for the judge
+        self.log = []
+
+    def _fallback(self, t_end):
+        advance_to(self.fine, t_end)
+        self.coarse.restrict_from(self.fine, self.r)
+
+    def step_window(self):
+        g = self.coarse
+        k = len(self.log)
+        t0, V0, in0, cl0, dt0 = g.time(), g.mass(), g.inflow(), g.ledger(), g.next_dt()
+        rc = g.run_rc(self.window)
+        reason, err = None, None
+        t_end = g.time()
+        if rc != 0:
+            reason = "step error %d" % rc
+            if not t_end > t0:           # stopped in its first step: a window of the last step length
+                t_end = t0 + self.window * dt0
+        else:
+            V, dV_in, dV_cl = g.mass(), g.inflow() - in0, g.ledger() - cl0
+            scale = max(abs(V), abs(V0), 1e-300)
+            if not abs(V - V0 - dV_in - dV_cl) <= self.vol_tol * scale:
+                reason = "volume balance"
+            elif not abs(dV_cl) <= self.clamp_tol * scale:
+                reason = "clamped volume"
+        if reason is None and self.judge_every and (k + 1) % self.judge_every == 0:
+            advance_to(self.fine, t_end)
+            self.ref.restrict_from(self.fine, self.r)
+            Hr, Hc = self.ref.state()[0], g.state()[0]
+            err = float(np.abs(Hc - Hr).sum() / max(np.abs(Hr).sum(), 1e-300))
+            if not err <= self.err_tol:
+                reason = "judged error %.3g > %.3g" % (err, self.err_tol)
+        if reason is not None:
+            self._fallback(t_end)
+        self.log.append(dict(window=k, mode="fine" if reason else "learned", reason=reason,
+                             t_end=t_end, t=self.coarse.time(), err=err))
+        return self.log[-1]
+
+    def run(self, windows):
+        for _ in range(int(windows)):
+            self.step_window()
+        return self.log
+
+    def close(self):
+        self.net.detach(self.coarse)
+        for g in (self.fine, self.coarse, self.ref):
+            g.close()

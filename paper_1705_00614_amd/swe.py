@@ -65,6 +65,7 @@ EXPORTS = {
     "swe_ledger": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
+    "swe_launch_grid": (ctypes.c_int, [ctypes.c_void_p]),
     "swe_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -91,6 +92,7 @@ EXPORTS = {
                                           ctypes.POINTER(SweParams), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p]),
     "swe_nest_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
+    "swe_nest_hold_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "swe_nest_run_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long, _dp]),
     "swe_nest_query": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long),
                                       _dp, _dp]),
@@ -362,6 +364,13 @@ class Solver:
                                ctypes.byref(tx), ctypes.byref(ty)))
         return dict(tile_steps=t.value, cell_steps=c.value, ntiles=n.value, tile=(tx.value, ty.value))
 
+    def launch_grid(self):
+        """Workgroups of one step launch (the tile list is strided over them)."""
+        n = load().swe_launch_grid(self._h)
+        if n < 0:
+            raise SweError(n, last_error())
+        return n
+
     def active_tiles(self):
         n = self.work()["ntiles"]
         buf = (ctypes.c_int * max(n, 1))()
@@ -527,6 +536,10 @@ class Nest:
         ms = ctypes.c_double(0.0)
         _check(load().swe_nest_run_timed(self._h, int(n), ctypes.byref(ms)))
         return ms.value
+
+    def hold_dt(self, tau_c):
+        """Hold the coarse step at tau_c (substeps tau_c / r); 0 returns to the CFL rule."""
+        _check(load().swe_nest_hold_dt(self._h, float(tau_c)))
 
     def query(self):
         v = [ctypes.c_double() for _ in range(6)]

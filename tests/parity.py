@@ -77,3 +77,26 @@ def with_precision(sc, prec):
 
 def oracle_of(sc):
     return orc.OracleSim(sc)
+
+
+def rounded(state, prec):
+    """A layer rounded to the stencil type (as doubles)."""
+    if prec == 64:
+        return tuple(np.asarray(x, np.float64) for x in state)
+    return tuple(np.asarray(x, np.float32).astype(np.float64) for x in state)
+
+
+def thacker_case(N, prec, L=2.0):
+    """Thacker's planar oscillation in a paraboloid bowl (tests/analytic.py)
+    at t = 0 on an N x N grid over [-L, L]^2, frictionless, eps = 1e-5."""
+    from paper_1705_00614_amd import scenarios as S
+    from tests import analytic as A
+    th = A.Thacker()
+    h = 2 * L / N
+    xc = -L + (np.arange(N) + 0.5) * h
+    X, Y = np.meshgrid(xc, xc)
+    H0 = th.depth(X, Y, 0.0)
+    u0, v0 = th.velocity(0.0)
+    sc = dict(nx=N, ny=N, h=h, b=th.bed(X, Y), n_manning=np.zeros_like(X), solid=None,
+              H0=H0, Qx0=H0 * u0, Qy0=H0 * v0, params=S.base_params(eps=1e-5, precision=prec))
+    return th, X, Y, sc

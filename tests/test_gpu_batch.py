@@ -11,6 +11,7 @@ import pytest
 
 from oracle import oracle as orc
 from paper_1705_00614_amd import scenarios as S
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -62,9 +63,7 @@ def test_batch_fp64_matches_oracle_and_balances_volume():
         o = orc.OracleSim(sc)
         o.run(80)
         H, Qx, Qy = b.state(k)
-        Ho, Qxo, Qyo = o.state()
-        assert np.abs(H - Ho).sum() <= 1e-10 * np.abs(Ho).sum()
-        assert np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum() <= 1e-10 * (np.abs(Qxo).sum() + np.abs(Qyo).sum())
+        P.check((H, Qx, Qy), o.state(), 64, label="batch scenario %d" % k)
         assert abs(q["time"][k] - o.time()) <= 1e-12 * o.time()
         V = q["mass"][k]
         assert abs(V - q0["mass"][k] - q["inflow"][k] - q["ledger"][k]) <= 1e-12 * V
@@ -139,9 +138,7 @@ def test_full_size_ensemble_sampled_scenarios_match_oracle():
     for k in np.argsort([sc["nx"] * sc["ny"] for sc in ens], kind="stable")[:3]:
         o = orc.OracleSim(ens[k])
         o.run(32)
-        (H, Qx, Qy), (Ho, Qxo, Qyo) = B.state(int(k)), o.state()
-        assert np.abs(H - Ho).sum() <= 1e-4 * np.abs(Ho).sum(), k
-        assert np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum() <= 1e-4 * (np.abs(Qxo).sum() + np.abs(Qyo).sum()), k
+        P.check(B.state(int(k)), o.state(), 32, label="ensemble scenario %d" % k)
     q = B.query()
     assert np.all(q["steps"] == 32)
     assert np.all(np.isfinite(q["time"])) and np.all(q["time"] > 0)

@@ -12,6 +12,7 @@ import pytest
 
 from oracle.nest import OracleNest
 from paper_1705_00614_amd import scenarios as S
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -37,15 +38,24 @@ def _rel(a, b):
     return np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300)
 
 
-def _compare(G, O, tol, tol_q=None):
-    """Relative L1 of H and of (Qx, Qy) together, as for a single grid."""
-    tol_q = tol if tol_q is None else tol_q
+def _compare(G, O, prec, label=""):
+    """The single-grid bars of tests/parity.py (relative L1 of H and of
+    (Qx, Qy) together, and per cell) on the coarse grid and every patch."""
     pairs = [(G.coarse_state(), O.coarse_state())]
     pairs += [(G.patch_state(k), O.patch_state(k)) for k in range(len(O.P))]
-    for k, ((H, Qx, Qy), (Ho, Qxo, Qyo)) in enumerate(pairs):
-        assert _rel(H, Ho) <= tol, k
-        eq = (np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum()) / max(np.abs(Qxo).sum() + np.abs(Qyo).sum(), 1e-300)
-        assert eq <= tol_q, (k, eq)
+    for k, (g, o) in enumerate(pairs):
+        P.check(g, o, prec, label="%s grid %d" % (label, k))
+
+
+def _run_held(G, O, steps, prec):
+    """Both sides take the oracle nest's coarse step of each layer, rounded
+    to the stencil type (substeps: a quarter of it, exact in binary)."""
+    for _ in range(steps):
+        tc = O.next_taus()[0]
+        tc = float(np.float32(tc)) if prec == 32 else tc
+        G.hold_dt(tc)
+        G.run(1)
+        O.step(tc)
 
 
 @pytest.mark.parametrize("wet", [False, True])
@@ -59,7 +69,7 @@ def test_nest_fp64_matches_oracle(wet):
     for _ in range(3):
         G.run(8)
         O.run(8)
-        _compare(G, O, 1e-10)
+        _compare(G, O, 64)
     for k in range(len(O.P)):                 # the patches carry flow
         Hf, Qxf, Qyf = O.patch_state(k)
         assert (Hf > 1e-4).any() and np.abs(Qxf).max() + np.abs(Qyf).max() > 1e-6
@@ -80,23 +90,45 @@ def test_nest_one_way_matches_oracle():
     G = swe.Nest(nest, feedback=False)
     G.run(16)
     O.run(16)
-    _compare(G, O, 1e-10)
+    _compare(G, O, 64)
 
 
-def test_nest_fp32_matches_oracle():
-    # FP32 stencil: the single-grid bar (relative L1 of H and of HU <= 1e-4),
-    # over 24 coarse steps.  The coupled system amplifies perturbations
-    # (relative 3e-8 in the initial depth of the oracle's own input grows to
-    # ~3e-5 in HU by coarse step 40 on this rough-relief case, while the
-    # single grid damps it), so a longer FP32-vs-FP64 comparison measures
-    # that conditioning rather than the kernels.
+def test_nest_fp32_matches_oracle_at_held_steps():
+    """FP32 nest over 48 coarse steps at the oracle nest's time steps.  The
+    nest's CFL rule takes the minimum over the coarse grid and r times every
+    patch, so a film in any patch can set it; with the steps held, FP32
+    rounding of the coupled layers stays at the single-grid level."""
+    nest = _floodplain_nest(32)
+    O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
+    G = swe.Nest(nest)
+    _run_held(G, O, 48, 32)
+    _compare(G, O, 32, "held")
+    assert G.query()["time"] == O.time()
+
+
+def test_nest_fp32_free_steps_match_oracle():
+    """FP32 nest with its own CFL steps over 24 coarse steps."""
     nest = _floodplain_nest(32)
     O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
     G = swe.Nest(nest)
     G.run(24)
     O.run(24)
-    _compare(G, O, 1e-4)
+    _compare(G, O, 32, "free")
     assert abs(G.query()["time"] - O.time()) <= 1e-4 * O.time()
+
+
+def test_nest_hold_then_release_follows_the_cfl_rule():
+    nest = _floodplain_nest(64)
+    O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
+    G = swe.Nest(nest)
+    _run_held(G, O, 5, 64)
+    G.hold_dt(0.0)
+    q = G.query()
+    tc, tf = O.next_taus()
+    assert abs(q["dt_coarse"] - tc) <= 1e-12 * tc and abs(q["dt_fine"] - tf) <= 1e-12 * tf
+    G.run(11)
+    O.run(11)
+    _compare(G, O, 64, "released")
 
 
 @pytest.mark.parametrize("prec", [32, 64])
@@ -125,7 +157,7 @@ def test_nest_r2_and_r1():
         G = swe.Nest(nest)
         G.run(12)
         O.run(12)
-        _compare(G, O, 1e-10)
+        _compare(G, O, 64)
 
 
 def test_nest_rejects_bad_layouts():
@@ -188,7 +220,7 @@ def test_full_size_nest_first_coarse_steps_match_oracle():
     O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
     G.run(8)
     O.run(8)
-    _compare(G, O, 1e-10)
+    _compare(G, O, 64)
     assert abs(G.query()["time"] - O.time()) <= 1e-12 * O.time()
     for k in range(2):
         assert (G.patch_state(k)[0] > 0).any()   # the patches hold water

@@ -14,6 +14,8 @@ import pytest
 
 from oracle import oracle as orc
 from paper_1705_00614_amd import scenarios as S
+from tests import analytic as A
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -28,26 +30,30 @@ def _announce(request):
 
 
 def rel_l1(a, b):
-    den = np.abs(b).sum()
-    return np.abs(a - b).sum() / (den if den > 0 else 1.0)
+    return P.rel_l1(a, b)
 
 
-def compare(sc, steps, prec, tol_H, tol_Q, tile=(0, 0), skip=True):
-    sc = dict(sc)
-    sc["params"] = dict(sc["params"], precision=prec)
+def compare(sc, steps, prec, tile=(0, 0), skip=True, held=False, l1=None, cell=None, label=""):
+    """Run the GPU path and the oracle `steps` steps from the same inputs and
+    assert the relative L1 and per-cell bars of tests/parity.py.  Free steps
+    (held=False): each side takes the CFL step of its own layer, so the
+    clocks must agree too.  Held steps: both take the oracle's CFL step of
+    each layer (rounded to the stencil type); the GPU's own choice of the step
+    is tested separately (test_time_step_selection_matches_oracle)."""
+    sc = P.with_precision(sc, prec)
     o = orc.OracleSim(sc)
     g = swe.Solver(sc, skip_dry=skip, tile=tile)
     m0 = g.mass()
-    o.run(steps)
-    g.run(steps)
-    H, Qx, Qy = g.state()
-    Ho, Qxo, Qyo = o.state()
-    eH = rel_l1(H, Ho)
-    eQ = (np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum()) / max(np.abs(Qxo).sum() + np.abs(Qyo).sum(), 1e-300)
+    if held:
+        P.run_held(o, g, steps, prec)
+        assert g.time() == o.time()
+    else:
+        o.run(steps)
+        g.run(steps)
+        tt = 1e-10 if prec == 64 else 1e-4
+        assert abs(g.time() - o.time()) <= tt * o.time() + 1e-12, (g.time(), o.time())
     assert g.steps() == steps
-    assert abs(g.time() - o.time()) <= max(tol_H, 1e-12) * o.time() + 1e-12
-    assert eH <= tol_H, eH
-    assert eQ <= tol_Q, eQ
+    P.check(g.state(), o.state(), prec, l1, cell, label)
     V = g.mass()
     drift = abs(V - m0 - g.inflow() - g.ledger()) / max(V, 1e-300)
     return g, o, drift
@@ -56,46 +62,112 @@ def compare(sc, steps, prec, tol_H, tol_Q, tile=(0, 0), skip=True):
 # ------------------------------------------------------------------ C1 and friends
 
 def test_dam_break_fp64_matches_oracle():
-    g, o, drift = compare(S.dam_break(precision=64), 200, 64, 1e-10, 1e-10)
+    g, o, drift = compare(S.dam_break(precision=64), 200, 64, label="dam64")
     assert drift < 1e-13
     # Stoker middle depth reached
     assert abs(g.state()[0][128, 150] - 1.1035) < 2e-3
 
 
 def test_dam_break_fp32_matches_oracle():
-    g, o, drift = compare(S.dam_break(precision=32), 200, 32, 1e-4, 1e-4)
+    g, o, drift = compare(S.dam_break(precision=32), 200, 32, label="dam32")
     assert drift < 1e-6
 
 
 @pytest.mark.parametrize("n", [128, 256])
 def test_floodplain_fp32_200_steps(n):
-    g, o, drift = compare(S.floodplain(n=n, seed=1), 200, 32, 1e-4, 1e-4)
+    g, o, drift = compare(S.floodplain(n=n, seed=1), 200, 32, label="flood%d" % n)
     assert drift <= 1e-6
 
 
 def test_floodplain_fp64_200_steps():
-    g, o, drift = compare(S.floodplain(n=128, seed=2, precision=64), 200, 64, 1e-10, 1e-10)
+    g, o, drift = compare(S.floodplain(n=128, seed=2, precision=64), 200, 64, label="flood64")
     assert drift < 1e-12
 
 
 @pytest.mark.parametrize("lim", [0, 1, 2])
-@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
-def test_random_state_all_forces_all_limiters(lim, prec, tol):
+def test_random_state_all_forces_all_limiters_fp64(lim):
     sc = S.random_state(70, 45, seed=5 + lim, limiter=lim)
-    compare(sc, 60, prec, tol, tol)
+    compare(sc, 60, 64, label="rs64 lim%d" % lim)
+
+
+@pytest.mark.parametrize("lim", [0, 1, 2])
+def test_random_state_all_forces_all_limiters_fp32_held_steps(lim):
+    """Random wet/dry states are ill-conditioned in the CFL step (friction in
+    films just above eps sets it; tests/test_oracle_conditioning.py), so the
+    FP32 path runs at the oracle's steps; at held steps FP32 rounding moves
+    these states by ~1e-6 over 200 steps."""
+    sc = S.random_state(70, 45, seed=5 + lim, limiter=lim)
+    compare(sc, 200, 32, held=True, label="rs32 lim%d" % lim)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (2, 3), (5, 7), (33, 17), (77, 45)])
 def test_ragged_and_tiny_grids_fp64(shape):
     nx, ny = shape
     sc = S.random_state(nx, ny, seed=nx * 31 + ny)
-    compare(sc, 25, 64, 1e-10, 1e-10)
+    compare(sc, 25, 64, label="ragged %dx%d" % shape)
 
 
 @pytest.mark.parametrize("tile", [(32, 32), (64, 16), (16, 16)])
 def test_every_tile_shape_fp32_matches_oracle(tile):
     sc = S.random_state(90, 70, seed=9)
-    compare(sc, 40, 32, 1e-4, 1e-4, tile=tile)
+    compare(sc, 200, 32, tile=tile, held=True, label="tile %dx%d" % tile)
+
+
+def test_ritter_dry_dam_break_fp32_matches_oracle():
+    """Dam break onto a dry bed (Ritter): a wet/dry front moving at 2 sqrt(g h0)."""
+    g, o, drift = compare(S.dam_break(h_right=0.0, precision=32), 200, 32, label="ritter32")
+    assert drift < 1e-6
+    H = g.state()[0][128]
+    xi = ((np.arange(256) + 0.5) - 128.0) / g.time()
+    he = A.dam_break_depth(xi, 2.0, 0.0)
+    assert np.abs(H - he).sum() / he.sum() < 0.03
+
+
+def test_thacker_bowl_fp32_matches_oracle():
+    """Moving shoreline on a curved bed: one period of Thacker's oscillation."""
+    th, X, Y, sc = P.thacker_case(80, 32)
+    o = orc.OracleSim(sc)
+    steps = 0
+    while o.time() < th.period:
+        o.step()
+        steps += 1
+    g, o, drift = compare(sc, steps, 32, label="thacker32")
+    assert drift < 1e-6
+    He = th.depth(X, Y, g.time())
+    assert np.abs(g.state()[0] - He).sum() / He.sum() < 0.045
+
+
+TAU_CASES = {
+    "dam break": (lambda: S.dam_break(), 50),
+    "floodplain": (lambda: S.floodplain(n=160, seed=3), 150),
+    "random state": (lambda: S.random_state(70, 45, seed=5), 0),
+    "random state, run": (lambda: S.random_state(70, 45, seed=6), 30),
+    "thacker": (lambda: P.thacker_case(60, 64)[3], 40),
+    "wet control": (lambda: S.floodplain_wet(n=128, seed=0), 20),
+}
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("case", sorted(TAU_CASES))
+def test_time_step_selection_matches_oracle(case, prec):
+    """The CFL step of Sec. 2.3 stage I (U_s, U_p with F of Eq. 4, friction
+    included) chosen by the GPU for a layer equals the oracle's for the same
+    layer: the oracle's layer after k steps, rounded to the stencil type and
+    loaded into both.  FP64: the same arithmetic.  FP32: the speeds carry a
+    few FP32 roundings (the friction factor through the hardware log2/exp2
+    about 4e-7 relative) and the step is rounded to FP32 (6e-8); 1e-5
+    bounds both with margin."""
+    make, k = TAU_CASES[case]
+    sc = P.with_precision(make(), 64)
+    o = orc.OracleSim(sc)
+    o.run(k)
+    st = P.rounded(o.state(), prec)
+    o.set_state(*st)
+    g = swe.Solver(P.with_precision(sc, prec))
+    g.set_state(*st)
+    t_o, t_g = o.next_tau(), g.next_dt()
+    print("[tau] %s prec=%d oracle=%.9e gpu=%.9e rel=%.2e" % (case, prec, t_o, t_g, abs(t_g / t_o - 1)))
+    assert abs(t_g - t_o) <= (1e-13 if prec == 64 else 1e-5) * t_o
 
 
 def test_gates_fp64_match_oracle_and_stay_dry():
@@ -105,7 +177,7 @@ def test_gates_fp64_match_oracle_and_stay_dry():
     solid[10:14, 40] = 0          # an open gate in a closed wall
     solid[3, 20] = solid[17, 25] = 1
     sc["solid"] = solid
-    g, o, drift = compare(sc, 120, 64, 1e-10, 1e-10)
+    g, o, drift = compare(sc, 120, 64, label="gates")
     assert np.all(g.state()[0][solid == 1] == 0.0)
 
 
@@ -288,25 +360,80 @@ def test_dt_collapse_is_reported():
     assert g.steps() == 0
 
 
+# ------------------------------------------------------------------ many tiles per workgroup
+
+@pytest.mark.timeout(900)
+def test_floodplain_every_tile_listed_fp32():
+    """Without dry skipping every tile is listed, more tiles than the launch
+    has workgroups, so workgroups take several tiles in turn."""
+    g, o, drift = compare(S.floodplain(n=1024, seed=2), 200, 32, skip=False, label="flood1024 all tiles")
+    w = g.work()
+    assert w["ntiles"] > g.launch_grid()
+    assert w["tile_steps"] == 200 * w["ntiles"]
+    assert drift <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_wet_control_many_tiles_fp64():
+    """The fully wet control (about 60 % wet) at 1024^2: more listed tiles
+    per step than workgroups, every cell against the oracle at the FP64 bars."""
+    g, o, drift = compare(S.floodplain_wet(n=1024, seed=0, precision=64), 200, 64, label="wet1024 fp64")
+    assert g.work()["tile_steps"] > 200 * g.launch_grid()
+    assert drift < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_wet_control_many_tiles_fp32():
+    """The same in FP32.  The control is a nearly still lake under a weak
+    wind, and its discharge is ill-conditioned in FP32: rounding the level
+    (about 5e-7 m at 10 m depth) starts gravity waves of sqrt(g/H) * 5e-7 m/s,
+    not small against the wind-driven velocities of ~1e-3 m/s.  The spread is
+    measured here: the oracle run once plainly and once with its layer
+    rounded to FP32 after every step.  The GPU's FP32 stages round about five
+    more intermediates per step on the most sensitive chain (level, gradient,
+    half-step and Lagrangian velocities, fluxes); independent roundings add
+    in quadrature, sqrt(6) ~ 2.5 times the spread, and the bar is twice that.
+    Depth is well conditioned and keeps the 1e-4 bar."""
+    sc = P.with_precision(S.floodplain_wet(n=1024, seed=0), 32)
+    o, r = orc.OracleSim(sc), orc.OracleSim(sc)
+    g = swe.Solver(sc)
+    m0 = g.mass()
+    for _ in range(200):
+        o.step()
+        r.step()
+        r.set_state(*P.rounded(r.state(), 32))
+    g.run(200)
+    assert g.work()["tile_steps"] > 200 * g.launch_grid()
+    spread = P.errors(r.state(), o.state())
+    print("[wet32] FP32-rounding spread of the oracle: eH=%.3e eQ=%.3e cellH=%.3e cellQ=%.3e" % spread)
+    e = P.errors(g.state(), o.state())
+    print("[wet32] GPU vs oracle: eH=%.3e eQ=%.3e cellH=%.3e cellQ=%.3e" % e)
+    assert e[0] <= 1e-4 and e[2] <= 2e-4
+    assert e[1] <= max(1e-4, 5.0 * spread[1]) and e[3] <= max(2e-4, 5.0 * spread[3])
+    V = g.mass()
+    assert abs(V - m0 - g.inflow() - g.ledger()) <= 1e-6 * V
+
+
 # ------------------------------------------------------------------ full size
 
-def test_full_size_floodplain_first_steps_match_oracle():
+@pytest.mark.timeout(1200)
+def test_full_size_floodplain_200_steps_match_oracle():
     """The 4096^2 floodplain in the launch configuration the benchmark times
-    (FP32, skipping on, default tile): first steps against the oracle on the
-    whole grid, then a long run against the volume balance."""
+    (FP32, skipping on, default tile): 200 steps against the oracle on the
+    whole grid at the FP32 bars, then a long run against the volume balance."""
     sc = S.floodplain(n=4096, seed=0)
     g = swe.Solver(sc)
     o = orc.OracleSim(sc)
     m0 = g.mass()
     assert abs(m0 - o.mass()) <= 1e-6 * o.mass()
-    o.run(3)
-    g.run(3)
-    H, Qx, Qy = g.state()
-    Ho, Qxo, Qyo = o.state()
-    assert rel_l1(H, Ho) <= 1e-4
-    assert (np.abs(Qx - Qxo).sum() + np.abs(Qy - Qyo).sum()) / (np.abs(Qxo).sum() + np.abs(Qyo).sum()) <= 1e-4
+    o.run(200)
+    g.run(200)
+    assert abs(g.time() - o.time()) <= 1e-4 * o.time()
+    P.check(g.state(), o.state(), 32, label="flood4096 200 steps")
+    V = g.mass()
+    assert abs(V - m0 - g.inflow() - g.ledger()) <= 1e-6 * V
     del o
-    g.run(997)
+    g.run(800)
     V = g.mass()
     assert abs(V - m0 - g.inflow() - g.ledger()) <= 1e-6 * V
     assert g.work()["tile_steps"] < 0.2 * 1000 * g.work()["ntiles"]
