@@ -129,6 +129,19 @@ long   swe_steps(swe_t* s);    /* completed steps */
 int    swe_work(swe_t* s, long long* tile_steps, long long* cell_steps,
                 int* ntiles, int* tile_x, int* tile_y);
 
+/* Source rate field sigma(x, y) [m/s] of the continuity equation (Sec. 2.1,
+ * Eq. 1: precipitation > 0; infiltration and evaporation < 0), nx*ny host
+ * FP64, row-major, copied; zero on closed gates; NULL removes it.  Each step
+ * of length tau adds tau*sigma of depth with no momentum (stage I sources);
+ * a loss acts only on cells wet at layer n and takes at most the water
+ * there.  Cells with sigma > 0 are sources of the wet-tile rule (their tiles
+ * and the tiles facing them are stepped).  The volume the field applied is
+ * accumulated in FP64 per tile: swe_field_volume returns it [m^3], so that
+ * V_N - V_0 = swe_inflow + swe_field_volume + swe_ledger.  Not for grids of
+ * a nest.  Re-lists the active tiles of the current layer; 0 or SWE_E*. */
+int    swe_set_source_field(swe_t* s, const double* sigma);
+double swe_field_volume(swe_t* s);
+
 /* Workgroups of one step launch: the resident count of the step kernel
  * (compute units x workgroups per unit), fewer only without dry skipping
  * when the grid has fewer tiles.  The tile list is strided over them, so a

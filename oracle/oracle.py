@@ -67,7 +67,7 @@ def lib():
         L.orc_step_tau.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_long]
         for name in ("orc_next_tau", "orc_mass", "orc_time", "orc_last_tau",
-                     "orc_ledger", "orc_inflow"):
+                     "orc_ledger", "orc_inflow", "orc_field_volume"):
             getattr(L, name).restype = ctypes.c_double
             getattr(L, name).argtypes = [ctypes.c_void_p]
         L.orc_steps.restype = ctypes.c_long
@@ -80,6 +80,7 @@ def lib():
         L.orc_cell_speeds.argtypes = [ctypes.c_void_p, _c_double_p]
         L.orc_set_correction.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p]
         L.orc_set_correction_depth.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_set_source_field.argtypes = [ctypes.c_void_p, _c_double_p]
         L.orc_tau_from_speed.restype = ctypes.c_double
         L.orc_tau_from_speed.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_hydrograph_volume.restype = ctypes.c_double
@@ -125,6 +126,7 @@ class OracleSim:
 
     def __init__(self, sc, periodic=False):
         L = lib()
+        sigma = sc.get("sigma")
         self.nx, self.ny, self.h = int(sc["nx"]), int(sc["ny"]), float(sc["h"])
         shp = (self.ny, self.nx)
         self._keep = [_f64(sc.get(k), shp) for k in ("b", "n_manning", "H0", "Qx0", "Qy0")]
@@ -137,6 +139,8 @@ class OracleSim:
                                _dp(H0), _dp(Qx0), _dp(Qy0), ctypes.byref(self._prm))
         if not self._h:
             raise ValueError("orc_create rejected the scenario")
+        if sigma is not None:
+            self.set_source_field(sigma)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -180,6 +184,19 @@ class OracleSim:
     def set_correction_depth(self, hmin):
         if lib().orc_set_correction_depth(self._h, float(hmin)):
             raise ValueError("invalid correction depth")
+
+    def set_source_field(self, sigma):
+        """Rate field sigma(x, y) [m/s] (ny, nx) (rain > 0, losses < 0), or None."""
+        if sigma is None:
+            rc = lib().orc_set_source_field(self._h, None)
+        else:
+            self._sigma = _f64(sigma, (self.ny, self.nx))
+            rc = lib().orc_set_source_field(self._h, _dp(self._sigma))
+        if rc:
+            raise ValueError("orc_set_source_field rejected the field")
+
+    def field_volume(self):
+        return lib().orc_field_volume(self._h)
 
     def tau_from_speed(self, smax):
         return lib().orc_tau_from_speed(self._h, float(smax))

@@ -58,9 +58,10 @@ struct orc_sim {
     double *Utx, *Uty, *etat;       /* post-Lagrangian velocity and level */
     double *FxH, *FxQn, *FxQt;      /* x-faces (nx+1)*ny */
     double *FyH, *FyQn, *FyQt;      /* y-faces nx*(ny+1) */
+    double *sigma;                  /* source rate field [m/s] (rain > 0, losses < 0) or NULL */
     double *corrE, *corrN;          /* flux corrections (3 planes of nx*ny) or NULL */
     double corr_hmin;               /* depth both cells need for momentum corrections */
-    double t, tau_last, ledger, inflow;
+    double t, tau_last, ledger, inflow, field;
     long steps;
 };
 
@@ -158,6 +159,7 @@ void orc_destroy(orc_sim* s)
     free(s->wett);
     free(s->corrE);
     free(s->corrN);
+    free(s->sigma);
     free(s);
 }
 
@@ -443,14 +445,32 @@ static void lagrangian(orc_sim* s, double tau)
 
 /* Sources (Eq. 1 sigma; Sec. 2.3 stage I) and the post-Lagrangian state.
  * Reading: the inflow velocity V of Eqs. (2)-(3) is zero, so in conservative
- * form the source adds mass only: Ht = H + s, Qt = H U^L. */
-static void post_lagrangian(orc_sim* s, double sdepth)
+ * form the source adds mass only: Ht = H + s, Qt = H U^L.  Two kinds of
+ * sigma: the hydrograph spread over the inlet cells (depth sdepth per step),
+ * and a rate field sigma(x, y) [m/s] for the spatial factors of Sec. 2.1
+ * (precipitation > 0; infiltration and evaporation < 0).  Over a step of
+ * length tau a rate adds tau*sigma of depth; a loss acts only on a cell wet
+ * at layer n (films are inert) and takes at most the water it holds,
+ * Ht = max(Ht + tau*sigma, 0).  The depth the field applied is summed into
+ * the field volume, which closes the volume balance
+ * V_N - V_0 = inflow + field + ledger. */
+static void post_lagrangian(orc_sim* s, double sdepth, double tau)
 {
     const double eps = s->p.eps;
+    double field = 0.0;
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) {
             long c = P(s, i, j);
             double Ht = s->H[c] + (s->src[c] ? sdepth : 0.0);
+            if (s->sigma) {
+                double sg = s->sigma[(long)j * s->nx + i], H1 = Ht;
+                if (sg > 0.0)
+                    H1 = Ht + tau * sg;
+                else if (sg < 0.0 && s->wet[c])
+                    H1 = fmax(Ht + tau * sg, 0.0);
+                field += H1 - Ht;
+                Ht = H1;
+            }
             double qx = s->wet[c] ? s->H[c] * s->ULx[c] : 0.0;
             double qy = s->wet[c] ? s->H[c] * s->ULy[c] : 0.0;
             s->Ht[c] = Ht;
@@ -462,6 +482,7 @@ static void post_lagrangian(orc_sim* s, double sdepth)
             s->Uty[c] = w ? qy / Ht : 0.0;
             s->etat[c] = Ht + s->b[c];
         }
+    s->field += field * s->h * s->h;
     fill_ghost(s, s->Ht, 1.0, 1.0);
     fill_ghost(s, s->Utx, -1.0, 1.0);
     fill_ghost(s, s->Uty, 1.0, -1.0);
@@ -674,7 +695,7 @@ static int step_with(orc_sim* s, double tau)
                                    s->p.sigma_t, s->t, tau);
         sdepth = dV / ((double)s->n_src * s->h * s->h);
     }
-    post_lagrangian(s, sdepth);
+    post_lagrangian(s, sdepth, tau);
     fluxes(s);
     int bad = final_update(s, tau);
     s->t += tau;
@@ -730,6 +751,29 @@ double orc_time(const orc_sim* s) { return s ? s->t : NAN; }
 double orc_last_tau(const orc_sim* s) { return s ? s->tau_last : NAN; }
 double orc_ledger(const orc_sim* s) { return s ? s->ledger : NAN; }
 double orc_inflow(const orc_sim* s) { return s ? s->inflow : NAN; }
+double orc_field_volume(const orc_sim* s) { return s ? s->field : NAN; }
+
+int orc_set_source_field(orc_sim* s, const double* sigma)
+{
+    if (!s) return ORC_EINVAL;
+    if (!sigma) {
+        free(s->sigma);
+        s->sigma = NULL;
+        return 0;
+    }
+    long n = (long)s->nx * s->ny;
+    for (long k = 0; k < n; ++k)
+        if (!isfinite(sigma[k])) return ORC_EINVAL;
+    if (!s->sigma) s->sigma = zalloc(n);
+    if (!s->sigma) return ORC_EINVAL;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            long a = (long)j * s->nx + i;
+            /* a closed gate holds no water: no field there */
+            s->sigma[a] = s->solid[P(s, i, j)] ? 0.0 : sigma[a];
+        }
+    return 0;
+}
 long   orc_steps(const orc_sim* s) { return s ? s->steps : -1; }
 
 int orc_get_state(const orc_sim* s, double* H, double* Qx, double* Qy)

@@ -92,6 +92,10 @@ double orc_time(const orc_sim* s);      /* simulated time */
 double orc_last_tau(const orc_sim* s);  /* time step of the last step */
 double orc_ledger(const orc_sim* s);    /* volume added by depth clamps */
 double orc_inflow(const orc_sim* s);    /* sum of hydrograph volumes */
+/* Rate field sigma(x, y) [m/s] (nx*ny, row-major; rain > 0, infiltration and
+ * evaporation < 0; copied; NULL removes it) and the volume it has applied. */
+int    orc_set_source_field(orc_sim* s, const double* sigma);
+double orc_field_volume(const orc_sim* s);
 long   orc_steps(const orc_sim* s);
 
 int    orc_get_state(const orc_sim* s, double* H, double* Qx, double* Qy);

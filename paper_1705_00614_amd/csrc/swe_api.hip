@@ -185,6 +185,12 @@ struct swe_s {
     const int* ring_tiles = nullptr;
     int nring = 0;
     int ring_b[4] = {-1, 1 << 30, -1, 1 << 30};
+    // source rate field (stencil type), per-tile K1 source bits, per-tile
+    // applied field volume (kept when the field is removed)
+    void* sigma = nullptr;
+    unsigned char* fmask = nullptr;
+    double* fvol = nullptr;
+    bool field = false;
 };
 
 namespace {
@@ -247,6 +253,11 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->ring_tiles = s->ring_tiles;
     a->nring = s->nring;
     a->ring_x0 = s->ring_b[0]; a->ring_x1 = s->ring_b[1]; a->ring_y0 = s->ring_b[2]; a->ring_y1 = s->ring_b[3];
+    if (s->field) {
+        a->sigma = (const real*)s->sigma;
+        a->fmask = s->fmask;
+        a->fvol = s->fvol;
+    }
 }
 
 // Step kernel of a grid: the tapping variant for members of a nest.
@@ -339,7 +350,7 @@ void free_all(swe_t* s) {
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     void* ptrs[] = {s->Hb[0], s->Hb[1], s->Qxb[0], s->Qxb[1], s->Qyb[0], s->Qyb[1], s->bed, s->cf,
                     s->ctrl, s->hot, s->lists, s->stamp, s->wg_speed, s->wg_cells, s->mass, s->ledger,
-                    s->scalar, s->corrE, s->corrN, s->tapx, s->tapy};
+                    s->scalar, s->corrE, s->corrN, s->tapx, s->tapy, s->sigma, s->fmask, s->fvol};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -761,6 +772,74 @@ int swe_work(swe_t* s, long long* tile_steps, long long* cell_steps, int* ntiles
     if (tile_x) *tile_x = s->L->tx;
     if (tile_y) *tile_y = s->L->ty;
     return 0;
+}
+
+int swe_set_source_field(swe_t* s, const double* sigma) {
+    if (!s) { set_err("swe_set_source_field: NULL handle"); return SWE_EINVAL; }
+    if (s->ntap > 0) { set_err("swe_set_source_field: not for grids of a nest"); return SWE_EINVAL; }
+    const size_t n = (size_t)s->nx * s->ny;
+    Ctrl c;
+    int rc = sync_ctrl(s, &c);
+    if (rc) return rc;
+    s->launched = c.step;
+    if (!sigma) {
+        s->field = false;
+    } else {
+        std::vector<double> sg(sigma, sigma + n);
+        for (size_t i = 0; i < n; ++i) {
+            if (!std::isfinite(sg[i])) { set_err("swe_set_source_field: rates must be finite"); return SWE_EINVAL; }
+            if (!s->solid.empty() && s->solid[i]) sg[i] = 0.0;   // a closed gate holds no water
+        }
+        // K1 source bits per tile: own cells, edge cells, outer face neighbours
+        std::vector<unsigned char> fm(s->ntiles, 0);
+        const int tx = s->L->tx, ty = s->L->ty;
+        for (int t = 0; t < s->ntiles; ++t) {
+            const int x0 = (t % s->ntx) * tx, y0 = (t / s->ntx) * ty;
+            const int x1 = std::min(x0 + tx, s->nx), y1 = std::min(y0 + ty, s->ny);
+            unsigned char m = 0;
+            for (int y = y0; y < y1; ++y)
+                for (int x = x0; x < x1; ++x)
+                    if (sg[(size_t)y * s->nx + x] > 0.0) {
+                        m |= 1;
+                        if (x == x0) m |= 2;
+                        if (x == x1 - 1) m |= 4;
+                        if (y == y0) m |= 8;
+                        if (y == y1 - 1) m |= 16;
+                    }
+            auto rain = [&](int x, int y) {
+                return x >= 0 && x < s->nx && y >= 0 && y < s->ny && sg[(size_t)y * s->nx + x] > 0.0;
+            };
+            for (int x = x0; x < x1; ++x) if (rain(x, y0 - 1) || rain(x, y1)) m |= 32;
+            for (int y = y0; y < y1; ++y) if (rain(x0 - 1, y) || rain(x1, y)) m |= 32;
+            fm[t] = m;
+        }
+        if (!s->sigma) {
+            HIPCHK(hipMalloc(&s->sigma, n * s->rsize));
+            HIPCHK(hipMalloc((void**)&s->fmask, s->ntiles));
+        }
+        if (!s->fvol) {
+            HIPCHK(hipMalloc((void**)&s->fvol, sizeof(double) * s->ntiles));
+            HIPCHK(hipMemsetAsync(s->fvol, 0, sizeof(double) * s->ntiles, s->stream));
+        }
+        if ((rc = upload(s, s->sigma, sg.data(), 0.0))) return rc;
+        HIPCHK(hipMemcpyAsync(s->fmask, fm.data(), s->ntiles, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        s->field = true;
+    }
+    build_args(s);
+    drop_graph(s);
+    return prepare(s);
+}
+
+double swe_field_volume(swe_t* s) {
+    if (!s) return NAN;
+    if (!s->fvol) return 0.0;
+    hipLaunchKernelGGL(swe::k_sum_tiles, dim3(1), dim3(1024), 0, s->stream, s->fvol, s->ntiles, s->scalar);
+    double v = NAN;
+    if (hipMemcpyAsync(&v, s->scalar, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return NAN;
+    return v;
 }
 
 int swe_launch_grid(swe_t* s) {

@@ -134,6 +134,13 @@ struct Args {
     // >= ring_y1); such tiles are never put on the list
     const int* ring_tiles;
     int nring, ring_x0, ring_x1, ring_y0, ring_y1;
+    // source rate field sigma(x, y) [m/s] (rain > 0, losses < 0; null: none),
+    // per tile the K1 source bits of its cells with sigma > 0 (own 1, edge
+    // cells W 2, E 4, S 8, N 16, outer face neighbours 32), and per tile the
+    // field volume applied so far [m^3]
+    const real* sigma;
+    const unsigned char* fmask;
+    double* fvol;
 };
 
 template <typename real>
@@ -555,10 +562,23 @@ __device__ __forceinline__ void add_correction(const Args<real>& a, const real* 
     Ft += both ? (xface ? dY : dX) : real(0);
 }
 
+// Depth after the source rate field at cell (gx, gy) of tile coordinates
+// (x, y), from Hs (depth with the inlet source): rain adds tau*sigma; a loss
+// acts only on a cell wet at layer n and takes at most its water.  The depth
+// applied on the tile's own cells goes to fsum.
+template <typename real, int TX, int TY>
+__device__ __forceinline__ real field_depth_t(const Args<real>& a, int gx, int gy, real tau, real Hs, bool wet,
+                                              int x, int y, double& fsum) {
+    const real sg = a.sigma[gy * a.nx + gx];
+    const real Ht = sg > real(0) ? Hs + tau * sg : (sg < real(0) && wet ? rmax(Hs + tau * sg, real(0)) : Hs);
+    if (x >= 0 && x < TX && y >= 0 && y < TY) fsum += (double)(Ht - Hs);
+    return Ht;
+}
+
 template <typename real, int TX, int TY, int NT, int LIM, bool EDGE, int MODE>
 __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, int ty0,
                           real tau, real sdep, real& vmax, bool& bad, double& msum, double& lsum,
-                          int& bits, const ListCtx& lx, int& nbst) {
+                          double& fsum, int fm, int& bits, const ListCtx& lx, int& nbst) {
     using G = Geo<TX, TY>;
     constexpr int W = G::W;
     constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR;
@@ -625,7 +645,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             const bool ring = ((x == -1 || x == TX) && y >= 0 && y < TY) || ((y == -1 || y == TY) && x >= 0 && x < TX);
             if ((own || ring) && inside(x, y) && (w || is_src(a, tx0 + x, ty0 + y))) act = 1;
         }
-        if (__syncthreads_or(act)) bits |= 64;
+        if (__syncthreads_or(act) || (fm & 33)) bits |= 64;
     }
     // self-append of a tile K1-active at layer n: stamp now, slot after P1,
     // entry after P2 (thread 0)
@@ -751,7 +771,8 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     const int x = x0 + i;
                     if (!inside(x, y)) continue;
                     const int s = G::at(x, y);
-                    L.UX[s] = is_src(a, tx0 + x, ty0 + y) ? Hr[i + 1] + sdep : Hr[i + 1];
+                    const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hr[i + 1] + sdep : Hr[i + 1];
+                    L.UX[s] = a.sigma ? field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, false, x, y, fsum) : Hs;
                     L.UY[s] = real(0);
                     L.LM[s] = real(0);
                     L.GX[s] = real(0);
@@ -778,7 +799,8 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real d = real(1) + tau * lam;
                 const real qx = wc ? Hc * Mth<real>::div(ux + tau * ax, d) : real(0);
                 const real qy = wc ? Hc * Mth<real>::div(uy + tau * ay, d) : real(0);
-                const real Ht = is_src(a, tx0 + x, ty0 + y) ? Hc + sdep : Hc;
+                const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hc + sdep : Hc;
+                const real Ht = a.sigma && inside(x, y) ? field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, wc, x, y, fsum) : Hs;
                 const bool wt = Ht > eps;
                 out[i][0] = Ht;
                 out[i][1] = wt ? Mth<real>::div(qx, Ht) : real(0);
@@ -1019,7 +1041,7 @@ template <typename real, int TX, int TY, int NT, int LIM, int MODE>
 __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
-    __shared__ double red_d[2][NWAVE];
+    __shared__ double red_d[3][NWAVE];
     __shared__ int red_i[NWAVE];
     __shared__ int s_last;
 
@@ -1048,35 +1070,41 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
-        double msum = 0.0, lsum = 0.0;
+        double msum = 0.0, lsum = 0.0, fsum = 0.0;
         int bits = 0, nbst = gen;
-        // the tile's clamp ledger is read now and written back at the end
+        const int fm = a.fmask ? (int)a.fmask[tile] : 0;
+        // the tile's clamp ledger and field volume are read now and written
+        // back at the end
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
+        const double fvo = tid == 0 && a.fvol ? a.fvol[tile] : 0.0;
         const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
                          a.skip != 0 && !(RING && ring_tile(a, tile))};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
-                                                         lx, nbst);
+            tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, fsum,
+                                                         fm, bits, lx, nbst);
         else
-            tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, bits,
-                                                          lx, nbst);
+            tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, fsum,
+                                                          fm, bits, lx, nbst);
+        bits |= fm & 63;   // cells with rain are sources of the K1 rule
         // block reductions: flags, volume and ledger partials
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         msum = wave_sum(msum);
         lsum = wave_sum(lsum);
-        if (lane == 0) { red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum; }
+        if (a.fvol) fsum = wave_sum(fsum);
+        if (lane == 0) { red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum; red_d[2][wv] = fsum; }
         __syncthreads();
         if (wv == 0) {
             int bb = 0;
 #pragma unroll
             for (int q = 0; q < NWAVE; ++q) bb |= red_i[q];
             if (lane == 0) {
-                double ms = 0.0, ls = 0.0;
-                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; }
+                double ms = 0.0, ls = 0.0, fs = 0.0;
+                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; fs += red_d[2][q]; }
                 a.mass[tile] = ms;
                 a.ledger[tile] = led + ls * a.h_d * a.h_d;
+                if (a.fvol) a.fvol[tile] = fvo + fs * a.h_d * a.h_d;
             }
             if (a.skip) {
                 // next list: this tile if K1-active at layer n (appended
@@ -1202,7 +1230,7 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
         const bool corner = (lx < 0 || lx >= TX) && (ly < 0 || ly >= TY);
         if (corner) continue;
         const bool w = sH[k] > eps;
-        if (w || is_src(a, gx, gy)) act = 1;
+        if (w || is_src(a, gx, gy) || (a.sigma && a.sigma[gy * nx + gx] > real(0))) act = 1;
         if (!in_tile) continue;
         const real H = sH[k];
         msum += (double)H;
@@ -1339,18 +1367,18 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
         real vt = real(0);
         bool bad = false;
-        double msum = 0.0, lsum = 0.0;
+        double msum = 0.0, lsum = 0.0, fnone = 0.0;   // scenarios of a batch carry no rate field
         int bits = 0, nbst = gen;
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
         const ListCtx lx{a.stamp, ba.lists, ba.hot, ba.list_cap, ba.slot ^ 1, grp, gen, sid, a.tile_base, tile,
                          a.ntx, a.nty, a.skip != 0};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
-            tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits,
-                                                               lx, nbst);
+            tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, fnone,
+                                                               0, bits, lx, nbst);
         else
-            tile_step<real, TX, TY, NT, LIM, false, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, bits,
-                                                                lx, nbst);
+            tile_step<real, TX, TY, NT, LIM, false, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, fnone,
+                                                                0, bits, lx, nbst);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         bits |= __any(bad) ? 128 : 0;

@@ -66,6 +66,8 @@ EXPORTS = {
     "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
     "swe_launch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_set_source_field": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "swe_field_volume": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -296,6 +298,8 @@ class Solver:
         self._h = L.swe_create(self.nx, self.ny, self.h, b, nm, ctypes.byref(p))
         if not self._h:
             raise SweError(SWE_EINVAL, last_error())
+        if sc.get("sigma") is not None:
+            self.set_source_field(sc["sigma"])
 
     def close(self):
         if getattr(self, "_h", None):
@@ -364,6 +368,17 @@ class Solver:
                                ctypes.byref(tx), ctypes.byref(ty)))
         return dict(tile_steps=t.value, cell_steps=c.value, ntiles=n.value, tile=(tx.value, ty.value))
 
+    def set_source_field(self, sigma):
+        """Source rate field sigma(x, y) [m/s] (ny, nx), or None to remove it."""
+        if sigma is None:
+            _check(load().swe_set_source_field(self._h, None))
+        else:
+            a = _f64(sigma, (self.ny, self.nx))
+            _check(load().swe_set_source_field(self._h, _ptr(a)))
+
+    def field_volume(self):
+        return load().swe_field_volume(self._h)
+
     def launch_grid(self):
         """Workgroups of one step launch (the tile list is strided over them)."""
         n = load().swe_launch_grid(self._h)
@@ -421,6 +436,8 @@ class Batch:
     precision, limiter and tile shape come from the first one."""
 
     def __init__(self, scenarios, tile=(0, 0), precision=None, stream="torch"):
+        if any(sc.get("sigma") is not None for sc in scenarios):
+            raise ValueError("scenarios of a batch carry no source rate field")
         L = load()
         st = current_stream() if stream == "torch" else stream
         self.shapes = [(int(sc["ny"]), int(sc["nx"])) for sc in scenarios]
@@ -477,6 +494,8 @@ class Nest:
     extended fine b, n_manning, interior H0, Qx0, Qy0) and r."""
 
     def __init__(self, nest, feedback=True, precision=None, skip_dry=True, stream="torch"):
+        if nest["coarse"].get("sigma") is not None:
+            raise ValueError("a nest carries no source rate field")
         L = load()
         sc, r = nest["coarse"], int(nest["r"])
         st = current_stream() if stream == "torch" else stream

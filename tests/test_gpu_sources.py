@@ -1,0 +1,152 @@
+"""Source rate field sigma(x, y) on the GPU (swe_set_source_field) against the
+FP64 oracle: rain, infiltration and evaporation as spatial factors of the
+continuity equation (arXiv 1705.00614, Sec. 2.1, Eq. 1).  Bars: those of
+tests/parity.py; the field volume against the oracle's (FP64 accumulation of
+the applied depths); skipping dry tiles with rain cells as K1 sources changes
+nothing (bitwise); the volume budget V - V_0 = inflow + field + ledger closes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1705_00614_amd import scenarios as S
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+swe = pytest.importorskip("paper_1705_00614_amd.swe")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu] %s" % request.node.nodeid, flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _rain_case(n=160, seed=12, prec=64):
+    """Floodplain flood with rain over a band across the channel, losses
+    downstream and a dry corner with rain (which must wet it)."""
+    sc = S.floodplain(n=n, seed=seed, precision=prec)
+    sig = np.zeros((n, n))
+    sig[:, n // 4:n // 2] = 3e-5            # rain band
+    sig[:, 3 * n // 4:] = -2e-5             # infiltration / evaporation
+    sig[: n // 8, : n // 8] = 1e-4          # a storm cell over dry ground
+    sc["sigma"] = sig
+    return sc
+
+
+def _budget(g, V0):
+    V = g.mass()
+    return abs(V - V0 - g.inflow() - g.field_volume() - g.ledger()) / max(V, 1e-300)
+
+
+def test_field_fp64_matches_oracle():
+    sc = _rain_case()
+    o = orc.OracleSim(sc)
+    g = swe.Solver(sc)
+    V0 = g.mass()
+    o.run(200)
+    g.run(200)
+    assert abs(g.time() - o.time()) <= 1e-10 * o.time()
+    P.check(g.state(), o.state(), 64, label="field fp64")
+    assert abs(g.field_volume() - o.field_volume()) <= 1e-10 * abs(o.field_volume())
+    assert _budget(g, V0) <= 1e-12
+    assert g.field_volume() != 0.0
+
+
+def test_field_fp32_matches_oracle_at_held_steps():
+    """Rain on dry ground makes films everywhere, and films set the CFL step
+    through friction; the FP32 path runs at the oracle's steps (the step
+    choice is tested on its own below)."""
+    sc = _rain_case(prec=32)
+    o = orc.OracleSim(sc)
+    g = swe.Solver(sc)
+    V0 = g.mass()
+    P.run_held(o, g, 200, 32)
+    P.check(g.state(), o.state(), 32, label="field fp32 held")
+    assert abs(g.field_volume() - o.field_volume()) <= 1e-5 * abs(o.field_volume())
+    assert _budget(g, V0) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_field_time_step_selection_matches_oracle(prec):
+    sc = _rain_case(prec=64)
+    o = orc.OracleSim(sc)
+    o.run(60)
+    st = P.rounded(o.state(), prec)
+    o.set_state(*st)
+    g = swe.Solver(P.with_precision(sc, prec))
+    g.set_state(*st)
+    t_o, t_g = o.next_tau(), g.next_dt()
+    assert abs(t_g - t_o) <= (1e-13 if prec == 64 else 1e-5) * t_o, (t_o, t_g)
+
+
+def test_field_skip_dry_is_bitwise_identical():
+    sc = _rain_case(prec=32)
+    a = swe.Solver(sc, skip_dry=True)
+    b = swe.Solver(sc, skip_dry=False)
+    a.run(120)
+    b.run(120)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    assert a.time() == b.time() and a.field_volume() == b.field_volume()
+    assert a.work()["tile_steps"] < b.work()["tile_steps"]
+
+
+def test_field_tiles_follow_the_k1_rule_with_rain_cells_as_sources():
+    sc = _rain_case(n=200, prec=64)
+    g = swe.Solver(sc, tile=(16, 16))
+    o = orc.OracleSim(sc)
+    p = sc["params"]["inlet"]
+    src = sc["sigma"] > 0
+    src[p[1]:p[1] + p[3], p[0]:p[0] + p[2]] = True
+    prev = None
+    for k in range(20):
+        own, ring = orc.tile_flags(o.state()[0], 16, 16, 1e-4, src)
+        act = np.flatnonzero((own | ring).ravel())
+        expect = act if prev is None else np.union1d(act, prev)
+        assert np.array_equal(g.active_tiles(), expect), k
+        prev = act
+        o.step()
+        g.step()
+
+
+def test_uniform_rain_on_a_still_lake_fp32():
+    n, H0, rate = 64, 1.0, 2e-3
+    z = np.zeros((n, n))
+    sc = dict(nx=n, ny=n, h=2.0, b=z.copy(), n_manning=z.copy(), solid=None, H0=np.full((n, n), H0),
+              Qx0=z.copy(), Qy0=z.copy(), sigma=np.full((n, n), rate),
+              params=S.base_params(precision=32, tau_max=0.5))
+    g = swe.Solver(sc)
+    g.run(100)
+    H, Qx, Qy = g.state()
+    t = g.time()
+    # FP32: each step rounds H + tau*sigma once (relative 6e-8 of ~1 m)
+    assert np.abs(H - (H0 + rate * t)).max() <= 100 * 6e-8 * (H0 + rate * t)
+    assert np.all(H == H[0, 0]) and np.abs(Qx).max() == 0.0 and np.abs(Qy).max() == 0.0
+    area = (n * 2.0) ** 2
+    assert abs(g.field_volume() - rate * t * area) <= 1e-5 * rate * t * area
+
+
+def test_field_can_be_removed_and_is_rejected_when_not_finite():
+    sc = _rain_case(n=96, prec=64)
+    g = swe.Solver(sc)
+    o = orc.OracleSim(sc)
+    g.run(40)
+    o.run(40)
+    g.set_source_field(None)
+    o.set_source_field(None)
+    v = g.field_volume()
+    g.run(40)
+    o.run(40)
+    assert g.field_volume() == v
+    P.check(g.state(), o.state(), 64, label="field removed")
+    bad = np.zeros((96, 96))
+    bad[3, 3] = np.inf
+    with pytest.raises(swe.SweError):
+        g.set_source_field(bad)
+    with pytest.raises(ValueError):
+        swe.Batch([sc])
