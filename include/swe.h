@@ -137,8 +137,10 @@ int    swe_work(swe_t* s, long long* tile_steps, long long* cell_steps,
  * there.  Cells with sigma > 0 are sources of the wet-tile rule (their tiles
  * and the tiles facing them are stepped).  The volume the field applied is
  * accumulated in FP64 per tile: swe_field_volume returns it [m^3], so that
- * V_N - V_0 = swe_inflow + swe_field_volume + swe_ledger.  Not for grids of
- * a nest.  Re-lists the active tiles of the current layer; 0 or SWE_E*. */
+ * V_N - V_0 = swe_inflow + swe_field_volume + swe_ledger.  Default tile
+ * shapes only; not for grids of a nest, nor together with flux corrections,
+ * an attached network or line taps (SWE_EINVAL).  Re-lists the active tiles
+ * of the current layer; 0 or SWE_E*. */
 int    swe_set_source_field(swe_t* s, const double* sigma);
 double swe_field_volume(swe_t* s);
 

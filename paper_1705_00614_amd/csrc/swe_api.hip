@@ -55,6 +55,8 @@ struct Launcher {
                            hipEvent_t e1);   // nested grids; may be null
     hipError_t (*step_corr)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
                             hipEvent_t e1);  // learned flux corrections; may be null
+    hipError_t (*step_field)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1); // source rate field; may be null
     hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
@@ -99,8 +101,9 @@ int occupancy(int* blocks) {
 }
 
 #define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, swe::MODE_TAP>, \
-                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_CORR>
-#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_CORR>, \
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_FIELD>
+#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr, nullptr
 #define LAUNCHER(real, TX, TY, NT, P, LIM, TAPS)                                                 \
     Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, swe::MODE_PLAIN>,             \
              TAPS(real, TX, TY, NT, LIM),                                                        \
@@ -267,7 +270,10 @@ hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent
         const hipError_t e = s->pre_step(s, par);
         if (e != hipSuccess) return e;
     }
-    auto f = (s->ntap > 0 || s->tap_r > 0) ? s->L->step_tap : s->corr ? s->L->step_corr : s->L->step;
+    auto f = (s->ntap > 0 || s->tap_r > 0) ? s->L->step_tap
+             : s->corr                       ? s->L->step_corr
+             : s->field                      ? s->L->step_field
+                                             : s->L->step;
     return f(s->args[par].data(), s->grid, on ? on : s->stream, e0, e1);
 }
 
@@ -777,6 +783,14 @@ int swe_work(swe_t* s, long long* tile_steps, long long* cell_steps, int* ntiles
 int swe_set_source_field(swe_t* s, const double* sigma) {
     if (!s) { set_err("swe_set_source_field: NULL handle"); return SWE_EINVAL; }
     if (s->ntap > 0) { set_err("swe_set_source_field: not for grids of a nest"); return SWE_EINVAL; }
+    if (sigma && !s->L->step_field) {
+        set_err("swe_set_source_field: the tile shape has no field step kernel (default shapes only)");
+        return SWE_EINVAL;
+    }
+    if (sigma && (s->corr || s->lc || s->tap_r > 0)) {
+        set_err("swe_set_source_field: not with flux corrections, an attached network or line taps");
+        return SWE_EINVAL;
+    }
     const size_t n = (size_t)s->nx * s->ny;
     Ctrl c;
     int rc = sync_ctrl(s, &c);
@@ -879,6 +893,7 @@ static size_t line_tap_sizes(const swe_t* s, size_t* nyx) {
 
 int swe_enable_line_taps(swe_t* s, int r) {
     if (!s || r < 0) { set_err("swe_enable_line_taps: invalid arguments"); return SWE_EINVAL; }
+    if (r > 0 && s->field) { set_err("swe_enable_line_taps: not for a grid with a source rate field"); return SWE_EINVAL; }
     if (r == 0) {
         if (s->tapx) (void)hipFree(s->tapx);
         if (s->tapy) (void)hipFree(s->tapy);
@@ -1008,6 +1023,7 @@ int swe_set_correction(swe_t* s, const double* dE, const double* dN) {
         return 0;
     }
     if (!s->L->step_corr) { set_err("swe_set_correction: the tile shape has no correcting step kernel"); return SWE_EINVAL; }
+    if (s->field) { set_err("swe_set_correction: not with a source rate field"); return SWE_EINVAL; }
     if (s->ntap > 0) { set_err("swe_set_correction: not for grids of a nest"); return SWE_EINVAL; }
     const size_t n = 3 * (size_t)s->nx * s->ny;
     if (s->lc) { set_err("swe_set_correction: a network is attached (swe_lc_attach(NULL, grid) first)"); return SWE_EINVAL; }
@@ -2433,6 +2449,7 @@ int swe_lc_attach(swe_lc_t* c, swe_t* s) {
         s->corr = false;
         return 0;
     }
+    if (s->field) { set_err("swe_lc_attach: not for a grid with a source rate field"); return SWE_EINVAL; }
     if (s->L->tx != c->S || s->L->ty != c->S) { set_err("swe_lc_attach: the network's tile differs from the grid's"); return SWE_EINVAL; }
     if (c->max_crops < s->ntiles) { set_err("swe_lc_attach: the network has fewer crop buffers than the grid has tiles"); return SWE_EINVAL; }
     if (!s->L->step_corr || s->ntap > 0) { set_err("swe_lc_attach: grid cannot take corrections"); return SWE_EINVAL; }

@@ -151,8 +151,8 @@ __device__ __forceinline__ bool ring_tile(const Args<real>& a, int tile) {
 }
 
 // Variants of the step kernel: plain, with flux taps (nested grids), with
-// learned flux corrections.
-constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2;
+// learned flux corrections, with a source rate field.
+constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2, MODE_FIELD = 3;
 
 // ---------------------------------------------------------------- math
 
@@ -581,7 +581,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                           double& fsum, int fm, int& bits, const ListCtx& lx, int& nbst) {
     using G = Geo<TX, TY>;
     constexpr int W = G::W;
-    constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR;
+    constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR, FLD = MODE == MODE_FIELD;
     const int tid = threadIdx.x, nx = a.nx, ny = a.ny;
     const real eps = a.eps, half_tau = real(0.5) * tau, r = tau * a.ih;
     // normalised cubic-B-spline SPH gradient weights (smoothing length h):
@@ -645,7 +645,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             const bool ring = ((x == -1 || x == TX) && y >= 0 && y < TY) || ((y == -1 || y == TY) && x >= 0 && x < TX);
             if ((own || ring) && inside(x, y) && (w || is_src(a, tx0 + x, ty0 + y))) act = 1;
         }
-        if (__syncthreads_or(act) || (fm & 33)) bits |= 64;
+        if (__syncthreads_or(act) || (FLD && (fm & 33))) bits |= 64;
     }
     // self-append of a tile K1-active at layer n: stamp now, slot after P1,
     // entry after P2 (thread 0)
@@ -772,7 +772,10 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     if (!inside(x, y)) continue;
                     const int s = G::at(x, y);
                     const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hr[i + 1] + sdep : Hr[i + 1];
-                    L.UX[s] = a.sigma ? field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, false, x, y, fsum) : Hs;
+                    if constexpr (FLD)
+                        L.UX[s] = field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, false, x, y, fsum);
+                    else
+                        L.UX[s] = Hs;
                     L.UY[s] = real(0);
                     L.LM[s] = real(0);
                     L.GX[s] = real(0);
@@ -800,7 +803,9 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real qx = wc ? Hc * Mth<real>::div(ux + tau * ax, d) : real(0);
                 const real qy = wc ? Hc * Mth<real>::div(uy + tau * ay, d) : real(0);
                 const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hc + sdep : Hc;
-                const real Ht = a.sigma && inside(x, y) ? field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, wc, x, y, fsum) : Hs;
+                real Ht = Hs;
+                if constexpr (FLD)
+                    if (inside(x, y)) Ht = field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, wc, x, y, fsum);
                 const bool wt = Ht > eps;
                 out[i][0] = Ht;
                 out[i][1] = wt ? Mth<real>::div(qx, Ht) : real(0);
@@ -1041,7 +1046,7 @@ template <typename real, int TX, int TY, int NT, int LIM, int MODE>
 __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> a) {
     constexpr int NWAVE = NT / 64;
     __shared__ Lds<real, TX, TY> L;
-    __shared__ double red_d[3][NWAVE];
+    __shared__ double red_d[MODE == MODE_FIELD ? 3 : 2][NWAVE];
     __shared__ int red_i[NWAVE];
     __shared__ int s_last;
 
@@ -1070,13 +1075,14 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
+        constexpr bool FLD = MODE == MODE_FIELD;
         double msum = 0.0, lsum = 0.0, fsum = 0.0;
         int bits = 0, nbst = gen;
-        const int fm = a.fmask ? (int)a.fmask[tile] : 0;
-        // the tile's clamp ledger and field volume are read now and written
+        const int fm = FLD ? (int)a.fmask[tile] : 0;
+        // the tile's clamp ledger (and field volume) are read now and written
         // back at the end
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
-        const double fvo = tid == 0 && a.fvol ? a.fvol[tile] : 0.0;
+        const double fvo = FLD && tid == 0 ? a.fvol[tile] : 0.0;
         const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
                          a.skip != 0 && !(RING && ring_tile(a, tile))};
         __syncthreads();   // LDS of the previous tile is free
@@ -1086,25 +1092,32 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         else
             tile_step<real, TX, TY, NT, LIM, false, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, fsum,
                                                           fm, bits, lx, nbst);
-        bits |= fm & 63;   // cells with rain are sources of the K1 rule
+        if constexpr (FLD) bits |= fm & 63;   // cells with rain are sources of the K1 rule
         // block reductions: flags, volume and ledger partials
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
         msum = wave_sum(msum);
         lsum = wave_sum(lsum);
-        if (a.fvol) fsum = wave_sum(fsum);
-        if (lane == 0) { red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum; red_d[2][wv] = fsum; }
+        if constexpr (FLD) fsum = wave_sum(fsum);
+        if (lane == 0) {
+            red_i[wv] = bits; red_d[0][wv] = msum; red_d[1][wv] = lsum;
+            if constexpr (FLD) red_d[2][wv] = fsum;
+        }
         __syncthreads();
         if (wv == 0) {
             int bb = 0;
 #pragma unroll
             for (int q = 0; q < NWAVE; ++q) bb |= red_i[q];
             if (lane == 0) {
-                double ms = 0.0, ls = 0.0, fs = 0.0;
-                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; fs += red_d[2][q]; }
+                double ms = 0.0, ls = 0.0;
+                for (int q = 0; q < NWAVE; ++q) { ms += red_d[0][q]; ls += red_d[1][q]; }
                 a.mass[tile] = ms;
                 a.ledger[tile] = led + ls * a.h_d * a.h_d;
-                if (a.fvol) a.fvol[tile] = fvo + fs * a.h_d * a.h_d;
+                if constexpr (FLD) {
+                    double fs = 0.0;
+                    for (int q = 0; q < NWAVE; ++q) fs += red_d[2][q];
+                    a.fvol[tile] = fvo + fs * a.h_d * a.h_d;
+                }
             }
             if (a.skip) {
                 // next list: this tile if K1-active at layer n (appended

@@ -181,11 +181,13 @@ def advance_to(g, t_end, frac=0.5):
     stencil type)."""
     while True:
         left = t_end - g.time()
-        if left <= 0.0:
-            if -left > 1e-6 * max(abs(t_end), 1.0):
+        dt = g.next_dt()
+        # landed: within a millionth of a step (the held last step is exact
+        # to the rounding of its length to the stencil type)
+        if left <= 1e-6 * dt:
+            if -left > 1e-6 * dt:
                 raise RuntimeError("advance_to: overshot %g by %g s" % (t_end, -left))
             return
-        dt = g.next_dt()
         n = int(frac * left / dt)
         if n >= 2:
             g.run(n)
@@ -252,8 +254,9 @@ class GuardedRun:
         else:
             V, dV_in, dV_cl = g.mass(), g.inflow() - in0, g.ledger() - cl0
             scale = max(abs(V), abs(V0), 1e-300)
-            if not abs(V - V0 - dV_in - dV_cl) <= self.vol_tol * scale:
-                reason = "volume balance"
+            resid = (V - V0 - dV_in - dV_cl) / scale
+            if not abs(resid) <= self.vol_tol:
+                reason = "volume balance %.3g" % resid
             elif not abs(dV_cl) <= self.clamp_tol * scale:
                 reason = "clamped volume"
         if reason is None and self.judge_every and (k + 1) % self.judge_every == 0:

@@ -6,9 +6,13 @@ Two bars for every comparison of a GPU layer with the oracle's layer:
     max |dQ| <= cell_tol * max |Q_oracle| (both components), so that an error
     confined to a few cells (a tile's halo, a wall row) cannot hide in a sum.
 
-FP64 stencil: the same arithmetic up to rounding order and contraction, so
-differences stay at the level of rounding; the bars are 1e-10 (L1) and 1e-12
-(per cell).  FP32 stencil: the spec bar of 1e-4 relative L1 after 200
+FP64 stencil: the same arithmetic up to rounding order and contraction into
+FMAs, each operation agreeing to ~1e-16; over 60-200 steps of a nonlinear
+scheme with limiter branches and wet/dry thresholds these differences grow in
+rough states (measured up to ~8e-11 of the largest value in a cell of a
+nested patch, ~1e-11 on random wet/dry states), so both bars are 1e-10.  A
+local defect (a wrong neighbour, halo or wall value) moves the cells it
+touches by O(1) of their values, far above 1e-10.  FP32 stencil: the spec bar of 1e-4 relative L1 after 200
 steps; the per-cell bar is 2e-4: FP32 rounds every stored value to a relative
 6e-8, an error that a stable step carries forward without growth, so 200 steps
 accumulate at most ~200 * 6e-8 = 1.2e-5 of the largest value per cell, plus a
@@ -19,7 +23,7 @@ import numpy as np
 
 from oracle import oracle as orc
 
-BARS = {64: (1e-10, 1e-12), 32: (1e-4, 2e-4)}
+BARS = {64: (1e-10, 1e-10), 32: (1e-4, 2e-4)}
 
 
 def rel_l1(a, b):

@@ -96,25 +96,17 @@ def test_nest_one_way_matches_oracle():
 def test_nest_fp32_matches_oracle_at_held_steps():
     """FP32 nest over 48 coarse steps at the oracle nest's time steps.  The
     nest's CFL rule takes the minimum over the coarse grid and r times every
-    patch, so a film in any patch can set it; with the steps held, FP32
-    rounding of the coupled layers stays at the single-grid level."""
+    patch, so a film in any grid can set it, and with free steps FP32
+    rounding alone parts two oracle runs beyond 1e-4
+    (tests/test_oracle_conditioning.py); with the steps held it stays at the
+    single-grid level.  The rule itself is checked in FP64 (clock and both
+    step lengths to 1e-12 above)."""
     nest = _floodplain_nest(32)
     O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
     G = swe.Nest(nest)
     _run_held(G, O, 48, 32)
     _compare(G, O, 32, "held")
     assert G.query()["time"] == O.time()
-
-
-def test_nest_fp32_free_steps_match_oracle():
-    """FP32 nest with its own CFL steps over 24 coarse steps."""
-    nest = _floodplain_nest(32)
-    O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
-    G = swe.Nest(nest)
-    G.run(24)
-    O.run(24)
-    _compare(G, O, 32, "free")
-    assert abs(G.query()["time"] - O.time()) <= 1e-4 * O.time()
 
 
 def test_nest_hold_then_release_follows_the_cfl_rule():
@@ -171,9 +163,9 @@ def test_nest_rejects_bad_layouts():
         swe.Nest(two)
 
 
-@pytest.mark.parametrize("prec,tol,box", [(64, 1e-10, (24, 24, 44, 40)), (32, None, (24, 24, 44, 40)),
-                                          (64, 1e-10, (22, 26, 46, 38))])
-def test_patches_skip_dry_tiles_exactly(prec, tol, box):
+@pytest.mark.parametrize("prec,vs_oracle,box", [(64, True, (24, 24, 44, 40)), (32, False, (24, 24, 44, 40)),
+                                                 (64, True, (22, 26, 46, 38))])
+def test_patches_skip_dry_tiles_exactly(prec, vs_oracle, box):
     """Patches skip dry tiles except the ring of tiles holding the frame,
     which the nest rewrites between substeps (also where the frame straddles
     two tile columns and rows): a patch large enough to have dry interior
@@ -199,10 +191,10 @@ def test_patches_skip_dry_tiles_exactly(prec, tol, box):
     wa, wb = a.work(), b.work()
     assert wa["fine_cells"] < wb["fine_cells"]
     assert (a.patch_state(0)[0] > 1e-4).any()
-    if tol is not None:
+    if vs_oracle:
         O = OracleNest(nest["coarse"], nest["patches"], r=nest["r"])
         O.run(40)
-        _compare(a, O, tol)
+        _compare(a, O, prec, "skip box %s" % (box,))
 
 
 def test_full_size_nest_first_coarse_steps_match_oracle():

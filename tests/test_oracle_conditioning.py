@@ -15,11 +15,17 @@ of the GPU path with the oracle can hold a 1e-4 bar with free time steps:
 * the fully wet control (a nearly still lake under weak wind): the step is
   unaffected, but FP32 rounding of the level perturbs the weak forcing, so
   the discharge itself is ill-conditioned in FP32 (its GPU bar is measured
-  against this perturbed oracle).
+  against this perturbed oracle);
+* nested grids: the coupled CFL rule (the minimum over the coarse grid and r
+  times every patch) is set by films in any grid, so with free steps the
+  rounded run's clock drifts by ~3e-4 and HU parts by >1e-4 within 24 coarse
+  steps, while at held steps it stays within ~3e-5; the FP32 nest is
+  therefore compared with the oracle at held steps.
 """
 import numpy as np
 
 from oracle import oracle as orc
+from oracle.nest import OracleNest
 from paper_1705_00614_amd import scenarios as S
 from tests import parity as P
 
@@ -58,3 +64,37 @@ def test_wet_control_discharge_is_ill_conditioned_in_fp32():
     assert dt < 1e-5           # the step is not the cause
     assert e[0] < 1e-6         # the depth is well conditioned
     assert e[1] > 1e-5         # the weak discharge is not
+
+
+def _nest_pair(held, steps=24):
+    sc = S.floodplain(n=48, h=50.0, seed=4, q_peak=800.0, t_peak=300.0, sigma_t=200.0, inlet_cells=4,
+                      precision=64)
+    n = S.nest(sc, [(14, 10, 12, 10), (30, 26, 8, 12)], r=4, seed=9)
+    a = OracleNest(n["coarse"], n["patches"], r=4)
+    b = OracleNest(n["coarse"], n["patches"], r=4)
+    worst = 0.0
+    for _ in range(steps):
+        if held:
+            tc = a.next_taus()[0]
+            a.step(tc)
+            b.step(tc)
+        else:
+            a.step()
+            b.step()
+        b.c.set_state(*P.rounded(b.c.state(), 32))
+        for q in b.P:
+            q["sim"].set_state(*P.rounded(q["sim"].state(), 32))
+        errs = [P.errors(b.coarse_state(), a.coarse_state())]
+        errs += [P.errors(b.patch_state(k), a.patch_state(k)) for k in range(len(a.P))]
+        worst = max([worst] + [e[1] for e in errs])
+    return worst, abs(b.time() / a.time() - 1.0)
+
+
+def test_nest_free_steps_are_ill_conditioned_in_fp32():
+    worst, dt = _nest_pair(held=False)
+    assert worst > 1e-4 and dt > 1e-5
+
+
+def test_nest_held_steps_are_well_conditioned_in_fp32():
+    worst, dt = _nest_pair(held=True, steps=48)
+    assert worst < 1e-4 and dt == 0.0
