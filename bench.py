@@ -51,8 +51,9 @@ BYTES_PER_CELL = {32: 32, 64: 64}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9900)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: floodplain and wet 20, nest 5000, ensemble 2000)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 5, ensemble 20)")
     ap.add_argument("--workload", choices=["floodplain", "wet", "nest", "ensemble", "learned"],
                     default="floodplain")
     ap.add_argument("--n", type=int, default=4096)
@@ -60,16 +61,21 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--corr-depth", type=float, default=None, metavar="M",
                     help="learned leg: depth both cells of a face need for a momentum correction")
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     ap.add_argument("--warmup-launches", action="store_true",
                     help="run the warm-up as single launches (no hipGraph), e.g. under counter collection")
     ap.add_argument("--progress", type=int, default=0, metavar="N",
                     help="run the timed steps in chunks of N with a progress line on stderr after each "
                          "(long profiler passes)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the skip-off and FP64 runs of the same window (counter passes)")
     ap.add_argument("--per-launch", action="store_true",
                     help="time each step kernel with its own HIP event pair instead of graph replays")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.steps = a.steps if a.steps is not None else {"nest": 5000, "ensemble": 2000}.get(a.workload, 20)
+    a.warmup = a.warmup if a.warmup is not None else {"ensemble": 20}.get(a.workload, 5)
+    return a
 
 
 def kernel_source_digest():
@@ -80,7 +86,8 @@ def kernel_source_digest():
 
 def profiled_traffic(key):
     """HBM bytes per launch from a committed counter summary, if it was taken
-    with the current kernel source for the same workload and steps."""
+    with the current kernel source for the same workload (its window of steps
+    is stated in the summary)."""
     path = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -106,18 +113,41 @@ def profiled_traffic(key):
     return None
 
 
-def cpu_baseline(sc, steps):
+def cpu_baseline(sc, skip, steps):
+    """The FP64 oracle (single-threaded C) on the host: `skip` untimed steps
+    from the initial state, then `steps` timed steps, every cell each step."""
     from oracle import oracle
     t0 = time.perf_counter()
     sim = oracle.OracleSim(sc)
+    sim.run(skip)
     t1 = time.perf_counter()
     sim.run(steps)
     t2 = time.perf_counter()
     cells = sc["nx"] * sc["ny"] * steps
     return {"value": cells / (t2 - t1) / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d steps of the same %dx%d workload from its initial state, FP64, every "
-                      "cell each step (the oracle has no dry-tile skip); %.1f s of CPU time, setup "
-                      "%.1f s excluded" % (steps, sc["nx"], sc["ny"], t2 - t1, t1 - t0)}
+            "sample": "steps %d..%d of the same %dx%d workload (the first %d untimed), FP64, every cell "
+                      "each step (the oracle has no dry-tile skip), one thread; %.1f s timed, %.1f s setup "
+                      "and untimed steps" % (skip, skip + steps, sc["nx"], sc["ny"], skip, t2 - t1, t1 - t0)}
+
+
+def time_window(swe, torch, stream, sc, warmup, steps, **kw):
+    """ms per step and processed cells of `steps` graph-replayed steps after
+    `warmup` steps, on a fresh solver built from the scenario."""
+    g = swe.Solver(sc, **kw)
+    g.run(warmup)
+    w0 = g.work()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = g.work()["cell_steps"] - w0["cell_steps"]
+    st = g.state()
+    g.close()
+    return ms / steps, cells, st
 
 
 def main():
@@ -212,9 +242,23 @@ def main():
             "volume_balance_rel": abs(V - V0 - inflow - ledger) / max(V, 1e-300),
         },
     }
+    # the same window with dry-tile skipping off (the paper's Sec. 5 gain of
+    # skipping dry blocks, in kind) and with the FP64 stencil
+    if not args.no_extra:
+        with torch.cuda.stream(stream):
+            ms_off, _, st_off = time_window(swe, torch, stream, sc, args.warmup, args.steps, tile=tile,
+                                            skip_dry=False)
+            same = all(np.array_equal(a, b) for a, b in zip(st_off, g.state()))
+            sc64 = dict(sc, params=dict(sc["params"], precision=64))
+            ms64, cells64, _ = time_window(swe, torch, stream, sc64, args.warmup, args.steps)
+        out["config"]["skip_off"] = {"ms_per_step": ms_off, "skip_speedup": ms_off / (ev_ms / args.steps),
+                                     "state_bitwise_equal": bool(same)}
+        out["config"]["fp64"] = {"ms_per_step": ms64,
+                                 "active_gcell_per_s": cells64 / (ms64 * args.steps * 1e-3) / 1e9,
+                                 "hbm_frac": 64.0 * cells64 / (ms64 * args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
     alg_bytes = BYTES_PER_CELL[prec] * cells
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    key = "%s n=%d tile=%s warmup=%d steps=%d" % (args.workload, args.n, args.tile, args.warmup, args.steps)
+    key = "%s n=%d tile=%s" % (args.workload, args.n, args.tile)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(key),
                        "traffic_unit": "HBM bytes per launch",
@@ -223,7 +267,10 @@ def main():
                        "mean_launch_us": kernel_ms * 1e3 / args.steps,
                        "bytes_per_launch": alg_bytes / args.steps}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+        # the oracle's window: the GPU's own when its warm-up is short,
+        # else the first steps of the flood
+        skip = args.warmup if args.warmup <= 50 else 0
+        out["cpu_baseline"] = cpu_baseline(sc, skip, min(args.cpu_steps, args.steps))
     print(json.dumps(out), flush=True)
 
 
@@ -242,7 +289,7 @@ def bench_nest(args):
     from paper_1705_00614_amd import scenarios as S
     from paper_1705_00614_amd import swe
     nd = S.nest_floodplain(n=2048, h=50.0, seed=1, r=4, box=512)
-    steps = args.steps if args.steps != 9900 else 5000
+    steps = args.steps
     warm = args.warmup
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -288,8 +335,8 @@ def bench_ensemble(args):
     from paper_1705_00614_amd import scenarios as S
     from paper_1705_00614_amd import swe
     ens = S.ensemble(n=256)
-    steps = args.steps if args.steps != 9900 else 2000
-    warm = args.warmup if args.warmup != 100 else 20
+    steps = args.steps
+    warm = args.warmup
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         # the project's autotuner picks the tile shape (outside the timed region)

@@ -42,11 +42,11 @@ class OrcParams(ctypes.Structure):
         ("in_j0", ctypes.c_int), ("in_ni", ctypes.c_int),
         ("in_nj", ctypes.c_int), ("q_base", ctypes.c_double),
         ("q_peak", ctypes.c_double), ("t_peak", ctypes.c_double),
-        ("sigma_t", ctypes.c_double),
+        ("sigma_t", ctypes.c_double), ("sph_displaced", ctypes.c_int),
     ]
 
 
-F_GX, F_GY, F_UHX, F_UHY, F_ULX, F_ULY, F_HT, F_QTX, F_QTY = range(9)
+F_GX, F_GY, F_UHX, F_UHY, F_ULX, F_ULY, F_HT, F_QTX, F_QTY, F_GDX, F_GDY = range(11)
 
 _lib = None
 
@@ -116,7 +116,8 @@ def make_params(prm, periodic=False):
         limiter=prm.get("limiter", 0), periodic=int(periodic),
         in_i0=inlet[0], in_j0=inlet[1], in_ni=inlet[2], in_nj=inlet[3],
         q_base=prm.get("q_base", 0.0), q_peak=prm.get("q_peak", 0.0),
-        t_peak=prm.get("t_peak", 0.0), sigma_t=prm.get("sigma_t", 0.0))
+        t_peak=prm.get("t_peak", 0.0), sigma_t=prm.get("sigma_t", 0.0),
+        sph_displaced=int(prm.get("sph_displaced", 0)))
 
 
 class OracleSim:

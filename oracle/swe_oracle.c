@@ -51,6 +51,7 @@ struct orc_sim {
     unsigned char *wet;             /* H > eps at layer n */
     double *Ux, *Uy, *eta;          /* derived at layer n */
     double *Gx, *Gy, *lam0;         /* pressure gradient, c_f / H^(4/3) */
+    double *Gdx, *Gdy;              /* gradient at the displaced positions (corrector) */
     double *Uhx, *Uhy;              /* U at t_{n+1/2} */
     double *ULx, *ULy;              /* Lagrangian U at t_{n+1} */
     double *Ht, *Qtx, *Qty;         /* post-Lagrangian state */
@@ -151,7 +152,7 @@ void orc_destroy(orc_sim* s)
                          &s->eta, &s->Gx, &s->Gy, &s->lam0, &s->Uhx, &s->Uhy,
                          &s->ULx, &s->ULy, &s->Ht, &s->Qtx, &s->Qty, &s->Utx,
                          &s->Uty, &s->etat, &s->FxH, &s->FxQn, &s->FxQt,
-                         &s->FyH, &s->FyQn, &s->FyQt};
+                         &s->FyH, &s->FyQn, &s->FyQt, &s->Gdx, &s->Gdy};
     for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k) free(*fields[k]);
     free(s->src);
     free(s->solid);
@@ -230,7 +231,7 @@ orc_sim* orc_create(int nx, int ny, double h, const double* b,
     double** fields[] = {&s->b, &s->cf, &s->H, &s->Qx, &s->Qy, &s->Ux, &s->Uy,
                          &s->eta, &s->Gx, &s->Gy, &s->lam0, &s->Uhx, &s->Uhy,
                          &s->ULx, &s->ULy, &s->Ht, &s->Qtx, &s->Qty, &s->Utx,
-                         &s->Uty, &s->etat};
+                         &s->Uty, &s->etat, &s->Gdx, &s->Gdy};
     for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k) {
         *fields[k] = zalloc(n);
         if (!*fields[k]) { orc_destroy(s); return NULL; }
@@ -406,12 +407,74 @@ static double cfl_tau(orc_sim* s)
 /* Stage II: Lagrangian predictor-corrector                            */
 /* ------------------------------------------------------------------ */
 
+/* Derivative dW/dq of the 2D cubic B-spline kernel shape (support q < 2):
+ * W = 1 - 3/2 q^2 + 3/4 q^3 for q < 1, 1/4 (2 - q)^3 for 1 <= q < 2.  Its
+ * normalisation constant cancels in the corrected gradient below. */
+static double bspline_dw(double q)
+{
+    if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+    if (q < 2.0) return -0.75 * (2.0 - q) * (2.0 - q);
+    return 0.0;
+}
+
+/* Pressure gradient at the displaced particle positions of t_{n+1/2}
+ * (Sec. 2.3 stage II and kernels K4-K6: the particles move inside the cells;
+ * the corrector takes the forces at the positions of the half step).
+ * Reading: particle j sits at its cell centre c_j + (tau/2) U_j^n (dry
+ * particles at rest); the level gradient at a wet particle i is the
+ * corrected SPH sum of the cubic B-spline kernel with smoothing length h over
+ * the particles of its 5x5 neighbourhood (with |tau U| <= K h < h every
+ * particle within the support 2h of i is among them):
+ *   w_ij = W'(|r_ij|/h) r_ij / |r_ij|,  r_ij = p_j - p_i,
+ *   S    = sum_j (eta*_j - eta_i) w_ij,  M = sum_j w_ij r_ij^T,
+ *   G_i  = M^{-1} S,
+ * exact for a linear level whatever the displacements; with no
+ * displacement it is the lattice stencil of pressure_gradient.  eta*_j is the
+ * level particle j shows to i (the rule of pressure_gradient). */
+static void displaced_gradient(orc_sim* s, double tau)
+{
+    const double h = s->h;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            long c = P(s, i, j);
+            if (!s->wet[c]) { s->Gdx[c] = s->Gdy[c] = 0.0; continue; }
+            double ec = s->eta[c], bc = s->b[c];
+            double pxi = 0.5 * tau * s->Ux[c] / h, pyi = 0.5 * tau * s->Uy[c] / h;
+            double Sx = 0.0, Sy = 0.0, mxx = 0.0, mxy = 0.0, myx = 0.0, myy = 0.0;
+            for (int dj = -2; dj <= 2; ++dj)
+                for (int di = -2; di <= 2; ++di) {
+                    if (!di && !dj) continue;
+                    long m = c + (long)dj * s->px + di;
+                    double rx = di + 0.5 * tau * s->Ux[m] / h - pxi;
+                    double ry = dj + 0.5 * tau * s->Uy[m] / h - pyi;
+                    double r = sqrt(rx * rx + ry * ry);
+                    double dw = bspline_dw(r);
+                    if (dw == 0.0) continue;
+                    double Hm = s->wet[m] ? s->H[m] : 0.0;
+                    double em = s->wet[m] ? s->eta[m] : s->b[m];
+                    double es = fmax(bc, fmin(em, ec + Hm));
+                    double wx = dw * rx / r, wy = dw * ry / r;
+                    Sx += (es - ec) * wx;
+                    Sy += (es - ec) * wy;
+                    mxx += wx * rx;
+                    mxy += wx * ry;
+                    myx += wy * rx;
+                    myy += wy * ry;
+                }
+            double det = mxx * myy - mxy * myx;
+            s->Gdx[c] = (myy * Sx - mxy * Sy) / det / h;
+            s->Gdy[c] = (mxx * Sy - myx * Sx) / det / h;
+        }
+}
+
 /* Reading of the predictor-corrector (Sec. 2.3, stage II; K4-K6): midpoint
  * rule with the pressure gradient of layer n and friction point-implicit:
  *   U^{n+1/2} = (U + tau/2 A(U)) / (1 + tau/2 Lambda(U)),
  *   U^L       = (U + tau   A(U^{n+1/2})) / (1 + tau Lambda(U^{n+1/2})),
  * A(U) = -g G + F_visc(U) + F_cor(U) + F_wind(U), Lambda(U) = c_f|U|/H^(4/3).
- * The particle displacement tau*U^L is carried by the fluxes of stage III. */
+ * The particle displacement tau*U^L is carried by the fluxes of stage III.
+ * G is the lattice gradient of layer n in both halves, or (sph_displaced) in
+ * the corrector the gradient at the displaced positions of t_{n+1/2}. */
 static void lagrangian(orc_sim* s, double tau)
 {
     const double g = s->p.g;
@@ -429,13 +492,19 @@ static void lagrangian(orc_sim* s, double tau)
         }
     fill_ghost(s, s->Uhx, -1.0, 1.0);
     fill_ghost(s, s->Uhy, 1.0, -1.0);
+    const double *Gcx = s->Gx, *Gcy = s->Gy;
+    if (s->p.sph_displaced) {
+        displaced_gradient(s, tau);
+        Gcx = s->Gdx;
+        Gcy = s->Gdy;
+    }
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) {
             long c = P(s, i, j);
             if (!s->wet[c]) { s->ULx[c] = s->ULy[c] = 0.0; continue; }
             double hx = s->Uhx[c], hy = s->Uhy[c], fx, fy;
             soft_forces(s, c, s->Uhx, s->Uhy, &fx, &fy);
-            double ax = -g * s->Gx[c] + fx, ay = -g * s->Gy[c] + fy;
+            double ax = -g * Gcx[c] + fx, ay = -g * Gcy[c] + fy;
             double lam = s->lam0[c] * sqrt(hx * hx + hy * hy);
             double d = 1.0 + tau * lam;
             s->ULx[c] = (s->Ux[c] + tau * ax) / d;
@@ -799,7 +868,7 @@ int orc_get_field(const orc_sim* s, int which, double* out)
 {
     if (!s || !out || which < 0 || which >= ORC_F_COUNT) return ORC_EINVAL;
     const double* f[ORC_F_COUNT] = {s->Gx, s->Gy, s->Uhx, s->Uhy, s->ULx, s->ULy,
-                                    s->Ht, s->Qtx, s->Qty};
+                                    s->Ht, s->Qtx, s->Qty, s->Gdx, s->Gdy};
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) out[(long)j * s->nx + i] = f[which][P(s, i, j)];
     return 0;

@@ -46,6 +46,9 @@ typedef struct {
     int periodic;      /* 0 reflective walls, 1 periodic wrap (tests) */
     int in_i0, in_j0, in_ni, in_nj;   /* inlet rectangle of source cells */
     double q_base, q_peak, t_peak, sigma_t; /* Gaussian hydrograph [m^3/s], [s] */
+    int sph_displaced; /* 1: corrector pressure gradient at the displaced
+                          particle positions of t_{n+1/2} (SPH sum over the
+                          5x5 neighbourhood, corrected); 0: lattice stencil */
 } orc_params;
 
 /* Error codes (negative). */
@@ -108,6 +111,8 @@ enum {
     ORC_F_UHX, ORC_F_UHY,       /* predictor velocity at t_{n+1/2}          */
     ORC_F_ULX, ORC_F_ULY,       /* corrector (Lagrangian) velocity          */
     ORC_F_HT, ORC_F_QTX, ORC_F_QTY, /* post-Lagrangian depth and momentum   */
+    ORC_F_GDX, ORC_F_GDY,       /* gradient at the displaced positions of
+                                   t_{n+1/2} (sph_displaced only)           */
     ORC_F_COUNT
 };
 int    orc_get_field(const orc_sim* s, int which, double* out);
