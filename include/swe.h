@@ -442,6 +442,44 @@ int       swe_lc_set_out_scale(swe_lc_t* c, const double* out_scale);
 /* Message of the last error on this host thread ("" if none). */
 const char* swe_last_error(void);
 
+/* ------------------------------------------------------------------ step without allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step
+ * of swe_step's arithmetic on a layer the caller owns, with no handle.  The
+ * step's bookkeeping (control block, completion counters, per-tile volume
+ * and clamp partials) lives in a fixed device array of about 300 KB that
+ * each GPU the library runs on holds until the process ends; the call makes
+ * no hipMalloc, hipFree or other allocation, and no memset (kernels clear
+ * what must start at zero, so it can be captured in a graph).
+ *
+ *   nx, ny, dx   grid; at most SWE_NOALLOC_MAX_TILES tiles of the default
+ *                tile shape of the precision (4096 x 4096 in FP32 with
+ *                32 x 32 tiles, 2048 x 2048 in FP64 with 16 x 16 tiles);
+ *                larger grids are SWE_EINVAL
+ *   p            physics, precision, limiter, inlet and hydrograph, stream
+ *                as for swe_create; solid, H0, Qx0, Qy0 and skip_dry are
+ *                not used (every tile is stepped, so every output cell is
+ *                written); tile_x, tile_y must be 0 or the default shape
+ *   b, cf        device arrays of the stencil type (float for precision 32,
+ *                double for 64), nx*ny row-major: bed (closed gates already
+ *                raised above any level) and c_f = g n_M^2
+ *   H, Qx, Qy    device layer n (depth >= 0; discharges 0 on dry cells)
+ *   H1, Qx1, Qy1 device layer n+1, written; must not alias the inputs
+ *   t            time of layer n [s] (the hydrograph's clock)
+ *   out          optional device array of 5 doubles, written: t_{n+1}, the
+ *                step length (the CFL step of layer n, Sec. 2.3), the
+ *                hydrograph volume of the step, the clamped volume, and the
+ *                device error code (0, SWE_ENONFINITE or SWE_EDTCOLLAPSE)
+ *
+ * Work is queued on p->stream and not waited for.  Every call on one GPU
+ * shares that GPU's array and leaves the last call's contents in it: calls
+ * that overlap on one GPU (other streams, other host threads) race and are
+ * not allowed.  Returns 0 or SWE_EINVAL / SWE_EHIP (host-side checks). */
+#define SWE_NOALLOC_MAX_TILES 16384
+int    swe_step_noalloc(int nx, int ny, double dx, const swe_params* p, const void* b, const void* cf,
+                        const void* H, const void* Qx, const void* Qy, void* H1, void* Qx1, void* Qy1,
+                        double t, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2848,3 +2849,178 @@ int swe_batch_autotune(int nb, const int* nx, const int* ny, const double* dx, c
     }
     return report_shapes(sh, t, n, cap, tile_x, tile_y, ms);
 }
+
+// ---------------------------------------------------------------- step without allocation
+//
+// One step of a caller-owned layer for callers that cannot allocate (code
+// under HIP graph capture, tight serving loops).  The step's bookkeeping --
+// control block, completion counters, per-workgroup maxima and cell counts,
+// per-tile volume and clamp partials -- lives in `scratch`, a fixed device
+// array that every GPU holds for the life of the process.  In host code the
+// array's name stands for no device address: its address on each device is
+// taken once with hipGetSymbolAddress and only that pointer is passed on.
+
+namespace {
+
+constexpr int NOALLOC_MAX_GRID = 4096;   // workgroups of one step launch
+constexpr size_t NOALLOC_CTRL = 0;
+constexpr size_t NOALLOC_HOT = 256;
+constexpr size_t NOALLOC_MASS = NOALLOC_HOT + sizeof(int) * swe::HOT_INTS;
+constexpr size_t NOALLOC_LEDGER = NOALLOC_MASS + sizeof(double) * SWE_NOALLOC_MAX_TILES;
+constexpr size_t NOALLOC_BYTES = NOALLOC_LEDGER + sizeof(double) * SWE_NOALLOC_MAX_TILES;
+static_assert(sizeof(Ctrl) <= NOALLOC_HOT, "control block must fit its slot");
+static_assert(NOALLOC_HOT % 256 == 0 && NOALLOC_MASS % 256 == 0, "counters on 256-byte lines");
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};   // device address of `scratch` per device
+int g_noalloc_cus[NOALLOC_MAX_DEV] = {};
+
+// Clear the bookkeeping of one step and set the clock: a kernel, not a
+// memset, so the call can be captured in a graph.
+__global__ void k_noalloc_init(unsigned char* sc, int ntiles, double t) {
+    Ctrl* c = reinterpret_cast<Ctrl*>(sc + NOALLOC_CTRL);
+    int* hot = reinterpret_cast<int*>(sc + NOALLOC_HOT);
+    double* ledger = reinterpret_cast<double*>(sc + NOALLOC_LEDGER);
+    for (int i = threadIdx.x; i < swe::HOT_INTS; i += blockDim.x) hot[i] = 0;
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) ledger[i] = 0.0;
+    if (threadIdx.x == 0) {
+        Ctrl z{};
+        z.t = t;
+        *c = z;
+    }
+}
+
+// Scalars of the step for the caller: t_{n+1}, the step length, the
+// hydrograph volume and the clamped volume (fixed-order sum of the partials).
+__global__ void k_noalloc_out(const unsigned char* sc, int ntiles, double* out) {
+    __shared__ double red[256];
+    const double* ledger = reinterpret_cast<const double*>(sc + NOALLOC_LEDGER);
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) s += ledger[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int q = 0; q < (int)blockDim.x; ++q) v += red[q];
+        const Ctrl* c = reinterpret_cast<const Ctrl*>(sc + NOALLOC_CTRL);
+        out[0] = c->t;
+        out[1] = c->last_tau;
+        out[2] = c->inflow;
+        out[3] = v;
+        out[4] = (double)c->err;
+    }
+}
+
+template <typename real>
+void fill_args_noalloc(Args<real>* a, const swe_params& p, int nx, int ny, double dx, int ntx, int nty,
+                       const void* b, const void* cf, const void* H, const void* Qx, const void* Qy, void* H1,
+                       void* Qx1, void* Qy1, unsigned char* sc) {
+    std::memset(a, 0, sizeof *a);
+    a->Hi = (const real*)H; a->Qxi = (const real*)Qx; a->Qyi = (const real*)Qy;
+    a->Ho = (real*)H1; a->Qxo = (real*)Qx1; a->Qyo = (real*)Qy1;
+    a->bed = (const real*)b; a->cf = (const real*)cf;
+    a->ctrl = a->lctrl = reinterpret_cast<Ctrl*>(sc + NOALLOC_CTRL);
+    a->hot = reinterpret_cast<int*>(sc + NOALLOC_HOT);
+    a->mass = reinterpret_cast<double*>(sc + NOALLOC_MASS);
+    a->ledger = reinterpret_cast<double*>(sc + NOALLOC_LEDGER);
+    a->nx = nx; a->ny = ny; a->ntx = ntx; a->nty = nty; a->ntiles = ntx * nty;
+    a->list_cap = ntx * nty;
+    a->skip = 0;   // every tile is stepped, so every output cell is written
+    a->limiter = p.limiter;
+    const int nin = p.inlet_ni > 0 && p.inlet_nj > 0 ? p.inlet_ni * p.inlet_nj : 0;
+    if (nin > 0) { a->i0 = p.inlet_i0; a->j0 = p.inlet_j0; a->ni = p.inlet_ni; a->nj = p.inlet_nj; }
+    a->h = (real)dx; a->ih = (real)(1.0 / dx); a->g = (real)p.g; a->eps = (real)p.eps;
+    a->nuh2 = (real)(p.nu / (dx * dx)); a->fcor = (real)p.f_coriolis;
+    a->wx = (real)p.wind_x; a->wy = (real)p.wind_y; a->kw = (real)p.wind_kappa; a->hw = (real)p.h_wind;
+    a->h_d = dx; a->g_d = p.g; a->cfl = p.cfl; a->tau_max = p.dt_max; a->tau_min = p.dt_min; a->nu_d = p.nu;
+    a->nin_h2 = nin > 0 ? (double)nin * dx * dx : 0.0;
+    a->q_base = p.q_base; a->q_peak = p.q_peak; a->t_peak = p.t_peak; a->sigma_t = p.sigma_t;
+    a->corr_hmin = (real)p.eps;
+    a->ring_x0 = -1; a->ring_x1 = 1 << 30; a->ring_y0 = -1; a->ring_y1 = 1 << 30;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_step_noalloc(int nx, int ny, double dx, const swe_params* p, const void* b, const void* cf,
+                     const void* H, const void* Qx, const void* Qy, void* H1, void* Qx1, void* Qy1, double t,
+                     double* out) {
+    if (nx < 1 || ny < 1 || !(dx > 0.0) || !std::isfinite(dx) || !p || !b || !cf || !H || !Qx || !Qy || !H1 ||
+        !Qx1 || !Qy1 || !std::isfinite(t)) {
+        set_err("swe_step_noalloc: invalid arguments");
+        return SWE_EINVAL;
+    }
+    if (H1 == H || H1 == Qx || H1 == Qy || Qx1 == H || Qx1 == Qx || Qx1 == Qy || Qy1 == H || Qy1 == Qx ||
+        Qy1 == Qy) {
+        set_err("swe_step_noalloc: outputs must not alias the inputs");
+        return SWE_EINVAL;
+    }
+    if ((p->precision != 32 && p->precision != 64) || !(p->cfl > 0.0 && p->cfl < 1.0) || !(p->eps > 0.0) ||
+        p->limiter < 0 || p->limiter > 2) {
+        set_err("swe_step_noalloc: invalid parameters");
+        return SWE_EINVAL;
+    }
+    const Launcher* L = find_launcher(p->precision, 0, 0, p->limiter);
+    if (!L || ((p->tile_x || p->tile_y) && (p->tile_x != L->tx || p->tile_y != L->ty))) {
+        set_err("swe_step_noalloc: default tile shape only");
+        return SWE_EINVAL;
+    }
+    const int ntx = (nx + L->tx - 1) / L->tx, nty = (ny + L->ty - 1) / L->ty;
+    if ((long long)ntx * nty > SWE_NOALLOC_MAX_TILES) {
+        set_err("swe_step_noalloc: the grid has more tiles than the fixed scratch holds (SWE_NOALLOC_MAX_TILES)");
+        return SWE_EINVAL;
+    }
+    if (p->inlet_ni > 0 && p->inlet_nj > 0 &&
+        (p->inlet_i0 < 0 || p->inlet_j0 < 0 || p->inlet_i0 + p->inlet_ni > nx || p->inlet_j0 + p->inlet_nj > ny)) {
+        set_err("swe_step_noalloc: inlet outside the grid");
+        return SWE_EINVAL;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) { set_err("swe_step_noalloc: device index out of range"); return SWE_EINVAL; }
+    unsigned char* sc;
+    int cus;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void* ptr = nullptr;
+            HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            int c = 0;
+            HIPCHK(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+            g_noalloc_cus[dev] = c;
+            g_noalloc_ptr[dev] = (unsigned char*)ptr;
+        }
+        sc = g_noalloc_ptr[dev];
+        cus = g_noalloc_cus[dev];
+    }
+    int occ = 0;
+    if (L->occupancy(&occ) != 0 || occ < 1) occ = 1;
+    int grid = cus * occ;
+    if (grid < 8) grid = 8;
+    if (grid > ntx * nty) grid = ntx * nty;
+    if (grid > NOALLOC_MAX_GRID) grid = NOALLOC_MAX_GRID;
+    hipStream_t st = (hipStream_t)p->stream;
+    constexpr size_t ARGS_BYTES = std::max(sizeof(Args<double>), sizeof(Args<float>));
+    alignas(16) unsigned char args[ARGS_BYTES];
+    if (p->precision == 32)
+        fill_args_noalloc<float>((Args<float>*)args, *p, nx, ny, dx, ntx, nty, b, cf, H, Qx, Qy, H1, Qx1, Qy1, sc);
+    else
+        fill_args_noalloc<double>((Args<double>*)args, *p, nx, ny, dx, ntx, nty, b, cf, H, Qx, Qy, H1, Qx1, Qy1,
+                                  sc);
+    hipLaunchKernelGGL(k_noalloc_init, dim3(1), dim3(256), 0, st, sc, ntx * nty, t);
+    HIPCHK(hipGetLastError());
+    HIPCHK(L->prepare(args, ntx * nty, st));          // CFL step of the layer, volume partials
+    HIPCHK(L->prepare_finish(args, st));              // tau, hydrograph volume of the step
+    HIPCHK(L->step(args, grid, st, nullptr, nullptr));
+    if (out) {
+        hipLaunchKernelGGL(k_noalloc_out, dim3(1), dim3(256), 0, st, (const unsigned char*)sc, ntx * nty, out);
+        HIPCHK(hipGetLastError());
+    }
+    return 0;
+}
+
+}  // extern "C"

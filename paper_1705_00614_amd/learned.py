@@ -228,17 +228,28 @@ class GuardedRun:
         self.vol_tol, self.clamp_tol = vol_tol, clamp_tol
         self.judge_every, self.err_tol = int(judge_every), err_tol
         self.fine = swe.Solver(fine_sc)
-        csc = coarsen(fine_sc, r)
-        self.coarse = swe.Solver(csc)
-        self.coarse.restrict_from(self.fine, r)
-        net.attach(self.coarse)
-        self.coarse.set_correction_depth(corr_depth)
-        self.ref = swe.Solver(csc)       # restricted fine layers for the judge
+        self.csc = coarsen(fine_sc, r)
+        self.corr_depth = corr_depth
+        self.coarse = None
+        self._new_coarse()
+        self.ref = swe.Solver(self.csc)  # restricted fine layers for the judge
         self.log = []
+
+    def _new_coarse(self):
+        """A fresh coarse grid at the fine solve's layer, network attached
+        (after a failed window the old grid's clamp ledger may hold the
+        diverged steps' volumes, so its bookkeeping is not carried over)."""
+        if self.coarse is not None:
+            self.net.detach(self.coarse)
+            self.coarse.close()
+        self.coarse = swe.Solver(self.csc)
+        self.coarse.restrict_from(self.fine, self.r)
+        self.net.attach(self.coarse)
+        self.coarse.set_correction_depth(self.corr_depth)
 
     def _fallback(self, t_end):
         advance_to(self.fine, t_end)
-        self.coarse.restrict_from(self.fine, self.r)
+        self._new_coarse()
 
     def step_window(self):
         g = self.coarse

@@ -66,6 +66,8 @@ EXPORTS = {
     "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
     "swe_launch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_step_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p]
+                         + [ctypes.c_void_p] * 8 + [ctypes.c_double, ctypes.c_void_p]),
     "swe_set_source_field": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "swe_field_volume": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_work": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
@@ -221,6 +223,21 @@ def make_params(prm, skip_dry=True, tile=(0, 0), stream=None):
     p.sigma_t = prm.get("sigma_t", 0.0)
     p.stream = stream
     return p
+
+
+def step_noalloc(sc, b, cf, H, Qx, Qy, H1, Qx1, Qy1, t, out=None, stream="torch"):
+    """One step of a caller-owned device layer without allocation
+    (swe_step_noalloc): the physics of scenario dict `sc`; b, cf, H, Qx, Qy
+    and the outputs H1, Qx1, Qy1 (and the optional 5-double `out`) are
+    device tensors of the stencil type (torch), row-major (ny, nx).  Queued
+    on the stream, not waited for."""
+    st = current_stream() if stream == "torch" else stream
+    p = make_params(dict(sc["params"]), True, (0, 0), st)
+    ptr = lambda a: ctypes.c_void_p(a.data_ptr())
+    rc = load().swe_step_noalloc(int(sc["nx"]), int(sc["ny"]), float(sc["h"]), ctypes.byref(p), ptr(b), ptr(cf),
+                                 ptr(H), ptr(Qx), ptr(Qy), ptr(H1), ptr(Qx1), ptr(Qy1), float(t),
+                                 None if out is None else ptr(out))
+    return _check(rc)
 
 
 def _grid_inputs(sc, skip_dry, tile, precision, st):

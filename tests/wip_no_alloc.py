@@ -1,0 +1,83 @@
+"""The step without allocation (swe_step_noalloc) against swe_step on a
+handle: the same arithmetic on the same layer, so the new layer and the
+step's scalars must agree bit for bit (every tile is stepped without a
+handle; skipping dry tiles does not change a result, which the handle's own
+tests show).  Two calls in a row, the second on a smaller grid, in FP32 and
+FP64; an oversized grid is refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1705_00614_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+swe = pytest.importorskip("paper_1705_00614_amd.swe")
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu] %s" % request.node.nodeid, flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _device_layer(sc, prec):
+    """Bed, c_f and layer 0 on the device, rounded to the stencil type as
+    swe_create rounds them (dry cells at rest, c_f = g n_M^2 in FP64)."""
+    dt = torch.float32 if prec == 32 else torch.float64
+    nt = np.float32 if prec == 32 else np.float64
+    eps = sc["params"]["eps"]
+    H0 = np.asarray(sc["H0"], np.float64)
+    wet = H0 > eps
+    Qx0 = np.where(wet, sc["Qx0"], 0.0)
+    Qy0 = np.where(wet, sc["Qy0"], 0.0)
+    nm = np.asarray(sc["n_manning"], np.float64)
+    cf = sc["params"]["g"] * nm * nm
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).astype(nt))).to("cuda", dt)
+    return dev(sc["b"]), dev(cf), dev(H0), dev(Qx0), dev(Qy0)
+
+
+def _one(sc, prec):
+    sc = dict(sc, params=dict(sc["params"], precision=prec))
+    b, cf, H, Qx, Qy = _device_layer(sc, prec)
+    H1, Qx1, Qy1 = torch.empty_like(H), torch.empty_like(Qx), torch.empty_like(Qy)
+    # poison the outputs: every cell must be written
+    for a in (H1, Qx1, Qy1):
+        a.fill_(float("nan"))
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
+    swe.step_noalloc(sc, b, cf, H, Qx, Qy, H1, Qx1, Qy1, 0.0, out)
+    torch.cuda.synchronize()
+    g = swe.Solver(sc)
+    g.step()
+    ref = g.state()
+    got = [a.cpu().numpy().astype(np.float64) for a in (H1, Qx1, Qy1)]
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    o = out.cpu().numpy()
+    assert o[0] == g.time() and o[1] == g.last_dt() and o[4] == 0.0
+    assert o[2] == g.inflow()
+    # clamped volume: the same partials summed in another order
+    assert abs(o[3] - g.ledger()) <= 1e-12 * max(1.0, abs(g.ledger()))
+    g.close()
+    return o
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_noalloc_step_equals_the_handle_step_on_two_calls(prec):
+    o1 = _one(S.floodplain(n=256, seed=21), prec)
+    o2 = _one(S.floodplain(n=96, seed=22), prec)     # second call, smaller grid
+    assert o1[1] > 0 and o2[1] > 0 and o1[2] > 0
+
+
+def test_noalloc_step_refuses_oversized_grids():
+    sc = S.floodplain(n=64, seed=1)
+    b, cf, H, Qx, Qy = _device_layer(sc, 32)
+    big = dict(sc, nx=4096 + 32, ny=4096)
+    with pytest.raises(swe.SweError):
+        swe.step_noalloc(big, b, cf, H, Qx, Qy, torch.empty_like(H), torch.empty_like(Qx),
+                         torch.empty_like(Qy), 0.0)
+    with pytest.raises(swe.SweError):   # outputs aliasing inputs
+        swe.step_noalloc(sc, b, cf, H, Qx, Qy, H, torch.empty_like(Qx), torch.empty_like(Qy), 0.0)
