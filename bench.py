@@ -131,7 +131,7 @@ def cpu_baseline(sc, skip, steps):
 
 
 def time_window(swe, torch, stream, sc, warmup, steps, **kw):
-    """ms per step and processed cells of `steps` graph-replayed steps after
+    """ms per step and processed cells of `steps` queued steps after
     `warmup` steps, on a fresh solver built from the scenario."""
     g = swe.Solver(sc, **kw)
     g.run(warmup)
@@ -140,9 +140,10 @@ def time_window(swe, torch, stream, sc, warmup, steps, **kw):
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    g.run(steps)
+    g.enqueue(steps)
     e1.record(stream)
     torch.cuda.synchronize()
+    g.run(0)
     ms = e0.elapsed_time(e1)
     cells = g.work()["cell_steps"] - w0["cell_steps"]
     st = g.state()
@@ -201,14 +202,17 @@ def main():
             c = min(chunk, args.steps - done)
             if args.per_launch:
                 kernel_ms += g.run_timed(c)
-            else:
+            elif args.progress > 0:
                 g.run(c)
+            else:
+                g.enqueue(c)          # queued; the events bracket the steps alone
             done += c
             if args.progress > 0:
                 print("bench: %d/%d steps" % (done, args.steps), file=sys.stderr, flush=True)
         e1.record(stream)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
+        g.run(0)                      # device errors of the queued steps
         w1, t_sim1 = g.work(), g.time()
         ev_ms = e0.elapsed_time(e1)
         if not args.per_launch:
@@ -238,7 +242,8 @@ def main():
             "simulated_seconds": t_sim1 - t_sim0,
             "wall_seconds": wall,
             "timing": "per-launch HIP events" if args.per_launch else
-                      "hipGraph replays of the single-step kernel; HIP events around the timed region",
+                      "steps queued as swe_run queues them (hipGraph replays of 32 single-step kernels, single "
+                      "launches for the rest) with HIP events on the library's stream around them",
             "volume_balance_rel": abs(V - V0 - inflow - ledger) / max(V, 1e-300),
         },
     }
@@ -310,6 +315,7 @@ def bench_nest(args):
     cells = (w1["coarse_cells"] - w0["coarse_cells"]) + (w1["fine_cells"] - w0["fine_cells"])
     secs = kms * 1e-3
     r = nd["r"]
+    cmp = {} if args.no_extra else nest_feedback_comparison(swe, S, torch, stream, nd, N, warm, steps)
     grid_cells = steps * (nd["coarse"]["nx"] * nd["coarse"]["ny"] +
                           r * sum(r * p["cw"] * r * p["ch"] for p in nd["patches"]))
     _line("nested grids: cell-updates/s (coarse and patch cells of the tiles processed)", cells / secs / 1e9,
@@ -322,10 +328,61 @@ def bench_nest(args):
            "simulated_seconds": q1["time"] - q0["time"],
            "timing": "hipGraph replays of whole coarse steps (coarse step, frames, patch substeps, feedback, "
                      "time step); HIP events around the timed region",
-           "volume_balance_rel": abs(q1["volume"] - q0["volume"] - q1["inflow"] - q1["ledger"]) / q1["volume"]},
+           "volume_balance_rel": abs(q1["volume"] - q0["volume"] - q1["inflow"] - q1["ledger"]) / q1["volume"],
+           **cmp},
           roofline={"bound": "hbm", "achieved": 32.0 * cells / secs / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": 32.0 * cells / secs / 1e9 / HBM_PEAK_GBS, "traffic": None,
                     "kernel": "whole coarse step (k_step coarse and patches, frame, feedback, time step)"})
+
+
+def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps):
+    """Zoom-in without feedback (one-way) against the two-way nest (Sec. 2.2:
+    less accurate but faster): time per coarse step of the one-way nest over
+    the same steps, and the depth error of both inside the patches against a
+    uniform fine grid over the whole domain (the same terrain at the patch
+    resolution, run to the same simulated time), beside the error of the
+    coarse grid alone."""
+    from paper_1705_00614_amd import learned as LC
+    r = nd["r"]
+    with torch.cuda.stream(stream):
+        one = swe.Nest(nd, feedback=False)
+        one.run(warm)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        one.run(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_one = e0.elapsed_time(e1) / steps
+        runs = {"two_way": two_way, "one_way": one}
+        times = {k: v.query()["time"] for k, v in runs.items()}
+        coarse = swe.Solver(nd["coarse"])
+        fine = swe.Solver(S.nest_reference(nd["source"], nd))
+        err = {k: [] for k in list(runs) + ["coarse_only"]}
+        for name in sorted(runs, key=lambda k: times[k]):
+            LC.advance_to(fine, times[name])
+            LC.advance_to(coarse, times[name])
+            Hf = fine.state()[0]
+            Hc = coarse.state()[0]
+            for k, p in enumerate(nd["patches"]):
+                win = (slice(p["cj0"] * r, (p["cj0"] + p["ch"]) * r), slice(p["ci0"] * r, (p["ci0"] + p["cw"]) * r))
+                ref = Hf[win]
+                den = max(np.abs(ref).sum(), 1e-300)
+                err[name].append(float(np.abs(runs[name].patch_state(k)[0] - ref).sum() / den))
+                if name == "two_way":
+                    cwin = (slice(p["cj0"], p["cj0"] + p["ch"]), slice(p["ci0"], p["ci0"] + p["cw"]))
+                    up = np.kron(Hc[cwin], np.ones((r, r)))
+                    err["coarse_only"].append(float(np.abs(up - ref).sum() / den))
+        fine.close()
+        coarse.close()
+        one.close()
+    return {"one_way": {"ms_per_coarse_step": ms_one, "depth_error_in_patches_vs_uniform_fine": err["one_way"],
+                        "simulated_seconds": times["one_way"]},
+            "two_way_depth_error_in_patches_vs_uniform_fine": err["two_way"],
+            "coarse_only_depth_error_in_patches_vs_uniform_fine": err["coarse_only"],
+            "uniform_fine_reference": "%dx%d at %g m, same terrain, run to each nest's time"
+                                      % (nd["coarse"]["nx"] * r, nd["coarse"]["ny"] * r, nd["coarse"]["h"] / r)}
 
 
 def bench_ensemble(args):

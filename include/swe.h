@@ -77,6 +77,14 @@ typedef struct {
     const double* Qx0;     /* nx*ny initial unit discharge H*Ux or NULL */
     const double* Qy0;     /* nx*ny initial unit discharge H*Uy or NULL */
     void*  stream;         /* hipStream_t owned by the caller, or NULL */
+    int    sph_displaced;  /* 1: the corrector takes the pressure gradient at
+                            the particle positions of t_{n+1/2} (Sec. 2.3
+                            stage II, K4-K6): cell centre + (tau/2) U^n, the
+                            corrected SPH sum of the cubic B-spline kernel
+                            over the 5x5 neighbourhood; 0: the lattice
+                            stencil at the centres (default).  Single grids
+                            with the default tile shape; not with nests,
+                            batches, corrections, networks, taps or fields. */
 } swe_params;
 
 /* Create a solver on an nx x ny grid of cell size dx [m] with bed elevation
@@ -97,6 +105,13 @@ int    swe_step(swe_t* s);
  * steps replayed from a captured hipGraph.  Synchronises at the end.  Stops
  * advancing at the first device error and returns it. */
 int    swe_run(swe_t* s, long nsteps);
+
+/* As swe_run, but only queues the steps on the stream and returns without
+ * waiting (host-side errors only).  Device errors of the queued steps are
+ * reported by the next synchronising call (swe_run(s, 0), swe_step, a
+ * query).  For callers that overlap host work with the steps, and for
+ * timing the steps alone with events on the stream. */
+int    swe_enqueue(swe_t* s, long nsteps);
 
 /* Water volume dx^2 * sum(H) [m^3], reduced on the GPU in FP64 in a fixed
  * order; NaN on error. */

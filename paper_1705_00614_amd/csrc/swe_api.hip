@@ -58,6 +58,8 @@ struct Launcher {
                             hipEvent_t e1);  // learned flux corrections; may be null
     hipError_t (*step_field)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
                              hipEvent_t e1); // source rate field; may be null
+    hipError_t (*step_disp)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
+                            hipEvent_t e1);  // displaced-particle corrector; may be null
     hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
@@ -103,8 +105,9 @@ int occupancy(int* blocks) {
 
 #define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, swe::MODE_TAP>, \
                                         launch_step<real, TX, TY, NT, LIM, swe::MODE_CORR>, \
-                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_FIELD>
-#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr, nullptr
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_FIELD>, \
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_DISP>
+#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr, nullptr, nullptr
 #define LAUNCHER(real, TX, TY, NT, P, LIM, TAPS)                                                 \
     Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, swe::MODE_PLAIN>,             \
              TAPS(real, TX, TY, NT, LIM),                                                        \
@@ -274,6 +277,7 @@ hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent
     auto f = (s->ntap > 0 || s->tap_r > 0) ? s->L->step_tap
              : s->corr                       ? s->L->step_corr
              : s->field                      ? s->L->step_field
+             : s->p.sph_displaced            ? s->L->step_disp
                                              : s->L->step;
     return f(s->args[par].data(), s->grid, on ? on : s->stream, e0, e1);
 }
@@ -509,6 +513,10 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
     }
     const Launcher* L = find_launcher(p->precision, p->tile_x, p->tile_y, p->limiter);
     if (!L) { set_err("swe_create: tile shape not available for this precision"); return nullptr; }
+    if (p->sph_displaced && (!L->step_disp || ex)) {
+        set_err("swe_create: the displaced-particle corrector needs a single grid with the default tile shape");
+        return nullptr;
+    }
     // a tile-list entry holds the tile index in TILE_BITS bits
     if ((long long)((nx + L->tx - 1) / L->tx) * ((ny + L->ty - 1) / L->ty) >= (1LL << swe::TILE_BITS)) {
         set_err("swe_create: grid has too many tiles for the tile list (at most 2^20 - 1)"); return nullptr;
@@ -640,8 +648,9 @@ int swe_step(swe_t* s) {
     return finish(s);
 }
 
-int swe_run(swe_t* s, long nsteps) {
-    if (!s || nsteps < 0) { set_err("swe_run: invalid arguments"); return SWE_EINVAL; }
+// Queue nsteps steps (graph replays of GRAPH_STEPS steps, single launches
+// for the rest) without waiting for them.
+static int enqueue_steps(swe_t* s, long nsteps) {
     long left = nsteps;
     int rc;
     if (left > 0 && (s->launched & 1)) {
@@ -656,8 +665,18 @@ int swe_run(swe_t* s, long nsteps) {
             left -= GRAPH_STEPS;
         }
     }
-    if ((rc = launch_steps(s, left))) return rc;
-    return finish(s);
+    return launch_steps(s, left);
+}
+
+int swe_run(swe_t* s, long nsteps) {
+    if (!s || nsteps < 0) { set_err("swe_run: invalid arguments"); return SWE_EINVAL; }
+    const int rc = enqueue_steps(s, nsteps);
+    return rc ? rc : finish(s);
+}
+
+int swe_enqueue(swe_t* s, long nsteps) {
+    if (!s || nsteps < 0) { set_err("swe_enqueue: invalid arguments"); return SWE_EINVAL; }
+    return enqueue_steps(s, nsteps);
 }
 
 int swe_run_timed(swe_t* s, long nsteps, double* kernel_ms) {
@@ -788,7 +807,7 @@ int swe_set_source_field(swe_t* s, const double* sigma) {
         set_err("swe_set_source_field: the tile shape has no field step kernel (default shapes only)");
         return SWE_EINVAL;
     }
-    if (sigma && (s->corr || s->lc || s->tap_r > 0)) {
+    if (sigma && (s->corr || s->lc || s->tap_r > 0 || s->p.sph_displaced)) {
         set_err("swe_set_source_field: not with flux corrections, an attached network or line taps");
         return SWE_EINVAL;
     }
@@ -894,7 +913,10 @@ static size_t line_tap_sizes(const swe_t* s, size_t* nyx) {
 
 int swe_enable_line_taps(swe_t* s, int r) {
     if (!s || r < 0) { set_err("swe_enable_line_taps: invalid arguments"); return SWE_EINVAL; }
-    if (r > 0 && s->field) { set_err("swe_enable_line_taps: not for a grid with a source rate field"); return SWE_EINVAL; }
+    if (r > 0 && (s->field || s->p.sph_displaced)) {
+        set_err("swe_enable_line_taps: not for a grid with a source rate field or the displaced-particle corrector");
+        return SWE_EINVAL;
+    }
     if (r == 0) {
         if (s->tapx) (void)hipFree(s->tapx);
         if (s->tapy) (void)hipFree(s->tapy);
@@ -1024,7 +1046,10 @@ int swe_set_correction(swe_t* s, const double* dE, const double* dN) {
         return 0;
     }
     if (!s->L->step_corr) { set_err("swe_set_correction: the tile shape has no correcting step kernel"); return SWE_EINVAL; }
-    if (s->field) { set_err("swe_set_correction: not with a source rate field"); return SWE_EINVAL; }
+    if (s->field || s->p.sph_displaced) {
+        set_err("swe_set_correction: not with a source rate field or the displaced-particle corrector");
+        return SWE_EINVAL;
+    }
     if (s->ntap > 0) { set_err("swe_set_correction: not for grids of a nest"); return SWE_EINVAL; }
     const size_t n = 3 * (size_t)s->nx * s->ny;
     if (s->lc) { set_err("swe_set_correction: a network is attached (swe_lc_attach(NULL, grid) first)"); return SWE_EINVAL; }
@@ -1183,6 +1208,8 @@ swe_batch_t* swe_batch_create(int n, const int* nx, const int* ny, const double*
     }
     const swe_params& p0 = p[0];
     if (!p0.skip_dry) { set_err("swe_batch_create: a batch runs with dry-tile skipping"); return nullptr; }
+    for (int k = 0; k < n; ++k)
+        if (p[k].sph_displaced) { set_err("swe_batch_create: no displaced-particle corrector in a batch"); return nullptr; }
     const Launcher* L = find_launcher(p0.precision, p0.tile_x, p0.tile_y, p0.limiter);
     if (!L) { set_err("swe_batch_create: tile shape not available for this precision/limiter"); return nullptr; }
     long long total = 0;
@@ -2450,7 +2477,10 @@ int swe_lc_attach(swe_lc_t* c, swe_t* s) {
         s->corr = false;
         return 0;
     }
-    if (s->field) { set_err("swe_lc_attach: not for a grid with a source rate field"); return SWE_EINVAL; }
+    if (s->field || s->p.sph_displaced) {
+        set_err("swe_lc_attach: not for a grid with a source rate field or the displaced-particle corrector");
+        return SWE_EINVAL;
+    }
     if (s->L->tx != c->S || s->L->ty != c->S) { set_err("swe_lc_attach: the network's tile differs from the grid's"); return SWE_EINVAL; }
     if (c->max_crops < s->ntiles) { set_err("swe_lc_attach: the network has fewer crop buffers than the grid has tiles"); return SWE_EINVAL; }
     if (!s->L->step_corr || s->ntap > 0) { set_err("swe_lc_attach: grid cannot take corrections"); return SWE_EINVAL; }
@@ -3015,7 +3045,7 @@ int swe_step_noalloc(int nx, int ny, double dx, const swe_params* p, const void*
     HIPCHK(hipGetLastError());
     HIPCHK(L->prepare(args, ntx * nty, st));          // CFL step of the layer, volume partials
     HIPCHK(L->prepare_finish(args, st));              // tau, hydrograph volume of the step
-    HIPCHK(L->step(args, grid, st, nullptr, nullptr));
+    HIPCHK((p->sph_displaced ? L->step_disp : L->step)(args, grid, st, nullptr, nullptr));
     if (out) {
         hipLaunchKernelGGL(k_noalloc_out, dim3(1), dim3(256), 0, st, (const unsigned char*)sc, ntx * nty, out);
         HIPCHK(hipGetLastError());

@@ -151,8 +151,9 @@ __device__ __forceinline__ bool ring_tile(const Args<real>& a, int tile) {
 }
 
 // Variants of the step kernel: plain, with flux taps (nested grids), with
-// learned flux corrections, with a source rate field.
-constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2, MODE_FIELD = 3;
+// learned flux corrections, with a source rate field, with the corrector's
+// pressure gradient at the displaced particle positions.
+constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2, MODE_FIELD = 3, MODE_DISP = 4;
 
 // ---------------------------------------------------------------- math
 
@@ -562,6 +563,56 @@ __device__ __forceinline__ void add_correction(const Args<real>& a, const real* 
     Ft += both ? (xface ? dY : dX) : real(0);
 }
 
+// Slope dW/dq of the 2D cubic B-spline kernel shape (support q < 2); its
+// normalisation cancels in the corrected gradient.
+template <typename real>
+__device__ __forceinline__ real bspline_dw(real q) {
+    const real u = real(2) - q;
+    return q < real(1) ? q * (real(2.25) * q - real(3)) : (q < real(2) ? real(-0.75) * u * u : real(0));
+}
+
+// Level gradient at the particle of LDS cell s displaced to its position of
+// t_{n+1/2} (cell centre + tau/2 U^n), as the corrected SPH sum over the
+// particles of its 5x5 neighbourhood (Sec. 2.3 stage II, K4-K6):
+// G = M^{-1} sum_j (eta*_j - eta_i) w_ij, M = sum_j w_ij r_ij^T,
+// w_ij = W'(|r_ij|) r_ij / |r_ij|, positions in cell units; eta*_j is the
+// level a neighbour shows to the cell (the rule of the lattice stencil).
+template <typename real, int W>
+__device__ __forceinline__ void displaced_gradient(const real* LH, const real* LB, const real* UX, const real* UY,
+                                                   int s, real eps, real half_tau_ih, real ih, real& gx,
+                                                   real& gy) {
+    const real Hc = LH[s], bc = LB[s], ec = Hc + bc;
+    const real pxi = half_tau_ih * UX[s], pyi = half_tau_ih * UY[s];
+    real Sx = real(0), Sy = real(0), mxx = real(0), mxy = real(0), myx = real(0), myy = real(0);
+    // one row of the neighbourhood at a time keeps the live loads few
+#pragma unroll 1
+    for (int dj = -2; dj <= 2; ++dj)
+#pragma unroll
+        for (int di = -2; di <= 2; ++di) {
+            if (di == 0 && dj == 0) continue;
+            const int m = s + dj * W + di;
+            const real rx = real(di) + half_tau_ih * UX[m] - pxi;
+            const real ry = real(dj) + half_tau_ih * UY[m] - pyi;
+            const real r = Mth<real>::sqrt(rx * rx + ry * ry);
+            const real dw = bspline_dw(r);
+            const real Hm = LH[m];
+            const bool wm = Hm > eps;
+            const real em = wm ? Hm + LB[m] : LB[m];
+            const real es = rmax(bc, rmin(em, ec + (wm ? Hm : real(0))));
+            const real k = Mth<real>::div(dw, r);
+            const real wx = k * rx, wy = k * ry;
+            Sx += (es - ec) * wx;
+            Sy += (es - ec) * wy;
+            mxx += wx * rx;
+            mxy += wx * ry;
+            myx += wy * rx;
+            myy += wy * ry;
+        }
+    const real idet = Mth<real>::div(ih, mxx * myy - mxy * myx);
+    gx = (myy * Sx - mxy * Sy) * idet;
+    gy = (mxx * Sy - myx * Sx) * idet;
+}
+
 // Depth after the source rate field at cell (gx, gy) of tile coordinates
 // (x, y), from Hs (depth with the inlet source): rain adds tau*sigma; a loss
 // acts only on a cell wet at layer n and takes at most its water.  The depth
@@ -582,6 +633,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     using G = Geo<TX, TY>;
     constexpr int W = G::W;
     constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR, FLD = MODE == MODE_FIELD;
+    constexpr bool DISP = MODE == MODE_DISP;
     const int tid = threadIdx.x, nx = a.nx, ny = a.ny;
     const real eps = a.eps, half_tau = real(0.5) * tau, r = tau * a.ih;
     // normalised cubic-B-spline SPH gradient weights (smoothing length h):
@@ -739,6 +791,24 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                                           /*sgx*/ 1, /*sgy*/ 2);
             __syncthreads();
         }
+    }
+
+    // ---- PD (displaced-particle corrector only): the corrector's pressure
+    // gradient at the particle positions of t_{n+1/2} on tile + 3, from
+    // H, b and U^n of tile + 5; it replaces the lattice gradient P2 reads
+    if constexpr (DISP) {
+        constexpr int NW3 = TX + 6, NC3 = NW3 * (TY + 6);
+        const real hti = half_tau * a.ih;
+        for (int k = tid; k < NC3; k += NT) {
+            const int x = k % NW3 - 3, y = k / NW3 - 3;
+            const int s = G::at(x, y);
+            if (!(L.H[s] > eps)) continue;
+            real gx, gy;
+            displaced_gradient<real, W>(L.H, L.B, L.UX, L.UY, s, eps, hti, a.ih, gx, gy);
+            L.GX[s] = gx;
+            L.GY[s] = gy;
+        }
+        __syncthreads();
     }
 
     // ---- P2: forces at t_{n+1/2}, corrector, sources on tile + 3

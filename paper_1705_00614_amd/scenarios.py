@@ -261,6 +261,41 @@ def nest(coarse, boxes, r=4, seed=0, detail=0.5):
     return dict(coarse=c, patches=patches, r=r)
 
 
+def nest_reference(coarse, nest_dict, detail_from_patches=True):
+    """Uniform fine grid over the whole domain of a nest built by nest():
+    the fine bed is the bilinear upsampling of the original coarse bed, with
+    each patch's own fine bed (detail included) in its window; water fills to
+    the parent coarse cell's level where that cell is wet, with its unit
+    discharge; Manning n and the inlet (scaled by r) from the coarse grid.
+    The reference solution a nest approximates inside its patches."""
+    r = nest_dict["r"]
+    G = NEST_FRAME
+    bc = np.asarray(coarse["b"], dtype=np.float64)
+    ny, nx = bc.shape
+    nyf, nxf = ny * r, nx * r
+    bf = _bilinear_window(bc, r, 0, 0, nxf, nyf)
+    if detail_from_patches:
+        for p in nest_dict["patches"]:
+            fi0, fj0 = p["ci0"] * r - G, p["cj0"] * r - G
+            pb = np.asarray(p["b"], dtype=np.float64)
+            bf[fj0:fj0 + pb.shape[0], fi0:fi0 + pb.shape[1]] = pb
+    Hc = np.asarray(coarse["H0"], dtype=np.float64)
+    eta_c = np.where(Hc > 0.0, Hc + bc, -np.inf)
+    up = lambda a: np.repeat(np.repeat(a, r, axis=0), r, axis=1)
+    eta = up(eta_c)
+    Hf = np.where(np.isfinite(eta), np.maximum(eta - bf, 0.0), 0.0)
+    del eta
+    Qxf = np.where(Hf > 0.0, up(np.asarray(coarse["Qx0"], dtype=np.float64)), 0.0)
+    Qyf = np.where(Hf > 0.0, up(np.asarray(coarse["Qy0"], dtype=np.float64)), 0.0)
+    p = dict(coarse["params"])
+    if p.get("inlet"):
+        i0, j0, ni, nj = p["inlet"]
+        p["inlet"] = (i0 * r, j0 * r, ni * r, nj * r)
+    return dict(name=coarse["name"] + "-fine%d" % r, nx=nxf, ny=nyf, h=coarse["h"] / r, b=bf,
+                n_manning=up(np.asarray(coarse["n_manning"], dtype=np.float64)), solid=None,
+                H0=Hf, Qx0=Qxf, Qy0=Qyf, params=p)
+
+
 # Frame width of a patch in fine cells: one more than the reach of one step
 # of the scheme (4 cells).
 NEST_FRAME = 5
@@ -293,4 +328,5 @@ def nest_floodplain(n=2048, h=50.0, seed=1, r=4, box=512, precision=32):
         boxes.append((i - half, j, box, box))
     out = nest(sc, boxes, r=r, seed=seed + 7)
     out["coarse"]["name"] = "nest-floodplain-%d-r%d" % (n, r)
+    out["source"] = sc          # the coarse scenario before nesting (original bed)
     return out

@@ -35,7 +35,7 @@ class SweParams(ctypes.Structure):
         ("q_base", ctypes.c_double), ("q_peak", ctypes.c_double),
         ("t_peak", ctypes.c_double), ("sigma_t", ctypes.c_double),
         ("solid", ctypes.POINTER(ctypes.c_uint8)), ("H0", _dp), ("Qx0", _dp), ("Qy0", _dp),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("sph_displaced", ctypes.c_int),
     ]
 
 
@@ -66,6 +66,7 @@ EXPORTS = {
     "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
     "swe_launch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_enqueue": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
     "swe_step_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p]
                          + [ctypes.c_void_p] * 8 + [ctypes.c_double, ctypes.c_void_p]),
     "swe_set_source_field": (ctypes.c_int, [ctypes.c_void_p, _dp]),
@@ -222,6 +223,7 @@ def make_params(prm, skip_dry=True, tile=(0, 0), stream=None):
     p.t_peak = prm.get("t_peak", 0.0)
     p.sigma_t = prm.get("sigma_t", 0.0)
     p.stream = stream
+    p.sph_displaced = int(prm.get("sph_displaced", 0))
     return p
 
 
@@ -337,6 +339,10 @@ class Solver:
 
     def run_rc(self, n):
         return load().swe_run(self._h, int(n))
+
+    def enqueue(self, n):
+        """Queue n steps on the stream without waiting (swe_enqueue)."""
+        return _check(load().swe_enqueue(self._h, int(n)))
 
     def run_timed(self, n):
         ms = ctypes.c_double(0.0)
