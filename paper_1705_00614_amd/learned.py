@@ -172,13 +172,13 @@ def timing(net, fine_sc, r, sim_seconds, skip=0, corr_depth=CORR_DEPTH):
     return res
 
 
-def advance_to(g, t_end, frac=0.5):
-    """Advance a solver with its own CFL steps to t_end: graph-replayed runs
-    while the end is far (a run of n steps covers frac of what is left at the
-    current step length, so it overshoots only if the step more than doubles
-    within the run, which raises), single steps near it, and a last step held
-    to the remaining time (to within the rounding of the step length to the
-    stencil type)."""
+def advance_to(g, t_end, frac=0.5, chunk=16):
+    """Advance a solver with its own CFL steps to t_end: runs of at most
+    `chunk` steps while the end is far (a run covers at most frac of what is
+    left at the current step length, so it overshoots only if the step more
+    than doubles within `chunk` steps, which raises), single steps near it,
+    and a last step held to the remaining time (to within the rounding of the
+    step length to the stencil type)."""
     while True:
         left = t_end - g.time()
         dt = g.next_dt()
@@ -188,7 +188,7 @@ def advance_to(g, t_end, frac=0.5):
             if -left > 1e-6 * dt:
                 raise RuntimeError("advance_to: overshot %g by %g s" % (t_end, -left))
             return
-        n = int(frac * left / dt)
+        n = min(int(frac * left / dt), chunk)
         if n >= 2:
             g.run(n)
         elif dt < left:
