@@ -174,11 +174,13 @@ def timing(net, fine_sc, r, sim_seconds, skip=0, corr_depth=CORR_DEPTH):
 
 def advance_to(g, t_end, frac=0.5, chunk=16):
     """Advance a solver with its own CFL steps to t_end: runs of at most
-    `chunk` steps while the end is far (a run covers at most frac of what is
-    left at the current step length, so it overshoots only if the step more
-    than doubles within `chunk` steps, which raises), single steps near it,
-    and a last step held to the remaining time (to within the rounding of the
-    step length to the stencil type)."""
+    `chunk` steps while the end is far, single steps near it, and a last step
+    held to the remaining time (to within the rounding of the step length to
+    the stencil type).  A run never passes the end: where the solver has a
+    cap on its step (tau_max) a run is at most what is left over that cap;
+    without one it covers at most frac of what is left at the current step
+    length, and a step that grows faster than that within the run raises."""
+    cap = float(getattr(g, "tau_max", 0.0) or 0.0)
     while True:
         left = t_end - g.time()
         dt = g.next_dt()
@@ -188,7 +190,8 @@ def advance_to(g, t_end, frac=0.5, chunk=16):
             if -left > 1e-6 * dt:
                 raise RuntimeError("advance_to: overshot %g by %g s" % (t_end, -left))
             return
-        n = min(int(frac * left / dt), chunk)
+        n = int(left / max(cap, dt)) if cap > 0.0 else int(frac * left / dt)
+        n = min(n, chunk)
         if n >= 2:
             g.run(n)
         elif dt < left:

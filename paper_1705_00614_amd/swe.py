@@ -312,6 +312,8 @@ class Solver:
     def __init__(self, sc, skip_dry=True, tile=(0, 0), precision=None, stream="torch"):
         L = load()
         self.nx, self.ny, self.h = int(sc["nx"]), int(sc["ny"]), float(sc["h"])
+        # the cap on every step (0: none), which bounds how far a run can go
+        self.tau_max = float(sc["params"].get("tau_max", 0.0))
         st = current_stream() if stream == "torch" else stream
         (b, nm, p), keep = _grid_inputs(sc, skip_dry, tile, precision, st)
         self._h = L.swe_create(self.nx, self.ny, self.h, b, nm, ctypes.byref(p))
