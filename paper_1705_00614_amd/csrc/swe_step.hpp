@@ -403,6 +403,46 @@ __device__ __forceinline__ int list_entry(const Ctrl* c, const int* lists, int c
     return lists[(slot * NSEG + g) * cap + p - c->seg_off[slot][g]];
 }
 
+// Entry q of the list in `slot` in segment-interleaved order: entry 0 of
+// every segment, then entry 1 of every segment still that long, and so on.
+// Workgroup b runs on XCD b % NSEG (round-robin dispatch) and appends to
+// segment b % NSEG, so with G a multiple of NSEG, workgroup b of the next
+// step takes entry b / NSEG of the segment its own XCD filled -- a tile its
+// XCD stepped and the tiles facing it -- as long as that segment is that
+// long: neighbouring tiles, whose halos are each other's cells, stay on one
+// L2.  Any order gives the same results; only the placement changes.
+__device__ __forceinline__ int list_entry_interleaved(const Ctrl* c, const int* lists, int cap, int slot, int q) {
+    int n[NSEG], top = 0;
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g) {
+        n[g] = c->seg_off[slot][g + 1] - c->seg_off[slot][g];
+        top = max(top, n[g]);
+    }
+    // level L: the largest with sum_g min(n_g, L) <= q
+    int lo = 0, hi = top;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        int cm = 0;
+#pragma unroll
+        for (int g = 0; g < NSEG; ++g) cm += min(n[g], mid);
+        if (cm <= q) lo = mid; else hi = mid;
+    }
+    int r = q;
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g) r -= min(n[g], lo);
+    int seg = 0;
+#pragma unroll
+    for (int g = NSEG - 1; g >= 0; --g) {   // the r-th segment longer than lo
+        if (n[g] > lo) {
+            int k = 0;
+#pragma unroll
+            for (int h = 0; h < g; ++h) k += n[h] > lo;
+            if (k == r) seg = g;
+        }
+    }
+    return lists[(slot * NSEG + seg) * cap + lo];
+}
+
 // Append the candidate tiles of lanes 0..4 of one wave (cand < 0: none) of
 // scenario `sid` to segment `grp` of list `slot`: stamps de-duplicate across
 // the grid (one generation per list), one counter update per call reserves
@@ -1140,7 +1180,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
 
     for (int p = blockIdx.x; p < count; p += G) {
         const int tile = !a.skip ? p
-                         : !RING || p < nlist ? entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p))
+                         : !RING || p < nlist ? entry_tile(list_entry_interleaved(ctrl, a.lists, a.ntiles, a.slot, p))
                                               : a.ring_tiles[p - nlist];
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
