@@ -315,7 +315,8 @@ def bench_nest(args):
     cells = (w1["coarse_cells"] - w0["coarse_cells"]) + (w1["fine_cells"] - w0["fine_cells"])
     secs = kms * 1e-3
     r = nd["r"]
-    cmp = {} if args.no_extra else nest_feedback_comparison(swe, S, torch, stream, nd, N, warm, steps)
+    cmp = {} if args.no_extra else nest_feedback_comparison(swe, S, torch, stream, nd, N, warm, steps,
+                                                            (kms, q1["time"] - q0["time"]))
     grid_cells = steps * (nd["coarse"]["nx"] * nd["coarse"]["ny"] +
                           r * sum(r * p["cw"] * r * p["ch"] for p in nd["patches"]))
     _line("nested grids: cell-updates/s (coarse and patch cells of the tiles processed)", cells / secs / 1e9,
@@ -335,18 +336,21 @@ def bench_nest(args):
                     "kernel": "whole coarse step (k_step coarse and patches, frame, feedback, time step)"})
 
 
-def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps):
+def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, two_way_ms):
     """Zoom-in without feedback (one-way) against the two-way nest (Sec. 2.2:
-    less accurate but faster): time per coarse step of the one-way nest over
-    the same steps, and the depth error of both inside the patches against a
-    uniform fine grid over the whole domain (the same terrain at the patch
-    resolution, run to the same simulated time), beside the error of the
-    coarse grid alone."""
+    less accurate but faster).  Speed: ms per coarse step and simulated
+    seconds per wall second of the one-way nest over the same coarse steps
+    as the two-way window.  Accuracy: a second one-way nest advanced with its
+    own steps to the two-way nest's time (last step held to land on it); the
+    depth error of both inside the patches against a uniform fine grid over
+    the whole domain (the same terrain at the patch resolution, run to that
+    time), beside the error of the coarse grid alone."""
     from paper_1705_00614_amd import learned as LC
     r = nd["r"]
     with torch.cuda.stream(stream):
         one = swe.Nest(nd, feedback=False)
         one.run(warm)
+        t0 = one.time()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -354,34 +358,44 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps):
         one.run(steps)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms_one = e0.elapsed_time(e1) / steps
-        runs = {"two_way": two_way, "one_way": one}
-        times = {k: v.query()["time"] for k, v in runs.items()}
+        ms_one = e0.elapsed_time(e1)
+        sim_one = one.time() - t0
+        one.close()
+        t_end = two_way.time()
+        same = swe.Nest(nd, feedback=False)
+        LC.advance_to(same, t_end)
+        n_one = same.query()["steps"]
         coarse = swe.Solver(nd["coarse"])
         fine = swe.Solver(S.nest_reference(nd["source"], nd))
-        err = {k: [] for k in list(runs) + ["coarse_only"]}
-        for name in sorted(runs, key=lambda k: times[k]):
-            LC.advance_to(fine, times[name])
-            LC.advance_to(coarse, times[name])
-            Hf = fine.state()[0]
-            Hc = coarse.state()[0]
-            for k, p in enumerate(nd["patches"]):
-                win = (slice(p["cj0"] * r, (p["cj0"] + p["ch"]) * r), slice(p["ci0"] * r, (p["ci0"] + p["cw"]) * r))
-                ref = Hf[win]
-                den = max(np.abs(ref).sum(), 1e-300)
-                err[name].append(float(np.abs(runs[name].patch_state(k)[0] - ref).sum() / den))
-                if name == "two_way":
-                    cwin = (slice(p["cj0"], p["cj0"] + p["ch"]), slice(p["ci0"], p["ci0"] + p["cw"]))
-                    up = np.kron(Hc[cwin], np.ones((r, r)))
-                    err["coarse_only"].append(float(np.abs(up - ref).sum() / den))
+        LC.advance_to(fine, t_end)
+        LC.advance_to(coarse, t_end)
+        Hf = fine.state()[0]
+        Hc = coarse.state()[0]
+        err = {"two_way": [], "one_way": [], "coarse_only": []}
+        for k, p in enumerate(nd["patches"]):
+            win = (slice(p["cj0"] * r, (p["cj0"] + p["ch"]) * r), slice(p["ci0"] * r, (p["ci0"] + p["cw"]) * r))
+            ref = Hf[win]
+            den = max(np.abs(ref).sum(), 1e-300)
+            err["two_way"].append(float(np.abs(two_way.patch_state(k)[0] - ref).sum() / den))
+            err["one_way"].append(float(np.abs(same.patch_state(k)[0] - ref).sum() / den))
+            cwin = (slice(p["cj0"], p["cj0"] + p["ch"]), slice(p["ci0"], p["ci0"] + p["cw"]))
+            up = np.kron(Hc[cwin], np.ones((r, r)))
+            err["coarse_only"].append(float(np.abs(up - ref).sum() / den))
+        n_two = two_way.query()["steps"]
         fine.close()
         coarse.close()
-        one.close()
-    return {"one_way": {"ms_per_coarse_step": ms_one, "depth_error_in_patches_vs_uniform_fine": err["one_way"],
-                        "simulated_seconds": times["one_way"]},
+        same.close()
+    return {"one_way": {"ms_per_coarse_step": ms_one / steps,
+                        "simulated_seconds_per_wall_second": sim_one / (ms_one * 1e-3),
+                        "window_simulated_seconds": sim_one,
+                        "coarse_steps_to_the_comparison_time": n_one,
+                        "depth_error_in_patches_vs_uniform_fine": err["one_way"]},
+            "two_way_simulated_seconds_per_wall_second": two_way_ms[1] / (two_way_ms[0] * 1e-3),
+            "two_way_coarse_steps_to_the_comparison_time": n_two,
             "two_way_depth_error_in_patches_vs_uniform_fine": err["two_way"],
             "coarse_only_depth_error_in_patches_vs_uniform_fine": err["coarse_only"],
-            "uniform_fine_reference": "%dx%d at %g m, same terrain, run to each nest's time"
+            "comparison_time_s": t_end,
+            "uniform_fine_reference": "%dx%d at %g m, same terrain, run to the comparison time"
                                       % (nd["coarse"]["nx"] * r, nd["coarse"]["ny"] * r, nd["coarse"]["h"] / r)}
 
 

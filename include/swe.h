@@ -166,6 +166,16 @@ double swe_field_volume(swe_t* s);
  * count, or SWE_EINVAL for a NULL handle. */
 int    swe_launch_grid(swe_t* s);
 
+/* Set the workgroups of the following step launches to `grid`, from 8 up to
+ * the default count swe_launch_grid reports for a new handle.  A list no
+ * longer than the grid gives each workgroup one tile or none (first the
+ * entry its own XCD appended, then the overflow of longer segments); a
+ * longer list is strided over the workgroups.  The results do not depend on
+ * the grid: it places the work (tests and measurements of that placement).
+ * Waits for queued steps.  0, SWE_EINVAL (NULL handle, grid out of range, a
+ * grid of a nest) or SWE_EHIP. */
+int    swe_set_launch_grid(swe_t* s, int grid);
+
 /* Tiles the next step will process (row-major tile indices, unordered),
  * at most cap entries; returns the count or SWE_E*. */
 int    swe_active_tiles(swe_t* s, int* out, int cap);

@@ -147,7 +147,7 @@ const Launcher* find_launcher(int precision, int tx, int ty, int limiter) {
 
 struct swe_s {
     int nx = 0, ny = 0, precision = 32, rsize = 4;
-    int ntx = 0, nty = 0, ntiles = 0, grid = 0;
+    int ntx = 0, nty = 0, ntiles = 0, grid = 0, grid_max = 0;   // step launch grid, its default
     double h = 0.0;
     swe_params p{};
     const Launcher* L = nullptr;
@@ -619,6 +619,7 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
     s->grid = cus * occ;
     if (s->grid < 8) s->grid = 8;
     if (!p->skip_dry && s->grid > s->ntiles) s->grid = s->ntiles;
+    s->grid_max = s->grid;
     CK(hipMalloc(&s->wg_speed, sizeof(double) * s->grid));
     CK(hipMalloc((void**)&s->wg_cells, sizeof(long long) * s->grid));
 
@@ -879,6 +880,20 @@ double swe_field_volume(swe_t* s) {
 int swe_launch_grid(swe_t* s) {
     if (!s) { set_err("swe_launch_grid: NULL handle"); return SWE_EINVAL; }
     return s->grid;
+}
+
+int swe_set_launch_grid(swe_t* s, int grid) {
+    if (!s || grid < 8 || grid > s->grid_max) {
+        set_err("swe_set_launch_grid: the grid must be a handle's, from 8 to its default launch grid");
+        return SWE_EINVAL;
+    }
+    if (s->ntap > 0) { set_err("swe_set_launch_grid: the nest launches its grids"); return SWE_EINVAL; }
+    Ctrl c;
+    int rc = sync_ctrl(s, &c);   // queued launches keep the grid they were queued with
+    if (rc) return rc;
+    drop_graph(s);
+    s->grid = grid;
+    return 0;
 }
 
 int swe_active_tiles(swe_t* s, int* out, int cap) {

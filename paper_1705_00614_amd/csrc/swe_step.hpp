@@ -403,44 +403,33 @@ __device__ __forceinline__ int list_entry(const Ctrl* c, const int* lists, int c
     return lists[(slot * NSEG + g) * cap + p - c->seg_off[slot][g]];
 }
 
-// Entry q of the list in `slot` in segment-interleaved order: entry 0 of
-// every segment, then entry 1 of every segment still that long, and so on.
-// Workgroup b runs on XCD b % NSEG (round-robin dispatch) and appends to
-// segment b % NSEG, so with G a multiple of NSEG, workgroup b of the next
-// step takes entry b / NSEG of the segment its own XCD filled -- a tile its
-// XCD stepped and the tiles facing it -- as long as that segment is that
-// long: neighbouring tiles, whose halos are each other's cells, stay on one
-// L2.  Any order gives the same results; only the placement changes.
-__device__ __forceinline__ int list_entry_interleaved(const Ctrl* c, const int* lists, int cap, int slot, int q) {
-    int n[NSEG], top = 0;
+// The list entry of workgroup b when the list in `slot` is no longer than
+// the grid G, each workgroup then stepping at most one tile (own-segment
+// order): entry b / NSEG of segment b % NSEG -- the segment its own XCD
+// filled (workgroup b runs on XCD b % NSEG under round-robin dispatch), a
+// tile that XCD stepped or one facing it -- when that segment is that long;
+// the entries of a longer segment beyond the G / NSEG its workgroups take go,
+// in segment order, to the workgroups left without one, by rank.  Every
+// entry goes to exactly one workgroup (the list has at most G entries).
+// Returns the entry, or -1 when workgroup b has none.  The order only
+// places the tiles: the results do not depend on it.
+__device__ __forceinline__ int list_entry_own(const Ctrl* c, const int* lists, int cap, int slot, int b, int G) {
+    int n[NSEG];
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g) n[g] = c->seg_off[slot][g + 1] - c->seg_off[slot][g];
+    const int g0 = b % NSEG, i0 = b / NSEG;
+    if (i0 < n[g0]) return lists[(slot * NSEG + g0) * cap + i0];
+    int rank = i0 - n[g0];   // among the workgroups left without an entry
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g)
+        if (g < g0) rank += max(0, (G - g + NSEG - 1) / NSEG - n[g]);
 #pragma unroll
     for (int g = 0; g < NSEG; ++g) {
-        n[g] = c->seg_off[slot][g + 1] - c->seg_off[slot][g];
-        top = max(top, n[g]);
+        const int taken = (G - g + NSEG - 1) / NSEG, over = max(0, n[g] - taken);
+        if (rank < over) return lists[(slot * NSEG + g) * cap + taken + rank];
+        rank -= over;
     }
-    // level L: the largest with sum_g min(n_g, L) <= q
-    int lo = 0, hi = top;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        int cm = 0;
-#pragma unroll
-        for (int g = 0; g < NSEG; ++g) cm += min(n[g], mid);
-        if (cm <= q) lo = mid; else hi = mid;
-    }
-    int r = q;
-#pragma unroll
-    for (int g = 0; g < NSEG; ++g) r -= min(n[g], lo);
-    int seg = 0;
-#pragma unroll
-    for (int g = NSEG - 1; g >= 0; --g) {   // the r-th segment longer than lo
-        if (n[g] > lo) {
-            int k = 0;
-#pragma unroll
-            for (int h = 0; h < g; ++h) k += n[h] > lo;
-            if (k == r) seg = g;
-        }
-    }
-    return lists[(slot * NSEG + seg) * cap + lo];
+    return -1;
 }
 
 // Append the candidate tiles of lanes 0..4 of one wave (cand < 0: none) of
@@ -1161,27 +1150,44 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     __shared__ int s_last;
 
     Ctrl* const ctrl = a.ctrl;
+    // The workgroup's own-segment entry is read beside the list's counts
+    // (one memory round trip before the tile load, not two); it is used when
+    // the list is no longer than the grid and its segment is long enough.
+    constexpr bool RING = MODE == MODE_TAP;
+    const int b0 = blockIdx.x;
+    const bool spec_in = !RING && a.skip && b0 / NSEG < a.ntiles;
+    const int spec = spec_in ? a.lists[(a.slot * NSEG + b0 % NSEG) * a.ntiles + b0 / NSEG] : 0;
     if (ctrl->err_gate) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int G = gridDim.x, grp = blockIdx.x % NSEG;
     // only the patches of a nest (tapping grids) carry ring tiles; the other
     // variants compile without them (no registers held for their bounds)
-    constexpr bool RING = MODE == MODE_TAP;
     const int nlist = a.skip ? ctrl->seg_off[a.slot][NSEG] : a.ntiles;
     const int count = nlist + (RING && a.skip ? a.nring : 0);   // list entries, then the ring tiles
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
     const int gen = (int)ctrl->step + 2;
     const int nx = a.nx, ny = a.ny;
+    // a list no longer than the grid: one tile or none per workgroup, in
+    // own-segment order; a longer one: plain order, strided by the grid
+    const bool own = !RING && a.skip && count <= G;
+    int first = -1;
+    if (own) {
+        const int g0 = b0 % NSEG, n0 = ctrl->seg_off[a.slot][g0 + 1] - ctrl->seg_off[a.slot][g0];
+        const int e = spec_in && b0 / NSEG < n0 ? spec : list_entry_own(ctrl, a.lists, a.ntiles, a.slot, b0, G);
+        first = e < 0 ? -1 : entry_tile(e);
+    }
+    const int npos = own ? (first >= 0 ? b0 + 1 : 0) : count;
 
     real vmax = real(0);
     bool bad = false;
     long long ncells = 0;
 
-    for (int p = blockIdx.x; p < count; p += G) {
+    for (int p = blockIdx.x; p < npos; p += G) {
         const int tile = !a.skip ? p
-                         : !RING || p < nlist ? entry_tile(list_entry_interleaved(ctrl, a.lists, a.ntiles, a.slot, p))
-                                              : a.ring_tiles[p - nlist];
+                         : first >= 0 ? first
+                         : RING && p >= nlist ? a.ring_tiles[p - nlist]
+                                              : entry_tile(list_entry(ctrl, a.lists, a.ntiles, a.slot, p));
         const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
         ncells += (long long)min(TX, nx - tx0) * min(TY, ny - ty0);
         const bool edge = tx0 < HALO || ty0 < HALO || tx0 + TX + HALO > nx || ty0 + TY + HALO > ny;
@@ -1303,7 +1309,9 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         c.inflow += c.dV;
         c.last_tau = tau_done;
         c.step += 1;
-        c.tiles += count;
+        // tiles of the step: the list's (read again: the step does not
+        // change the counts of the list it runs) and the ring tiles
+        c.tiles += a.skip ? ctrl->seg_off[a.slot][NSEG] + (RING ? a.nring : 0) : a.ntiles;
         c.cells += cells;
         next_step_scalars(a, &c, S);
         if (c.err) c.err_gate = c.err;

@@ -173,7 +173,7 @@ def timing(net, fine_sc, r, sim_seconds, skip=0, corr_depth=CORR_DEPTH):
 
 
 def advance_to(g, t_end, frac=0.5, chunk=16):
-    """Advance a solver with its own CFL steps to t_end: runs of at most
+    """Advance a solver (or a nest, by coarse steps) with its own CFL steps to t_end: runs of at most
     `chunk` steps while the end is far, single steps near it, and a last step
     held to the remaining time (to within the rounding of the step length to
     the stencil type).  A run never passes the end: where the solver has a
@@ -190,7 +190,8 @@ def advance_to(g, t_end, frac=0.5, chunk=16):
             if -left > 1e-6 * dt:
                 raise RuntimeError("advance_to: overshot %g by %g s" % (t_end, -left))
             return
-        n = int(left / max(cap, dt)) if cap > 0.0 else int(frac * left / dt)
+        # (a step may exceed the cap by the rounding of its length to FP32)
+        n = int(left / (max(cap, dt) * (1.0 + 1e-6))) if cap > 0.0 else int(frac * left / dt)
         n = min(n, chunk)
         if n >= 2:
             g.run(n)

@@ -66,6 +66,7 @@ EXPORTS = {
     "swe_inflow": (ctypes.c_double, [ctypes.c_void_p]),
     "swe_steps": (ctypes.c_long, [ctypes.c_void_p]),
     "swe_launch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "swe_set_launch_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "swe_enqueue": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_long]),
     "swe_step_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p]
                          + [ctypes.c_void_p] * 8 + [ctypes.c_double, ctypes.c_void_p]),
@@ -405,11 +406,16 @@ class Solver:
         return load().swe_field_volume(self._h)
 
     def launch_grid(self):
-        """Workgroups of one step launch (the tile list is strided over them)."""
+        """Workgroups of one step launch."""
         n = load().swe_launch_grid(self._h)
         if n < 0:
             raise SweError(n, last_error())
         return n
+
+    def set_launch_grid(self, grid):
+        """Workgroups of the following step launches, 8 up to the default
+        (swe_set_launch_grid): places the tiles, changes no result."""
+        return _check(load().swe_set_launch_grid(self._h, int(grid)))
 
     def active_tiles(self):
         n = self.work()["ntiles"]
@@ -530,6 +536,8 @@ class Nest:
         p = make_params(pr, skip_dry, (0, 0), st)
         self.shape = (int(sc["ny"]), int(sc["nx"]))
         self.r = r
+        # the cap on every coarse step (0: none), which bounds how far a run can go
+        self.tau_max = float(pr.get("tau_max", 0.0))
         b = _f64(sc["b"], self.shape)
         nm = _f64(sc.get("n_manning"), self.shape)
         H0, Qx0, Qy0 = (_f64(sc.get(q), self.shape) for q in ("H0", "Qx0", "Qy0"))
@@ -584,6 +592,16 @@ class Nest:
     def hold_dt(self, tau_c):
         """Hold the coarse step at tau_c (substeps tau_c / r); 0 returns to the CFL rule."""
         _check(load().swe_nest_hold_dt(self._h, float(tau_c)))
+
+    def time(self):
+        return self.query()["time"]
+
+    def next_dt(self):
+        """Length of the next coarse step."""
+        return self.query()["dt_coarse"]
+
+    def step(self):
+        return self.run(1)
 
     def query(self):
         v = [ctypes.c_double() for _ in range(6)]
