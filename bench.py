@@ -52,7 +52,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: floodplain and wet 20, nest 5000, ensemble 2000)")
+                    help="timed steps (default: floodplain 10000, the whole flood of the workload; wet 20; "
+                         "nest 5000; ensemble 2000)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 5, ensemble 20)")
     ap.add_argument("--workload", choices=["floodplain", "wet", "nest", "ensemble", "learned"],
                     default="floodplain")
@@ -73,7 +74,8 @@ def parse():
     ap.add_argument("--per-launch", action="store_true",
                     help="time each step kernel with its own HIP event pair instead of graph replays")
     a = ap.parse_args()
-    a.steps = a.steps if a.steps is not None else {"nest": 5000, "ensemble": 2000}.get(a.workload, 20)
+    a.steps = a.steps if a.steps is not None else {"floodplain": 10000, "nest": 5000,
+                                                    "ensemble": 2000}.get(a.workload, 20)
     a.warmup = a.warmup if a.warmup is not None else {"ensemble": 20}.get(a.workload, 5)
     return a
 
@@ -340,11 +342,13 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
     """Zoom-in without feedback (one-way) against the two-way nest (Sec. 2.2:
     less accurate but faster).  Speed: ms per coarse step and simulated
     seconds per wall second of the one-way nest over the same coarse steps
-    as the two-way window.  Accuracy: a second one-way nest advanced with its
-    own steps to the two-way nest's time (last step held to land on it); the
-    depth error of both inside the patches against a uniform fine grid over
-    the whole domain (the same terrain at the patch resolution, run to that
-    time), beside the error of the coarse grid alone."""
+    as the two-way window.  Accuracy: at the time the one-way nest reaches
+    at the end of that window (past the hydrograph's peak, the flood through
+    the patches), the two-way nest advanced there with its own steps (the
+    last held to land on it); the depth error of both inside the patches
+    against a uniform fine grid over the whole domain (the same terrain at
+    the patch resolution, run to that time), beside the error of the coarse
+    grid alone."""
     from paper_1705_00614_amd import learned as LC
     r = nd["r"]
     with torch.cuda.stream(stream):
@@ -359,12 +363,11 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
         e1.record(stream)
         torch.cuda.synchronize()
         ms_one = e0.elapsed_time(e1)
-        sim_one = one.time() - t0
-        one.close()
-        t_end = two_way.time()
-        same = swe.Nest(nd, feedback=False)
-        LC.advance_to(same, t_end)
-        n_one = same.query()["steps"]
+        t_end = one.time()
+        sim_one = t_end - t0
+        n_one = one.query()["steps"]
+        LC.advance_to(two_way, t_end)
+        n_two = two_way.query()["steps"]
         coarse = swe.Solver(nd["coarse"])
         fine = swe.Solver(S.nest_reference(nd["source"], nd))
         LC.advance_to(fine, t_end)
@@ -377,14 +380,16 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
             ref = Hf[win]
             den = max(np.abs(ref).sum(), 1e-300)
             err["two_way"].append(float(np.abs(two_way.patch_state(k)[0] - ref).sum() / den))
-            err["one_way"].append(float(np.abs(same.patch_state(k)[0] - ref).sum() / den))
+            err["one_way"].append(float(np.abs(one.patch_state(k)[0] - ref).sum() / den))
             cwin = (slice(p["cj0"], p["cj0"] + p["ch"]), slice(p["ci0"], p["ci0"] + p["cw"]))
             up = np.kron(Hc[cwin], np.ones((r, r)))
             err["coarse_only"].append(float(np.abs(up - ref).sum() / den))
-        n_two = two_way.query()["steps"]
+        wet_frac = [float((Hf[(slice(p["cj0"] * r, (p["cj0"] + p["ch"]) * r),
+                               slice(p["ci0"] * r, (p["ci0"] + p["cw"]) * r))] > 1e-4).mean())
+                    for p in nd["patches"]]
         fine.close()
         coarse.close()
-        same.close()
+        one.close()
     return {"one_way": {"ms_per_coarse_step": ms_one / steps,
                         "simulated_seconds_per_wall_second": sim_one / (ms_one * 1e-3),
                         "window_simulated_seconds": sim_one,
@@ -395,6 +400,7 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
             "two_way_depth_error_in_patches_vs_uniform_fine": err["two_way"],
             "coarse_only_depth_error_in_patches_vs_uniform_fine": err["coarse_only"],
             "comparison_time_s": t_end,
+            "wet_fraction_of_the_patches_at_that_time": wet_frac,
             "uniform_fine_reference": "%dx%d at %g m, same terrain, run to the comparison time"
                                       % (nd["coarse"]["nx"] * r, nd["coarse"]["ny"] * r, nd["coarse"]["h"] / r)}
 

@@ -446,7 +446,9 @@ __device__ __forceinline__ void append_tiles(int cand, int sid, int tile_base, i
     int base = 0;
     if (lane == 0) base = atomicAdd(&hot[hot_seg(slot, grp)], n);
     base = __shfl(base, 0, 64);
-    if (ok) lists[(slot * NSEG + grp) * cap + base + __popcll(m & ((1ull << lane) - 1ull))] = pack_entry(sid, cand);
+    // set bits of the ballot below this lane (no 64-bit lane mask held live)
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (ok) lists[(slot * NSEG + grp) * cap + base + below] = pack_entry(sid, cand);
 }
 
 // Next-list bookkeeping of the tile being stepped (grids that skip dry
