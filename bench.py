@@ -366,11 +366,16 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
         t_end = one.time()
         sim_one = t_end - t0
         n_one = one.query()["steps"]
+        print("nest: one-way window done, t = %.1f s; advancing the two-way nest" % t_end, file=sys.stderr,
+              flush=True)
         LC.advance_to(two_way, t_end)
         n_two = two_way.query()["steps"]
+        print("nest: two-way at t after %d coarse steps; uniform fine reference" % n_two, file=sys.stderr,
+              flush=True)
         coarse = swe.Solver(nd["coarse"])
         fine = swe.Solver(S.nest_reference(nd["source"], nd))
         LC.advance_to(fine, t_end)
+        print("nest: uniform fine reference at t", file=sys.stderr, flush=True)
         LC.advance_to(coarse, t_end)
         Hf = fine.state()[0]
         Hc = coarse.state()[0]
