@@ -24,9 +24,13 @@ here is coarse-first subcycling with conservative flux matching:
      own outer edge.  Before
      every substep the frame is refilled from the covering coarse cell,
      piecewise constant in space and linear in time between coarse layers n
-     and n+1: the coarse depth H_c and Q are interpolated, the fine depth is
-     max(0, H_c + b_c - b_fine) and Q is copied where H_c > eps, else the
-     fine cell is dry; the fluxes on the boundary faces of the patch
+     and n+1: the coarse depth H_c and Q_c are interpolated, the fine depth
+     is H_f = max(0, H_c + b_c - b_fine) and the fine discharge carries the
+     coarse velocity, Q_f = H_f (Q_c / H_c), where H_c > eps, else the fine
+     cell is dry (copying Q_c itself would put the momentum of the coarse
+     column into a fine cell on a high spot of the fine bed: a film moving
+     at tens of m/s, whose friction term in U_p then sets the step of the
+     whole nest); the fluxes on the boundary faces of the patch
      interior are accumulated (times tau_f);
   4. restriction: covered coarse cells take the mean of their r x r fine
      cells (H, Qx, Qy);
@@ -119,9 +123,12 @@ class OracleNest:
         Hc = (1.0 - theta) * Hc0[CJ, CI] + theta * Hc1[CJ, CI]
         eta = Hc + self.bc[CJ, CI]
         wet = Hc > self.eps
-        qx = np.where(wet, (1.0 - theta) * Qxc0[CJ, CI] + theta * Qxc1[CJ, CI], 0.0)
-        qy = np.where(wet, (1.0 - theta) * Qyc0[CJ, CI] + theta * Qyc1[CJ, CI], 0.0)
+        Hs = np.where(wet, Hc, 1.0)
         Hf = np.where(wet, np.maximum(0.0, eta - P["bf"]), 0.0)
+        # the coarse velocity (interpolated discharge over interpolated
+        # depth) carried by the fine depth
+        qx = np.where(wet, Hf * (((1.0 - theta) * Qxc0[CJ, CI] + theta * Qxc1[CJ, CI]) / Hs), 0.0)
+        qy = np.where(wet, Hf * (((1.0 - theta) * Qyc0[CJ, CI] + theta * Qyc1[CJ, CI]) / Hs), 0.0)
         frame = np.ones_like(H, dtype=bool)
         frame[G:G + P["nyf"], G:G + P["nxf"]] = False
         H = np.where(frame, Hf, H)

@@ -13,8 +13,9 @@
 //            its interior, one more than the reach of one step) from the
 //            covering coarse cell, linear in time between the coarse layers
 //            n and n+1 (depth and discharge interpolated; fine depth
-//            max(0, H_c + b_c - b_fine) where the coarse cell is wet, else
-//            dry); then one ordinary step of every patch with tau_c / r,
+//            H_f = max(0, H_c + b_c - b_fine) and discharge H_f Q_c / H_c
+//            where the coarse cell is wet, else dry); then one ordinary
+//            step of every patch with tau_c / r,
 //            adding tau_f * flux of its interior boundary faces into its taps
 //   feedback k_feedback: each covered coarse cell takes the mean of its
 //            r x r fine cells; each uncovered cell next to a covered box
@@ -109,9 +110,12 @@ __global__ void k_frame(NestArgs<real> n, int pf, int pc, real theta) {
     const real Hm = u * n.Hc[pc][gc] + theta * n.Hc[pc ^ 1][gc];
     const bool w = Hm > n.eps;
     const real eta = Hm + n.bc[gc];
-    d.Hf[pf][gf] = w ? rmax(real(0), eta - d.bf[gf]) : real(0);
-    d.Qxf[pf][gf] = w ? u * n.Qxc[pc][gc] + theta * n.Qxc[pc ^ 1][gc] : real(0);
-    d.Qyf[pf][gf] = w ? u * n.Qyc[pc][gc] + theta * n.Qyc[pc ^ 1][gc] : real(0);
+    const real Hf = w ? rmax(real(0), eta - d.bf[gf]) : real(0);
+    d.Hf[pf][gf] = Hf;
+    // the coarse velocity carried by the fine depth (not the coarse
+    // discharge, which on a high spot of the fine bed would be a fast film)
+    d.Qxf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qxc[pc][gc] + theta * n.Qxc[pc ^ 1][gc], Hm) : real(0);
+    d.Qyf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qyc[pc][gc] + theta * n.Qyc[pc ^ 1][gc], Hm) : real(0);
 }
 
 // Restriction of the fine layer (patch buffers pf) into the covered coarse

@@ -223,8 +223,8 @@ def nest(coarse, boxes, r=4, seed=0, detail=0.5):
     the parent coarse cell's level where that cell is wet (still water); the
     covered coarse cells take the mean fine depth.  A patch carries the
     extended fine grid (frame of NEST_FRAME fine cells round the covered
-    area).  Fine cells take the unit discharge of their parent where they are
-    wet; covered coarse cells take the mean fine discharge."""
+    area).  Fine cells take their parent's velocity at their own depth where
+    they are wet; covered coarse cells take the mean fine discharge."""
     G = NEST_FRAME
     c = dict(coarse)
     bc = np.array(coarse["b"], dtype=np.float64)
@@ -248,8 +248,9 @@ def nest(coarse, boxes, r=4, seed=0, detail=0.5):
         nmf = nmc[PJ, PI].copy()
         eta = eta_c[PJ, PI]
         Hf = np.where(np.isfinite(eta), np.maximum(eta - bf, 0.0), 0.0)
-        Qxf = np.where(Hf > 0.0, Qxc[PJ, PI], 0.0)
-        Qyf = np.where(Hf > 0.0, Qyc[PJ, PI], 0.0)
+        Hp = np.where(Hc[PJ, PI] > 0.0, Hc[PJ, PI], 1.0)
+        Qxf = np.where(Hf > 0.0, Hf * (Qxc[PJ, PI] / Hp), 0.0)
+        Qyf = np.where(Hf > 0.0, Hf * (Qyc[PJ, PI] / Hp), 0.0)
         inner = (slice(G, G + ch * r), slice(G, G + cw * r))
         cov = (slice(cj0, cj0 + ch), slice(ci0, ci0 + cw))
         for fine_f, coarse_f in ((bf, bc), (Hf, Hc), (Qxf, Qxc), (Qyf, Qyc)):
@@ -265,8 +266,8 @@ def nest_reference(coarse, nest_dict, detail_from_patches=True):
     """Uniform fine grid over the whole domain of a nest built by nest():
     the fine bed is the bilinear upsampling of the original coarse bed, with
     each patch's own fine bed (detail included) in its window; water fills to
-    the parent coarse cell's level where that cell is wet, with its unit
-    discharge; Manning n and the inlet (scaled by r) from the coarse grid.
+    the parent coarse cell's level where that cell is wet, with its
+    velocity; Manning n and the inlet (scaled by r) from the coarse grid.
     The reference solution a nest approximates inside its patches."""
     r = nest_dict["r"]
     G = NEST_FRAME
@@ -285,8 +286,10 @@ def nest_reference(coarse, nest_dict, detail_from_patches=True):
     eta = up(eta_c)
     Hf = np.where(np.isfinite(eta), np.maximum(eta - bf, 0.0), 0.0)
     del eta
-    Qxf = np.where(Hf > 0.0, up(np.asarray(coarse["Qx0"], dtype=np.float64)), 0.0)
-    Qyf = np.where(Hf > 0.0, up(np.asarray(coarse["Qy0"], dtype=np.float64)), 0.0)
+    Hp = up(np.where(Hc > 0.0, Hc, 1.0))
+    Qxf = np.where(Hf > 0.0, Hf * (up(np.asarray(coarse["Qx0"], dtype=np.float64)) / Hp), 0.0)
+    Qyf = np.where(Hf > 0.0, Hf * (up(np.asarray(coarse["Qy0"], dtype=np.float64)) / Hp), 0.0)
+    del Hp
     p = dict(coarse["params"])
     if p.get("inlet"):
         i0, j0, ni, nj = p["inlet"]

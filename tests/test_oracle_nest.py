@@ -3,6 +3,7 @@ and Sec. 5), all on the CPU.  The coupling reading (coarse-first
 subcycling, frame from the coarse layers, restriction by the mean, reflux of
 the face-flux mismatch) is checked against what it must satisfy:
   - r = 1 with the same bed is the single grid (frame, indices, restriction);
+  - the frame carries the coarse velocity at the fine depth;
   - volume is conserved to rounding on a wet domain with inflow (reflux
     signs and targets), and dropping the reflux breaks that;
   - covered coarse cells equal the mean of their fine cells (nothing but
@@ -52,6 +53,35 @@ def test_r1_same_bed_is_the_single_grid():
     # the patch interior is the same cells
     Hp = N.patch_state(0)[0]
     assert np.abs(Hp - a[0][8:20, 9:23]).max() <= 1e-11 * np.abs(a[0]).max()
+
+
+def test_frame_carries_the_coarse_velocity():
+    """The frame of a patch takes the covering coarse cell's velocity at the
+    fine depth H_f = max(0, H_c + b_c - b_f): on a high spot of the fine bed
+    (a film of 1 cm under 2 m of coarse water) the discharge is 1 cm times
+    the coarse velocity, not the coarse column's discharge, which would move
+    that film at 200 times the flow's speed."""
+    n, r = 24, 4
+    sc = _flat(n, 10.0, 2.0)
+    ux, uy = 0.5, -0.2
+    sc["Qx0"] = np.full((n, n), 2.0 * ux)
+    sc["Qy0"] = np.full((n, n), 2.0 * uy)
+    nest = S.nest(sc, [(8, 8, 6, 6)], r=r, detail=0.0)
+    P = nest["patches"][0]
+    bf = np.zeros_like(P["b"])
+    bf[1, 7] = 1.99           # frame rows are 0..4 and the last 5
+    bf[3, 2] = 2.5            # above the coarse level: dry
+    P["b"] = bf
+    N = OracleNest(nest["coarse"], nest["patches"], r=r)
+    H0, Qx0, Qy0 = sc["H0"], sc["Qx0"], sc["Qy0"]
+    H, Qx, Qy = N._frame(N.P[0], H0, Qx0, Qy0, H0, Qx0, Qy0, 0.0)
+    G = 5
+    frame = np.ones_like(H, dtype=bool)
+    frame[G:-G, G:-G] = False
+    assert abs(H[1, 7] - 0.01) < 1e-12 and abs(Qx[1, 7] - 0.01 * ux) < 1e-14 and abs(Qy[1, 7] - 0.01 * uy) < 1e-14
+    assert H[3, 2] == 0.0 and Qx[3, 2] == 0.0 and Qy[3, 2] == 0.0
+    wet = frame & (H > 0)
+    assert np.abs(Qx[wet] / H[wet] - ux).max() < 1e-14 and np.abs(Qy[wet] / H[wet] - uy).max() < 1e-14
 
 
 def _wet_nest(r=4, feedback=True, reflux=True):
