@@ -186,6 +186,34 @@ __device__ __forceinline__ double rabs(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ bool finite(float a) { return rabs(a) <= 3.40282347e38f; }
 __device__ __forceinline__ bool finite(double a) { return rabs(a) <= 1.7976931348623157e308; }
 
+// Stochastic rounding of the depth update (FP32 state).  Round to nearest
+// drops every change below half an ulp: a deep cell losing a trickle to a
+// shallow neighbour keeps its depth while the neighbour gains, so on a
+// rising flood the stored volume creeps up step after step (6e-6 of the
+// volume over a 10 000-step 4096^2 flood).  Rounding s = fl(a + d) to its
+// neighbour toward the exact remainder e = (a + d) - s (two-sum) with
+// probability |e| / gap makes the stored depth unbiased, so the volume error
+// is a random walk at the rounding level.  The decision is a hash of the
+// cell's global index and the step: the same wherever the cell is computed
+// (its own tile, a neighbour's ring, a batch, any tile shape).
+__device__ __forceinline__ unsigned cell_hash(unsigned cell, unsigned gen) {
+    // MurmurHash3's 32-bit finalizer (Appleby) of the cell index mixed with
+    // the step by the golden-ratio constant
+    unsigned h = cell ^ (gen * 0x9E3779B9u);
+    h ^= h >> 16; h *= 0x85EBCA6Bu; h ^= h >> 13; h *= 0xC2B2AE35u; h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ float round_stochastic(float a, float d, float s, unsigned h) {
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (d - bb);
+    if (!(e != 0.0f)) return s;
+    const unsigned bits = __float_as_uint(s);
+    const bool away = (e > 0.0f) == (s > 0.0f);
+    const float nb = s == 0.0f ? (e > 0.0f ? 1.4e-45f : -1.4e-45f) : __uint_as_float(away ? bits + 1u : bits - 1u);
+    const float p = e * __builtin_amdgcn_rcpf(nb - s);   // in [0, 1]; the gap nb - s is exact
+    return (float)(h >> 8) * 5.9604645e-8f < p ? nb : s;
+}
+
 // Reflect a global index into [0, n) about the end faces; flips counts the
 // reflections (odd: the velocity component normal to that wall changes sign).
 __device__ __forceinline__ int mirror(int i, int n, int& flips) {
@@ -1048,7 +1076,10 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real dxH = L.HX[s] - L.HX[s + 1];
                 const real dxQx = L.HY[s] - L.HY[s + 1];
                 const real dxQy = L.H[s] - L.H[s + 1];
-                const real Hn = cl[i + 2].H + r * (dxH + (FH[i] - FH[i + 1]));
+                const real Ht = cl[i + 2].H, dH = r * (dxH + (FH[i] - FH[i + 1]));
+                real Hn = Ht + dH;
+                if constexpr (F32)
+                    Hn = round_stochastic(Ht, dH, Hn, cell_hash((unsigned)((ty0 + y) * nx + tx0 + x), (unsigned)lx.gen));
                 const real qx = L.GX[s] + r * (dxQx + (Ft[i] - Ft[i + 1]));
                 const real qy = L.GY[s] + r * (dxQy + (Fn[i] - Fn[i + 1]));
                 const real Hc = rmax(Hn, real(0));
