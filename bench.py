@@ -351,6 +351,15 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
     grid alone."""
     from paper_1705_00614_amd import learned as LC
     r = nd["r"]
+    last = [time.perf_counter()]
+
+    def progress(name):
+        def report(t):
+            if time.perf_counter() - last[0] > 20.0:
+                last[0] = time.perf_counter()
+                print("nest: %s at t = %.1f s" % (name, t), file=sys.stderr, flush=True)
+        return report
+
     with torch.cuda.stream(stream):
         one = swe.Nest(nd, feedback=False)
         one.run(warm)
@@ -368,15 +377,15 @@ def nest_feedback_comparison(swe, S, torch, stream, nd, two_way, warm, steps, tw
         n_one = one.query()["steps"]
         print("nest: one-way window done, t = %.1f s; advancing the two-way nest" % t_end, file=sys.stderr,
               flush=True)
-        LC.advance_to(two_way, t_end)
+        LC.advance_to(two_way, t_end, on_run=progress("two-way nest"))
         n_two = two_way.query()["steps"]
         print("nest: two-way at t after %d coarse steps; uniform fine reference" % n_two, file=sys.stderr,
               flush=True)
         coarse = swe.Solver(nd["coarse"])
         fine = swe.Solver(S.nest_reference(nd["source"], nd))
-        LC.advance_to(fine, t_end)
+        LC.advance_to(fine, t_end, on_run=progress("uniform fine reference"))
         print("nest: uniform fine reference at t", file=sys.stderr, flush=True)
-        LC.advance_to(coarse, t_end)
+        LC.advance_to(coarse, t_end, on_run=progress("coarse grid alone"))
         Hf = fine.state()[0]
         Hc = coarse.state()[0]
         err = {"two_way": [], "one_way": [], "coarse_only": []}

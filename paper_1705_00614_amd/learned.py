@@ -172,14 +172,15 @@ def timing(net, fine_sc, r, sim_seconds, skip=0, corr_depth=CORR_DEPTH):
     return res
 
 
-def advance_to(g, t_end, frac=0.5, chunk=16):
+def advance_to(g, t_end, frac=0.5, chunk=16, on_run=None):
     """Advance a solver (or a nest, by coarse steps) with its own CFL steps to t_end: runs of at most
     `chunk` steps while the end is far, single steps near it, and a last step
     held to the remaining time (to within the rounding of the step length to
     the stencil type).  A run never passes the end: where the solver has a
     cap on its step (tau_max) a run is at most what is left over that cap;
     without one it covers at most frac of what is left at the current step
-    length, and a step that grows faster than that within the run raises."""
+    length, and a step that grows faster than that within the run raises.
+    on_run(t) is called after every run or step with the solver's time."""
     cap = float(getattr(g, "tau_max", 0.0) or 0.0)
     while True:
         left = t_end - g.time()
@@ -202,6 +203,8 @@ def advance_to(g, t_end, frac=0.5, chunk=16):
             g.step()
             g.hold_dt(0.0)
             return
+        if on_run is not None:
+            on_run(g.time())
 
 
 class GuardedRun:
