@@ -194,12 +194,13 @@ __device__ __forceinline__ bool finite(double a) { return rabs(a) <= 1.797693134
 // neighbour toward the exact remainder e = (a + d) - s (two-sum) with
 // probability |e| / gap makes the stored depth unbiased, so the volume error
 // is a random walk at the rounding level.  The decision is a hash of the
-// cell's global index and the step: the same wherever the cell is computed
-// (its own tile, a neighbour's ring, a batch, any tile shape).
-__device__ __forceinline__ unsigned cell_hash(unsigned cell, unsigned gen) {
+// cell's global index and the step's clock: the same wherever the cell is
+// computed (its own tile, a neighbour's ring, a batch, any tile shape, a run
+// resumed from a checkpoint).
+__device__ __forceinline__ unsigned cell_hash(unsigned cell, unsigned clk) {
     // MurmurHash3's 32-bit finalizer (Appleby) of the cell index mixed with
-    // the step by the golden-ratio constant
-    unsigned h = cell ^ (gen * 0x9E3779B9u);
+    // the step's clock bits by the golden-ratio constant
+    unsigned h = cell ^ (clk * 0x9E3779B9u);
     h ^= h >> 16; h *= 0x85EBCA6Bu; h ^= h >> 13; h *= 0xC2B2AE35u; h ^= h >> 16;
     return h;
 }
@@ -489,7 +490,16 @@ struct ListCtx {
     int* stamp; int* lists; int* hot;
     int cap, slot, grp, gen, sid, tile_base, tile, ntx, nty;
     bool on;
+    unsigned clk;   // the step's clock mixed to 32 bits (stochastic rounding)
 };
+
+// The clock t at the start of a step, mixed to 32 bits: distinct for every
+// step of a run and restored with the clock (a resumed run rounds as the
+// original did).
+__device__ __forceinline__ unsigned clock_bits(double t) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(t);
+    return (unsigned)b ^ ((unsigned)(b >> 32) * 0x9E3779B9u);
+}
 
 template <typename real>
 __device__ __forceinline__ bool is_src(const Args<real>& a, int gx, int gy) {
@@ -1079,7 +1089,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real Ht = cl[i + 2].H, dH = r * (dxH + (FH[i] - FH[i + 1]));
                 real Hn = Ht + dH;
                 if constexpr (F32)
-                    Hn = round_stochastic(Ht, dH, Hn, cell_hash((unsigned)((ty0 + y) * nx + tx0 + x), (unsigned)lx.gen));
+                    Hn = round_stochastic(Ht, dH, Hn, cell_hash((unsigned)((ty0 + y) * nx + tx0 + x), lx.clk));
                 const real qx = L.GX[s] + r * (dxQx + (Ft[i] - Ft[i + 1]));
                 const real qy = L.GY[s] + r * (dxQy + (Fn[i] - Fn[i + 1]));
                 const real Hc = rmax(Hn, real(0));
@@ -1200,6 +1210,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
     const real tau = (real)ctrl->tau;
     const real sdep = (real)ctrl->sdepth;
     const int gen = (int)ctrl->step + 2;
+    const unsigned clk = clock_bits(ctrl->t);
     const int nx = a.nx, ny = a.ny;
     // a list no longer than the grid: one tile or none per workgroup, in
     // own-segment order; a longer one: plain order, strided by the grid
@@ -1233,7 +1244,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
         const double fvo = FLD && tid == 0 ? a.fvol[tile] : 0.0;
         const ListCtx lx{a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp, gen, 0, 0, tile, a.ntx, a.nty,
-                         a.skip != 0 && !(RING && ring_tile(a, tile))};
+                         a.skip != 0 && !(RING && ring_tile(a, tile)), clk};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
             tile_step<real, TX, TY, NT, LIM, true, MODE>(a, L, tx0, ty0, tau, sdep, vmax, bad, msum, lsum, fsum,
@@ -1539,7 +1550,7 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_batch_step(Batch
         int bits = 0, nbst = gen;
         const double led = tid == 0 ? a.ledger[tile] : 0.0;
         const ListCtx lx{a.stamp, ba.lists, ba.hot, ba.list_cap, ba.slot ^ 1, grp, gen, sid, a.tile_base, tile,
-                         a.ntx, a.nty, a.skip != 0};
+                         a.ntx, a.nty, a.skip != 0, clock_bits(a.ctrl->t)};
         __syncthreads();   // LDS of the previous tile is free
         if (edge)
             tile_step<real, TX, TY, NT, LIM, true, MODE_PLAIN>(a, L, tx0, ty0, tau, sdep, vt, bad, msum, lsum, fnone,
