@@ -37,7 +37,11 @@ here is coarse-first subcycling with conservative flux matching:
   5. reflux: each uncovered coarse cell next to a covered region gets the
      difference between the recorded coarse flux and the mean of the r fine
      face fluxes over the r substeps (depth clamped at 0 into the ledger, Q
-     zeroed where H <= eps, as in the final update);
+     zeroed where H <= eps, as in the final update); the momentum part only
+     where the corrected depth exceeds MOMENTUM_DEPTH (5 cm), the rule of
+     the learned path's corrections: a film that took the patch flow's
+     momentum would set the nest's CFL step through the friction term of
+     U_p (1-2 orders of magnitude shorter steps);
   6. the coarse bed under a patch is the mean of the fine bed (an input).
 Without feedback (one-way zoom-in) steps 4 and 5 are skipped: the coarse grid
 runs as if alone and only drives the patches.  Patches must not touch each
@@ -51,6 +55,7 @@ import numpy as np
 from oracle.oracle import OracleSim
 
 G = 5   # frame width in fine cells: reach of one step (4) plus one
+MOMENTUM_DEPTH = 0.05   # [m] ring cells shallower than this take no momentum reflux
 
 
 class OracleNest:
@@ -207,18 +212,30 @@ class OracleNest:
             ring[rows, ci0 - 1] = ring[rows, ci0 + cw] = True
             ring[cj0 - 1, cols] = ring[cj0 + ch, cols] = True
         if self.feedback:
-            # the corrected ring cells get the final update's clamp and dry rule
-            Hn = H + dH
-            Hcl = np.maximum(Hn, 0.0)
-            self.ledger += float(((Hcl - Hn) * h_c * h_c)[ring].sum())
-            wet = Hcl > self.eps
-            Qx = np.where(ring, np.where(wet, Qx + dQx, 0.0), Qx)
-            Qy = np.where(ring, np.where(wet, Qy + dQy, 0.0), Qy)
-            H = np.where(ring, Hcl, H)
+            H, Qx, Qy, clamped = self.ring_update(H, Qx, Qy, dH, dQx, dQy, ring)
+            self.ledger += clamped * h_c * h_c
             self.c.set_state(H, Qx, Qy)
             s_post = self.c.cell_speeds()[self.region].max()
             s_pre = max(s_pre, s_post)
         self._set_taus(self.c.tau_from_speed(s_pre), tau_k)
+
+    def ring_update(self, H, Qx, Qy, dH, dQx, dQy, ring):
+        """The reflux corrections applied to the ring cells (reading of the
+        final update's rules): depth clamped at 0 (the clamped depth is
+        returned for the ledger), discharge zeroed where the cell is dry
+        after the correction, and the momentum part added only where the
+        corrected depth exceeds MOMENTUM_DEPTH: the boundary-flux mismatch
+        would otherwise give a film at the edge of a box the momentum of the
+        patch's flow, and through the friction term of U_p such a film sets
+        the CFL step of the whole nest."""
+        Hn = H + dH
+        Hcl = np.maximum(Hn, 0.0)
+        clamped = float((Hcl - Hn)[ring].sum())
+        wet = Hcl > self.eps
+        deep = Hcl > MOMENTUM_DEPTH
+        Qx = np.where(ring, np.where(wet, Qx + np.where(deep, dQx, 0.0), 0.0), Qx)
+        Qy = np.where(ring, np.where(wet, Qy + np.where(deep, dQy, 0.0), 0.0), Qy)
+        return np.where(ring, Hcl, H), Qx, Qy, clamped
 
     def run(self, n, tau_c=None):
         for _ in range(n):

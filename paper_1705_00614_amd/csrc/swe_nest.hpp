@@ -21,9 +21,10 @@
 //            r x r fine cells; each uncovered cell next to a covered box
 //            takes (coarse tap - mean of the r fine taps of the same coarse
 //            face) / h_c through that face, with the final update's clamp,
-//            ledger and dry rule; k_nest_force puts the tiles round the
-//            covered boxes on the coarse tile list; k_region_speed gathers
-//            the CFL speed of the changed cells
+//            ledger and dry rule, the momentum part only where the cell is
+//            deeper than NEST_MOMENTUM_DEPTH after it; k_nest_force puts
+//            the tiles round the covered boxes on the coarse tile list;
+//            k_region_speed gathers the CFL speed of the changed cells
 //   tau      k_nest_tau: tau_c = min(CFL step of the coarse speeds,
 //            r * CFL step of every patch after its last substep), tau_f =
 //            tau_c / r, and the coarse hydrograph volume of the next step.
@@ -37,6 +38,10 @@
 namespace swe {
 
 constexpr int NEST_FRAME = 5;   // frame width in fine cells
+// ring cells shallower than this [m] after the reflux take its mass but not
+// its momentum (a film moving with the patch's flow would set the nest's
+// CFL step through the friction term of U_p)
+constexpr double NEST_MOMENTUM_DEPTH = 0.05;
 
 template <typename real>
 struct NestPatch {
@@ -188,10 +193,10 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
     const real Hn = n.Hc[po][gc] + dH;
     const real Hcl = rmax(Hn, real(0));
     n.ring_ledger[q] += (double)(Hcl - Hn) * n.h2;
-    const bool w = Hcl > n.eps;
+    const bool w = Hcl > n.eps, deep = Hcl > (real)NEST_MOMENTUM_DEPTH;
     n.Hc[po][gc] = Hcl;
-    n.Qxc[po][gc] = w ? n.Qxc[po][gc] + dQx : real(0);
-    n.Qyc[po][gc] = w ? n.Qyc[po][gc] + dQy : real(0);
+    n.Qxc[po][gc] = w ? n.Qxc[po][gc] + (deep ? dQx : real(0)) : real(0);
+    n.Qyc[po][gc] = w ? n.Qyc[po][gc] + (deep ? dQy : real(0)) : real(0);
 }
 
 // Put the tiles round the covered boxes on the coarse tile list of the next

@@ -84,6 +84,31 @@ def test_frame_carries_the_coarse_velocity():
     assert np.abs(Qx[wet] / H[wet] - ux).max() < 1e-14 and np.abs(Qy[wet] / H[wet] - uy).max() < 1e-14
 
 
+def test_ring_update_keeps_momentum_out_of_films():
+    """The reflux into a ring cell: depth clamped at 0 (the clamp returned
+    for the ledger), discharge zeroed where the cell ends dry, and the
+    momentum part only where the corrected cell is deeper than 5 cm; cells
+    off the ring are untouched."""
+    N = _wet_nest()
+    z = np.zeros((1, 5))
+    H = np.array([[0.0, 0.02, 1.0, 0.3, 2.0]])
+    Qx = np.array([[0.0, 0.001, 0.5, 0.1, 0.7]])
+    Qy = -Qx
+    dH = np.array([[0.0003, 0.01, 0.01, -0.5, 0.4]])
+    dQx = np.array([[0.002, 0.003, 0.02, 0.04, 0.05]])
+    dQy = 2.0 * dQx
+    ring = np.array([[True, True, True, True, False]])
+    H2, X2, Y2, clamped = N.ring_update(H, Qx, Qy, dH, dQx, dQy, ring)
+    # a film (3e-4 m after the reflux) keeps no momentum; a 3 cm cell keeps
+    # its own but takes none; a 1 m cell takes it; a drained cell is dry
+    assert H2[0, 0] == 0.0003 and X2[0, 0] == 0.0 and Y2[0, 0] == 0.0
+    assert H2[0, 1] == 0.03 and X2[0, 1] == 0.001 and Y2[0, 1] == -0.001
+    assert abs(H2[0, 2] - 1.01) < 1e-15 and abs(X2[0, 2] - 0.52) < 1e-15 and abs(Y2[0, 2] + 0.46) < 1e-15
+    assert H2[0, 3] == 0.0 and X2[0, 3] == 0.0 and Y2[0, 3] == 0.0
+    assert abs(clamped - 0.2) < 1e-15
+    assert H2[0, 4] == 2.0 and X2[0, 4] == 0.7 and Y2[0, 4] == -0.7
+
+
 def _wet_nest(r=4, feedback=True, reflux=True):
     sc = S.floodplain(n=48, h=50.0, seed=4, q_peak=800.0, t_peak=300.0, sigma_t=200.0,
                       inlet_cells=4, precision=64)
