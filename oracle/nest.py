@@ -37,9 +37,10 @@ here is coarse-first subcycling with conservative flux matching:
   5. reflux: each uncovered coarse cell next to a covered region gets the
      difference between the recorded coarse flux and the mean of the r fine
      face fluxes over the r substeps (depth clamped at 0 into the ledger, Q
-     zeroed where H <= eps, as in the final update); the momentum part only
-     where the corrected depth exceeds MOMENTUM_DEPTH (5 cm), the rule of
-     the learned path's corrections: a film that took the patch flow's
+     zeroed where H <= eps, as in the final update); the momentum part with
+     a weight rising from 0 at MOMENTUM_DEPTH (5 cm) to 1 at 10 cm of
+     corrected depth, as the learned path's corrections keep momentum out of
+     films: a film that took the patch flow's
      momentum would set the nest's CFL step through the friction term of
      U_p (1-2 orders of magnitude shorter steps);
   6. the coarse bed under a patch is the mean of the fine bed (an input).
@@ -55,7 +56,7 @@ import numpy as np
 from oracle.oracle import OracleSim
 
 G = 5   # frame width in fine cells: reach of one step (4) plus one
-MOMENTUM_DEPTH = 0.05   # [m] ring cells shallower than this take no momentum reflux
+MOMENTUM_DEPTH = 0.05   # [m] ring cells shallower take no momentum reflux, twice as deep all of it
 
 
 class OracleNest:
@@ -223,8 +224,8 @@ class OracleNest:
         """The reflux corrections applied to the ring cells (reading of the
         final update's rules): depth clamped at 0 (the clamped depth is
         returned for the ledger), discharge zeroed where the cell is dry
-        after the correction, and the momentum part added only where the
-        corrected depth exceeds MOMENTUM_DEPTH: the boundary-flux mismatch
+        after the correction, and the momentum part added with a weight that
+        rises from 0 at MOMENTUM_DEPTH to 1 at twice that: the boundary-flux mismatch
         would otherwise give a film at the edge of a box the momentum of the
         patch's flow, and through the friction term of U_p such a film sets
         the CFL step of the whole nest."""
@@ -232,9 +233,11 @@ class OracleNest:
         Hcl = np.maximum(Hn, 0.0)
         clamped = float((Hcl - Hn)[ring].sum())
         wet = Hcl > self.eps
-        deep = Hcl > MOMENTUM_DEPTH
-        Qx = np.where(ring, np.where(wet, Qx + np.where(deep, dQx, 0.0), 0.0), Qx)
-        Qy = np.where(ring, np.where(wet, Qy + np.where(deep, dQy, 0.0), 0.0), Qy)
+        # weight of the momentum part: 0 up to MOMENTUM_DEPTH, 1 from twice
+        # that, linear between (continuous, so that rounding cannot flip it)
+        wgt = np.clip(Hcl / MOMENTUM_DEPTH - 1.0, 0.0, 1.0)
+        Qx = np.where(ring, np.where(wet, Qx + wgt * dQx, 0.0), Qx)
+        Qy = np.where(ring, np.where(wet, Qy + wgt * dQy, 0.0), Qy)
         return np.where(ring, Hcl, H), Qx, Qy, clamped
 
     def run(self, n, tau_c=None):

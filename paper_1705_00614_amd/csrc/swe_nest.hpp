@@ -21,8 +21,8 @@
 //            r x r fine cells; each uncovered cell next to a covered box
 //            takes (coarse tap - mean of the r fine taps of the same coarse
 //            face) / h_c through that face, with the final update's clamp,
-//            ledger and dry rule, the momentum part only where the cell is
-//            deeper than NEST_MOMENTUM_DEPTH after it; k_nest_force puts
+//            ledger and dry rule, the momentum part weighted by the cell's
+//            depth after it (NEST_MOMENTUM_DEPTH); k_nest_force puts
 //            the tiles round the covered boxes on the coarse tile list;
 //            k_region_speed gathers the CFL speed of the changed cells
 //   tau      k_nest_tau: tau_c = min(CFL step of the coarse speeds,
@@ -39,8 +39,9 @@ namespace swe {
 
 constexpr int NEST_FRAME = 5;   // frame width in fine cells
 // ring cells shallower than this [m] after the reflux take its mass but not
-// its momentum (a film moving with the patch's flow would set the nest's
-// CFL step through the friction term of U_p)
+// its momentum, twice as deep all of it, linear between (a film moving with
+// the patch's flow would set the nest's CFL step through the friction term
+// of U_p)
 constexpr double NEST_MOMENTUM_DEPTH = 0.05;
 
 template <typename real>
@@ -193,10 +194,13 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
     const real Hn = n.Hc[po][gc] + dH;
     const real Hcl = rmax(Hn, real(0));
     n.ring_ledger[q] += (double)(Hcl - Hn) * n.h2;
-    const bool w = Hcl > n.eps, deep = Hcl > (real)NEST_MOMENTUM_DEPTH;
+    const bool w = Hcl > n.eps;
+    // momentum weight: 0 up to NEST_MOMENTUM_DEPTH, 1 from twice that,
+    // linear between (continuous: rounding cannot flip it)
+    const real wm = rmin(real(1), rmax(real(0), Hcl / (real)NEST_MOMENTUM_DEPTH - real(1)));
     n.Hc[po][gc] = Hcl;
-    n.Qxc[po][gc] = w ? n.Qxc[po][gc] + (deep ? dQx : real(0)) : real(0);
-    n.Qyc[po][gc] = w ? n.Qyc[po][gc] + (deep ? dQy : real(0)) : real(0);
+    n.Qxc[po][gc] = w ? n.Qxc[po][gc] + wm * dQx : real(0);
+    n.Qyc[po][gc] = w ? n.Qyc[po][gc] + wm * dQy : real(0);
 }
 
 // Put the tiles round the covered boxes on the coarse tile list of the next

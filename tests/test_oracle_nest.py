@@ -87,23 +87,24 @@ def test_frame_carries_the_coarse_velocity():
 def test_ring_update_keeps_momentum_out_of_films():
     """The reflux into a ring cell: depth clamped at 0 (the clamp returned
     for the ledger), discharge zeroed where the cell ends dry, and the
-    momentum part only where the corrected cell is deeper than 5 cm; cells
-    off the ring are untouched."""
+    momentum part weighted from 0 at 5 cm of corrected depth to 1 at 10 cm;
+    cells off the ring are untouched."""
     N = _wet_nest()
-    z = np.zeros((1, 5))
-    H = np.array([[0.0, 0.02, 1.0, 0.3, 2.0]])
-    Qx = np.array([[0.0, 0.001, 0.5, 0.1, 0.7]])
+    H = np.array([[0.0, 0.02, 1.0, 0.3, 2.0, 0.07]])
+    Qx = np.array([[0.0, 0.001, 0.5, 0.1, 0.7, 0.01]])
     Qy = -Qx
-    dH = np.array([[0.0003, 0.01, 0.01, -0.5, 0.4]])
-    dQx = np.array([[0.002, 0.003, 0.02, 0.04, 0.05]])
+    dH = np.array([[0.0003, 0.01, 0.01, -0.5, 0.4, 0.005]])
+    dQx = np.array([[0.002, 0.003, 0.02, 0.04, 0.05, 0.004]])
     dQy = 2.0 * dQx
-    ring = np.array([[True, True, True, True, False]])
+    ring = np.array([[True, True, True, True, False, True]])
     H2, X2, Y2, clamped = N.ring_update(H, Qx, Qy, dH, dQx, dQy, ring)
     # a film (3e-4 m after the reflux) keeps no momentum; a 3 cm cell keeps
-    # its own but takes none; a 1 m cell takes it; a drained cell is dry
+    # its own but takes none; a 1 m cell takes all; a 7.5 cm cell half; a
+    # drained cell is dry
     assert H2[0, 0] == 0.0003 and X2[0, 0] == 0.0 and Y2[0, 0] == 0.0
     assert H2[0, 1] == 0.03 and X2[0, 1] == 0.001 and Y2[0, 1] == -0.001
     assert abs(H2[0, 2] - 1.01) < 1e-15 and abs(X2[0, 2] - 0.52) < 1e-15 and abs(Y2[0, 2] + 0.46) < 1e-15
+    assert abs(H2[0, 5] - 0.075) < 1e-15 and abs(X2[0, 5] - 0.012) < 1e-14 and abs(Y2[0, 5] + 0.006) < 1e-14
     assert H2[0, 3] == 0.0 and X2[0, 3] == 0.0 and Y2[0, 3] == 0.0
     assert abs(clamped - 0.2) < 1e-15
     assert H2[0, 4] == 2.0 and X2[0, 4] == 0.7 and Y2[0, 4] == -0.7
