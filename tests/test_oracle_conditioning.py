@@ -99,3 +99,28 @@ def test_nest_free_steps_are_ill_conditioned_in_fp32():
 def test_nest_held_steps_are_well_conditioned_in_fp32():
     worst, dt = _nest_pair(held=True, steps=48)
     assert worst < 1e-4 and dt == 0.0
+
+
+def _nest_bed_sensitivity(box, steps=40):
+    """Largest relative change (H and HU, L1 and per cell, coarse grid and
+    patch) of the FP64 oracle nest after `steps` coarse steps when the
+    coarse bed is scaled by 1 + 1e-15."""
+    sc = S.floodplain(n=96, h=50.0, seed=6, q_peak=2500.0, t_peak=600.0, sigma_t=300.0, inlet_cells=4,
+                      precision=64)
+    n = S.nest(sc, [box], r=4, seed=3)
+    a = OracleNest(n["coarse"], n["patches"], r=4)
+    c2 = dict(n["coarse"], b=n["coarse"]["b"] * (1.0 + 1e-15))
+    b = OracleNest(c2, n["patches"], r=4)
+    a.run(steps)
+    b.run(steps)
+    return max(P.errors(b.coarse_state(), a.coarse_state()) + P.errors(b.patch_state(0), a.patch_state(0)))
+
+
+def test_nest_boxes_of_the_fp64_gpu_comparison_are_well_conditioned():
+    """The boxes the FP64 nest skip test compares with the oracle at 1e-10
+    (tests/test_gpu_nest.py): a 1e-15 change of the bed moves the oracle
+    by far less than that; a box next to them is shown to move by ~1e-8, so
+    the choice matters."""
+    for box in ((20, 24, 44, 40), (22, 26, 46, 38)):
+        assert _nest_bed_sensitivity(box) < 1e-12
+    assert _nest_bed_sensitivity((24, 24, 44, 40)) > 1e-10
