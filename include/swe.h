@@ -85,6 +85,16 @@ typedef struct {
                             stencil at the centres (default).  Single grids
                             with the default tile shape; not with nests,
                             batches, corrections, networks, taps or fields. */
+    int    periodic;       /* boundary: 0 reflective walls at the domain edges
+                            (default; mirror ghost cells, normal velocity
+                            negated); 1 periodic in x and y, for tests of
+                            conservation (the cell one period away).
+                            Periodic: single grids with the default tile
+                            shape, nx and ny multiples of it, no solid
+                            cells, the lattice corrector; not with nests,
+                            batches, fields, corrections, networks, taps,
+                            the autotuner or swe_step_noalloc (SWE_EINVAL /
+                            NULL from swe_create). */
 } swe_params;
 
 /* Create a solver on an nx x ny grid of cell size dx [m] with bed elevation

@@ -133,7 +133,7 @@ class OracleSim:
         self._keep = [_f64(sc.get(k), shp) for k in ("b", "n_manning", "H0", "Qx0", "Qy0")]
         solid = sc.get("solid")
         self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-        self._prm = make_params(sc["params"], periodic)
+        self._prm = make_params(sc["params"], periodic or bool(sc["params"].get("periodic", 0)))
         b, nm, H0, Qx0, Qy0 = self._keep
         self._h = L.orc_create(self.nx, self.ny, self.h, _dp(b), _dp(nm),
                                None if self._solid is None else self._solid.ctypes.data_as(_c_u8_p),

@@ -60,6 +60,8 @@ struct Launcher {
                              hipEvent_t e1); // source rate field; may be null
     hipError_t (*step_disp)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
                             hipEvent_t e1);  // displaced-particle corrector; may be null
+    hipError_t (*step_per)(const void* args, int grid, hipStream_t st, hipEvent_t e0,
+                           hipEvent_t e1);   // periodic domain; may be null
     hipError_t (*batch_step)(const void* bargs, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
     hipError_t (*batch_prepare_finish)(const void* bargs, hipStream_t st);
     hipError_t (*prepare)(const void* args, int grid, hipStream_t st);
@@ -106,8 +108,9 @@ int occupancy(int* blocks) {
 #define TAP_STEP(real, TX, TY, NT, LIM) launch_step<real, TX, TY, NT, LIM, swe::MODE_TAP>, \
                                         launch_step<real, TX, TY, NT, LIM, swe::MODE_CORR>, \
                                         launch_step<real, TX, TY, NT, LIM, swe::MODE_FIELD>, \
-                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_DISP>
-#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr, nullptr, nullptr
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_DISP>, \
+                                        launch_step<real, TX, TY, NT, LIM, swe::MODE_PERIODIC>
+#define NO_TAP_STEP(real, TX, TY, NT, LIM) nullptr, nullptr, nullptr, nullptr, nullptr
 #define LAUNCHER(real, TX, TY, NT, P, LIM, TAPS)                                                 \
     Launcher{TX, TY, NT, P, LIM, launch_step<real, TX, TY, NT, LIM, swe::MODE_PLAIN>,             \
              TAPS(real, TX, TY, NT, LIM),                                                        \
@@ -230,6 +233,7 @@ void fill_args(swe_t* s, int parity, Args<real>* a) {
     a->nx = s->nx; a->ny = s->ny; a->ntx = s->ntx; a->nty = s->nty; a->ntiles = s->ntiles;
     a->skip = p.skip_dry ? 1 : 0;
     a->limiter = p.limiter;
+    a->periodic = p.periodic ? 1 : 0;
     if (s->nin > 0) {
         a->i0 = p.inlet_i0; a->j0 = p.inlet_j0; a->ni = p.inlet_ni; a->nj = p.inlet_nj;
     }
@@ -278,6 +282,7 @@ hipError_t launch_grid_step(swe_t* s, int par, hipEvent_t e0 = nullptr, hipEvent
              : s->corr                       ? s->L->step_corr
              : s->field                      ? s->L->step_field
              : s->p.sph_displaced            ? s->L->step_disp
+             : s->p.periodic                 ? s->L->step_per
                                              : s->L->step;
     return f(s->args[par].data(), s->grid, on ? on : s->stream, e0, e1);
 }
@@ -515,6 +520,11 @@ static swe_t* create_grid(int nx, int ny, double dx, const double* b, const doub
     if (!L) { set_err("swe_create: tile shape not available for this precision"); return nullptr; }
     if (p->sph_displaced && (!L->step_disp || ex)) {
         set_err("swe_create: the displaced-particle corrector needs a single grid with the default tile shape");
+        return nullptr;
+    }
+    if (p->periodic && (!L->step_per || ex || p->sph_displaced || p->solid || nx % L->tx || ny % L->ty)) {
+        set_err("swe_create: a periodic domain needs a single grid with the default tile shape, nx and ny "
+                "multiples of it, no solid cells and the lattice corrector");
         return nullptr;
     }
     // a tile-list entry holds the tile index in TILE_BITS bits
@@ -808,8 +818,9 @@ int swe_set_source_field(swe_t* s, const double* sigma) {
         set_err("swe_set_source_field: the tile shape has no field step kernel (default shapes only)");
         return SWE_EINVAL;
     }
-    if (sigma && (s->corr || s->lc || s->tap_r > 0 || s->p.sph_displaced)) {
-        set_err("swe_set_source_field: not with flux corrections, an attached network or line taps");
+    if (sigma && (s->corr || s->lc || s->tap_r > 0 || s->p.sph_displaced || s->p.periodic)) {
+        set_err("swe_set_source_field: not with flux corrections, an attached network, line taps, the "
+                "displaced-particle corrector or a periodic domain");
         return SWE_EINVAL;
     }
     const size_t n = (size_t)s->nx * s->ny;
@@ -928,8 +939,9 @@ static size_t line_tap_sizes(const swe_t* s, size_t* nyx) {
 
 int swe_enable_line_taps(swe_t* s, int r) {
     if (!s || r < 0) { set_err("swe_enable_line_taps: invalid arguments"); return SWE_EINVAL; }
-    if (r > 0 && (s->field || s->p.sph_displaced)) {
-        set_err("swe_enable_line_taps: not for a grid with a source rate field or the displaced-particle corrector");
+    if (r > 0 && (s->field || s->p.sph_displaced || s->p.periodic)) {
+        set_err("swe_enable_line_taps: not for a grid with a source rate field, the displaced-particle corrector "
+                "or a periodic domain");
         return SWE_EINVAL;
     }
     if (r == 0) {
@@ -1061,8 +1073,9 @@ int swe_set_correction(swe_t* s, const double* dE, const double* dN) {
         return 0;
     }
     if (!s->L->step_corr) { set_err("swe_set_correction: the tile shape has no correcting step kernel"); return SWE_EINVAL; }
-    if (s->field || s->p.sph_displaced) {
-        set_err("swe_set_correction: not with a source rate field or the displaced-particle corrector");
+    if (s->field || s->p.sph_displaced || s->p.periodic) {
+        set_err("swe_set_correction: not with a source rate field, the displaced-particle corrector or a "
+                "periodic domain");
         return SWE_EINVAL;
     }
     if (s->ntap > 0) { set_err("swe_set_correction: not for grids of a nest"); return SWE_EINVAL; }
@@ -1223,8 +1236,10 @@ swe_batch_t* swe_batch_create(int n, const int* nx, const int* ny, const double*
     }
     const swe_params& p0 = p[0];
     if (!p0.skip_dry) { set_err("swe_batch_create: a batch runs with dry-tile skipping"); return nullptr; }
-    for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k) {
         if (p[k].sph_displaced) { set_err("swe_batch_create: no displaced-particle corrector in a batch"); return nullptr; }
+        if (p[k].periodic) { set_err("swe_batch_create: no periodic domain in a batch"); return nullptr; }
+    }
     const Launcher* L = find_launcher(p0.precision, p0.tile_x, p0.tile_y, p0.limiter);
     if (!L) { set_err("swe_batch_create: tile shape not available for this precision/limiter"); return nullptr; }
     long long total = 0;
@@ -2492,8 +2507,9 @@ int swe_lc_attach(swe_lc_t* c, swe_t* s) {
         s->corr = false;
         return 0;
     }
-    if (s->field || s->p.sph_displaced) {
-        set_err("swe_lc_attach: not for a grid with a source rate field or the displaced-particle corrector");
+    if (s->field || s->p.sph_displaced || s->p.periodic) {
+        set_err("swe_lc_attach: not for a grid with a source rate field, the displaced-particle corrector or a "
+                "periodic domain");
         return SWE_EINVAL;
     }
     if (s->L->tx != c->S || s->L->ty != c->S) { set_err("swe_lc_attach: the network's tile differs from the grid's"); return SWE_EINVAL; }
@@ -2854,6 +2870,7 @@ int swe_autotune(int nx, int ny, double dx, const double* b, const double* n_M, 
     if (!p || !b || warmup < 0 || nsteps < 1 || cap < 1 || !tile_x || !tile_y) {
         set_err("swe_autotune: invalid arguments"); return SWE_EINVAL;
     }
+    if (p->periodic) { set_err("swe_autotune: a periodic domain runs the default tile shape only"); return SWE_EINVAL; }
     const Launcher* sh[16];
     const int n = shapes_of(p->precision, p->limiter, sh, 16);
     if (n == 0) { set_err("swe_autotune: no tile shape for this precision and limiter"); return SWE_EINVAL; }
@@ -2975,6 +2992,7 @@ void fill_args_noalloc(Args<real>* a, const swe_params& p, int nx, int ny, doubl
     a->list_cap = ntx * nty;
     a->skip = 0;   // every tile is stepped, so every output cell is written
     a->limiter = p.limiter;
+    a->periodic = 0;
     const int nin = p.inlet_ni > 0 && p.inlet_nj > 0 ? p.inlet_ni * p.inlet_nj : 0;
     if (nin > 0) { a->i0 = p.inlet_i0; a->j0 = p.inlet_j0; a->ni = p.inlet_ni; a->nj = p.inlet_nj; }
     a->h = (real)dx; a->ih = (real)(1.0 / dx); a->g = (real)p.g; a->eps = (real)p.eps;
@@ -3005,8 +3023,8 @@ int swe_step_noalloc(int nx, int ny, double dx, const swe_params* p, const void*
         return SWE_EINVAL;
     }
     if ((p->precision != 32 && p->precision != 64) || !(p->cfl > 0.0 && p->cfl < 1.0) || !(p->eps > 0.0) ||
-        p->limiter < 0 || p->limiter > 2) {
-        set_err("swe_step_noalloc: invalid parameters");
+        p->limiter < 0 || p->limiter > 2 || p->periodic) {
+        set_err("swe_step_noalloc: invalid parameters (walls only)");
         return SWE_EINVAL;
     }
     const Launcher* L = find_launcher(p->precision, 0, 0, p->limiter);

@@ -104,6 +104,7 @@ struct Args {
     double* mass;                                       // per-tile sum of H
     double* ledger;                                     // per-tile clamp volume
     int nx, ny, ntx, nty, ntiles, skip, limiter;
+    int periodic;                                       // 1: the domain wraps in x and y (no walls)
     int list_cap;                                       // capacity of one list segment
     int i0, j0, ni, nj;                                 // inlet rectangle
     real h, ih, g, eps, nuh2, fcor, wx, wy, kw, hw;     // stencil constants
@@ -153,7 +154,7 @@ __device__ __forceinline__ bool ring_tile(const Args<real>& a, int tile) {
 // Variants of the step kernel: plain, with flux taps (nested grids), with
 // learned flux corrections, with a source rate field, with the corrector's
 // pressure gradient at the displaced particle positions.
-constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2, MODE_FIELD = 3, MODE_DISP = 4;
+constexpr int MODE_PLAIN = 0, MODE_TAP = 1, MODE_CORR = 2, MODE_FIELD = 3, MODE_DISP = 4, MODE_PERIODIC = 5;
 
 // ---------------------------------------------------------------- math
 
@@ -703,7 +704,13 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     constexpr int W = G::W;
     constexpr bool TAP = MODE == MODE_TAP, CORR = MODE == MODE_CORR, FLD = MODE == MODE_FIELD;
     constexpr bool DISP = MODE == MODE_DISP;
+    // periodic domain (tests of conservation): a halo cell is the cell one
+    // period away, computed there exactly as in its own tile, so the walls'
+    // ghost fills are not needed; nx and ny are multiples of the tile shape
+    constexpr bool PER = MODE == MODE_PERIODIC;
     const int tid = threadIdx.x, nx = a.nx, ny = a.ny;
+    auto wrapx = [&](int g) { if constexpr (PER) { g %= nx; if (g < 0) g += nx; } return g; };
+    auto wrapy = [&](int g) { if constexpr (PER) { g %= ny; if (g < 0) g += ny; } return g; };
     const real eps = a.eps, half_tau = real(0.5) * tau, r = tau * a.ih;
     // normalised cubic-B-spline SPH gradient weights (smoothing length h):
     // al = 1/(12 sqrt2 - 14), be = (3 sqrt2 - 4)/(12 sqrt2 - 14), 2 al + 4 be = 1
@@ -718,7 +725,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     constexpr int RFY = F32 ? 3 : 4;
     static_assert((TX + 8) % RP == 0 && (TX + 4) % RFX == 0, "run lengths must tile the stage rows");
     auto inside = [&](int x, int y) {
-        if constexpr (!EDGE) return true;
+        if constexpr (!EDGE || PER) return true;
         const int gx = tx0 + x, gy = ty0 + y;
         return gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     };
@@ -736,7 +743,8 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             if (k >= NL) continue;
             const int x = k % RW - HALO, y = k / RW - HALO;
             int gx = tx0 + x, gy = ty0 + y, fx = 0, fy = 0;
-            if constexpr (EDGE) { gx = mirror(gx, nx, fx); gy = mirror(gy, ny, fy); }
+            if constexpr (PER) { gx = wrapx(gx); gy = wrapy(gy); }
+            else if constexpr (EDGE) { gx = mirror(gx, nx, fx); gy = mirror(gy, ny, fy); }
             const int gi = gy * nx + gx;
             vH[j] = a.Hi[gi];
             vX[j] = a.Qxi[gi];
@@ -764,7 +772,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             // K1 rule at layer n: own cells and outer face neighbours (no corners)
             const bool own = x >= 0 && x < TX && y >= 0 && y < TY;
             const bool ring = ((x == -1 || x == TX) && y >= 0 && y < TY) || ((y == -1 || y == TY) && x >= 0 && x < TX);
-            if ((own || ring) && inside(x, y) && (w || is_src(a, tx0 + x, ty0 + y))) act = 1;
+            if ((own || ring) && inside(x, y) && (w || is_src(a, wrapx(tx0 + x), wrapy(ty0 + y)))) act = 1;
         }
         if (__syncthreads_or(act) || (FLD && (fm & 33))) bits |= 64;
     }
@@ -855,7 +863,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
         }
         __syncthreads();
         if (early && e_old < lx.gen) e_base = atomicAdd(&lx.hot[hot_seg(lx.slot, lx.grp)], 1);
-        if constexpr (EDGE) {
+        if constexpr (EDGE && !PER) {
             fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -4, TX + 4, -4, TY + 4, L.HX, L.HY, nullptr,
                                           /*sgx*/ 1, /*sgy*/ 2);
             __syncthreads();
@@ -910,7 +918,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                     const int x = x0 + i;
                     if (!inside(x, y)) continue;
                     const int s = G::at(x, y);
-                    const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hr[i + 1] + sdep : Hr[i + 1];
+                    const real Hs = is_src(a, wrapx(tx0 + x), wrapy(ty0 + y)) ? Hr[i + 1] + sdep : Hr[i + 1];
                     if constexpr (FLD)
                         L.UX[s] = field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, false, x, y, fsum);
                     else
@@ -941,7 +949,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
                 const real d = real(1) + tau * lam;
                 const real qx = wc ? Hc * Mth<real>::div(ux + tau * ax, d) : real(0);
                 const real qy = wc ? Hc * Mth<real>::div(uy + tau * ay, d) : real(0);
-                const real Hs = is_src(a, tx0 + x, ty0 + y) ? Hc + sdep : Hc;
+                const real Hs = is_src(a, wrapx(tx0 + x), wrapy(ty0 + y)) ? Hc + sdep : Hc;
                 real Ht = Hs;
                 if constexpr (FLD)
                     if (inside(x, y)) Ht = field_depth_t<real, TX, TY>(a, tx0 + x, ty0 + y, tau, Hs, wc, x, y, fsum);
@@ -967,7 +975,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
         __syncthreads();
         if (early && e_old < lx.gen)
             lx.lists[(lx.slot * NSEG + lx.grp) * lx.cap + e_base] = pack_entry(lx.sid, lx.tile);
-        if constexpr (EDGE) {
+        if constexpr (EDGE && !PER) {
             fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -3, TX + 3, -3, TY + 3, L.UX, L.UY, L.LM,
                                           /*sgx*/ 2, /*sgy*/ 4);
             __syncthreads();
@@ -1022,10 +1030,10 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
     nbst = lx.gen;
     if (lx.on && tid >= 1 && tid <= 4) {
         const int ti = lx.tile % lx.ntx, tj = lx.tile / lx.ntx;
-        const int nb = tid == 1 ? (ti > 0 ? lx.tile - 1 : -1)
-                     : tid == 2 ? (ti < lx.ntx - 1 ? lx.tile + 1 : -1)
-                     : tid == 3 ? (tj > 0 ? lx.tile - lx.ntx : -1)
-                                : (tj < lx.nty - 1 ? lx.tile + lx.ntx : -1);
+        const int nb = tid == 1 ? (ti > 0 ? lx.tile - 1 : PER ? lx.tile + lx.ntx - 1 : -1)
+                     : tid == 2 ? (ti < lx.ntx - 1 ? lx.tile + 1 : PER ? lx.tile - lx.ntx + 1 : -1)
+                     : tid == 3 ? (tj > 0 ? lx.tile - lx.ntx : PER ? lx.tile + (lx.nty - 1) * lx.ntx : -1)
+                                : (tj < lx.nty - 1 ? lx.tile + lx.ntx : PER ? lx.tile - (lx.nty - 1) * lx.ntx : -1);
         if (nb >= 0) nbst = lx.stamp[lx.tile_base + nb];
     }
 
@@ -1118,7 +1126,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             }
         }
         __syncthreads();
-        if constexpr (EDGE) {
+        if constexpr (EDGE && !PER) {
             fill_ghosts<real, TX, TY, NT>(tx0, ty0, nx, ny, -1, TX + 1, -1, TY + 1, L.NH, L.GX, L.GY,
                                           /*sgx*/ 2, /*sgy*/ 4);
             __syncthreads();
@@ -1144,7 +1152,7 @@ __device__ void tile_step(const Args<real>& a, Lds<real, TX, TY>& L, int tx0, in
             const int s = G::at(x, y);
             const real H = L.NH[s];
             const bool w = H > eps;
-            const bool ws = w || is_src(a, tx0 + x, ty0 + y);
+            const bool ws = w || is_src(a, wrapx(tx0 + x), wrapy(ty0 + y));
             if (k >= NT_CELLS) { rg |= ws; continue; }
             if (ws) {
                 own = 1;
@@ -1287,10 +1295,14 @@ __global__ __launch_bounds__(NT, waves_per_simd<real>()) void k_step(Args<real> 
                 const bool fresh = nbst < gen;
                 int cand = -1;
                 if (lane == 0 && !(bb & 64) && (bb & (1 | 32))) cand = tile;
-                if (lane == 1 && (bb & 2) && ti > 0 && fresh) cand = tile - 1;
-                if (lane == 2 && (bb & 4) && ti < a.ntx - 1 && fresh) cand = tile + 1;
-                if (lane == 3 && (bb & 8) && tj > 0 && fresh) cand = tile - a.ntx;
-                if (lane == 4 && (bb & 16) && tj < a.nty - 1 && fresh) cand = tile + a.ntx;
+                constexpr bool PER = MODE == MODE_PERIODIC;   // neighbours wrap round the domain
+                if (lane == 1 && (bb & 2) && fresh && (ti > 0 || PER)) cand = ti > 0 ? tile - 1 : tile + a.ntx - 1;
+                if (lane == 2 && (bb & 4) && fresh && (ti < a.ntx - 1 || PER))
+                    cand = ti < a.ntx - 1 ? tile + 1 : tile - a.ntx + 1;
+                if (lane == 3 && (bb & 8) && fresh && (tj > 0 || PER))
+                    cand = tj > 0 ? tile - a.ntx : tile + (a.nty - 1) * a.ntx;
+                if (lane == 4 && (bb & 16) && fresh && (tj < a.nty - 1 || PER))
+                    cand = tj < a.nty - 1 ? tile + a.ntx : tile - (a.nty - 1) * a.ntx;
                 if (RING && cand >= 0 && ring_tile(a, cand)) cand = -1;
                 append_tiles(cand, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, a.slot ^ 1, grp);
             }
@@ -1385,8 +1397,14 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
     const real eps = a.eps;
     for (int k = tid; k < N; k += NT) {
         const int lx = k % W - 1, ly = k / W - 1;
-        int fx = 0, fy = 0;
-        const int gx = mirror(tx0 + lx, nx, fx), gy = mirror(ty0 + ly, ny, fy);
+        int fx = 0, fy = 0, gx, gy;
+        if (a.periodic) {   // the cell one period away, as it is
+            gx = (tx0 + lx + nx) % nx;
+            gy = (ty0 + ly + ny) % ny;
+        } else {
+            gx = mirror(tx0 + lx, nx, fx);
+            gy = mirror(ty0 + ly, ny, fy);
+        }
         const int gi = gy * nx + gx;
         const real H = a.Hi[gi];
         real qx = a.Qxi[gi], qy = a.Qyi[gi];
@@ -1403,7 +1421,8 @@ __global__ __launch_bounds__(NT) void k_prepare(Args<real> a) {
     int act = 0;
     for (int k = tid; k < N; k += NT) {
         const int lx = k % W - 1, ly = k / W - 1;
-        const int gx = tx0 + lx, gy = ty0 + ly;
+        int gx = tx0 + lx, gy = ty0 + ly;
+        if (a.periodic) { gx = (gx + nx) % nx; gy = (gy + ny) % ny; }
         if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
         const bool in_tile = lx >= 0 && lx < TX && ly >= 0 && ly < TY;
         const bool corner = (lx < 0 || lx >= TX) && (ly < 0 || ly >= TY);

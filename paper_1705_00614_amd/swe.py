@@ -35,7 +35,7 @@ class SweParams(ctypes.Structure):
         ("q_base", ctypes.c_double), ("q_peak", ctypes.c_double),
         ("t_peak", ctypes.c_double), ("sigma_t", ctypes.c_double),
         ("solid", ctypes.POINTER(ctypes.c_uint8)), ("H0", _dp), ("Qx0", _dp), ("Qy0", _dp),
-        ("stream", ctypes.c_void_p), ("sph_displaced", ctypes.c_int),
+        ("stream", ctypes.c_void_p), ("sph_displaced", ctypes.c_int), ("periodic", ctypes.c_int),
     ]
 
 
@@ -225,6 +225,7 @@ def make_params(prm, skip_dry=True, tile=(0, 0), stream=None):
     p.sigma_t = prm.get("sigma_t", 0.0)
     p.stream = stream
     p.sph_displaced = int(prm.get("sph_displaced", 0))
+    p.periodic = int(prm.get("periodic", 0))
     return p
 
 
