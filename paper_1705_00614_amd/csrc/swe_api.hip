@@ -1595,9 +1595,13 @@ hipError_t nest_step_t(swe_nest_t* n) {
     swe_t* c = n->c;
     const int pc = (int)(c->launched & 1);
     hipError_t e;
-    hipLaunchKernelGGL(swe::k_nest_zero<real>, dim3(blocks_for(n->ntap, 256) < 1024 ? blocks_for(n->ntap, 256) : 1024),
-                       dim3(256), 0, n->stream, (real*)n->tap, n->ntap);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // with feedback the previous close cleared the taps (and creation did)
+    if (!n->feedback) {
+        hipLaunchKernelGGL(swe::k_nest_zero<real>,
+                           dim3(blocks_for(n->ntap, 256) < 1024 ? blocks_for(n->ntap, 256) : 1024), dim3(256), 0,
+                           n->stream, (real*)n->tap, n->ntap);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if ((e = launch_grid_step(c, pc)) != hipSuccess) return e;
     c->launched++;
     for (int s = 0; s < n->r; ++s) {
@@ -1629,14 +1633,12 @@ hipError_t nest_step_t(swe_nest_t* n) {
         hipLaunchKernelGGL(swe::k_feedback<real>, dim3(blocks_for(na.ncov + na.nring, 256)), dim3(256), 0,
                            n->stream, na, pf, pc ^ 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (c->p.skip_dry && n->nforce > 0) {
-            hipLaunchKernelGGL(swe::k_nest_force<real>, dim3(blocks_for(n->nforce, 64)), dim3(64), 0, n->stream,
-                               an, n->force_tiles, n->nforce, pc ^ 1);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(swe::k_region_speed<real>, dim3(blocks_for(n->nregion_cells, 256)), dim3(256), 0,
-                           n->stream, an, n->region, n->nregion, n->nregion_cells);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int nforce = c->p.skip_dry ? n->nforce : 0;
+        const int work = std::max(n->nregion_cells, std::max(n->ntap, nforce));
+        const int grid = std::max(1, std::min(blocks_for(work, 256), swe::NEST_CLOSE_GRID));
+        hipLaunchKernelGGL(swe::k_nest_close<real>, dim3(grid), dim3(256), 0, n->stream, an, na, n->region,
+                           n->nregion, n->nregion_cells, n->force_tiles, nforce, n->ntap, pc ^ 1);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, an, na, pc ^ 1);
     return hipGetLastError();
@@ -1867,6 +1869,7 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
     NK(hipMalloc((void**)&n->scalar, sizeof(double)));
     NK(hipMemcpy(n->ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice));
     NK(hipMemset(n->ring_ledger, 0, sizeof(double) * std::max(nring, 1)));
+    NK(hipMemset(n->tap, 0, (size_t)ntap * n->rsize));
     n->force_tiles = n->ints + o_force;
     n->region = n->ints + o_region;
 

@@ -22,12 +22,14 @@
 //            takes (coarse tap - mean of the r fine taps of the same coarse
 //            face) / h_c through that face, with the final update's clamp,
 //            ledger and dry rule, the momentum part weighted by the cell's
-//            depth after it (NEST_MOMENTUM_DEPTH); k_nest_force puts
-//            the tiles round the covered boxes on the coarse tile list;
-//            k_region_speed gathers the CFL speed of the changed cells
-//   tau      k_nest_tau: tau_c = min(CFL step of the coarse speeds,
-//            r * CFL step of every patch after its last substep), tau_f =
-//            tau_c / r, and the coarse hydrograph volume of the next step.
+//            depth after it (NEST_MOMENTUM_DEPTH); then k_nest_close
+//            gathers the CFL speed of the changed cells, puts the tiles
+//            round the covered boxes on the coarse tile list and clears the
+//            taps, its last workgroup setting the steps as below
+//   tau      (k_nest_tau without feedback) tau_c = min(CFL step of the
+//            coarse speeds, r * CFL step of every patch after its last
+//            substep), tau_f = tau_c / r, and the coarse hydrograph volume of
+//            the next step.
 //
 // All of it is device work on one stream (capturable in a graph); the host
 // only launches.
@@ -203,58 +205,40 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
     n.Qyc[po][gc] = w ? n.Qyc[po][gc] + wm * dQy : real(0);
 }
 
-// Put the tiles round the covered boxes on the coarse tile list of the next
-// step (list slot `slot`, generation of that list), so that the cells the
-// feedback changed are stepped and both buffers of the pair stay consistent.
+// CFL speed of the new coarse layer (buffers of a's input) at cell t of the
+// cells the feedback can change: each covered box widened by 2 cells (rects:
+// x0, y0, x1, y1, cell prefix); 0 for a dry cell.
 template <typename real>
-__global__ void k_nest_force(Args<real> a, const int* tiles, int ntiles_forced, int slot) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int gen = (int)a.ctrl->step + 1;
-    append_tiles(t < ntiles_forced ? tiles[t] : -1, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, slot,
-                 blockIdx.x % NSEG);
-}
-
-// CFL speed of the new coarse layer (buffers of a's input) on the cells the
-// feedback can change: each covered box widened by 2 cells (rects: x0, y0,
-// x1, y1, cell prefix), gathered into the coarse control block.
-template <typename real>
-__global__ void k_region_speed(Args<real> a, const int* rects, int nrect, int ncells) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    real vmax = real(0);
-    if (t < ncells) {
-        int k = 0;
-        for (int q = 1; q < nrect; ++q) k += t >= rects[5 * q + 4];
-        const int* R = rects + 5 * k;
-        const int m = t - R[4], w = R[2] - R[0];
-        const int gx = R[0] + m % w, gy = R[1] + m / w;
-        const real eps = a.eps;
-        real Hs[5], ux[5], uy[5];
-        const int ox[5] = {0, -1, 1, 0, 0}, oy[5] = {0, 0, 0, -1, 1};
+__device__ real region_speed(const Args<real>& a, const int* rects, int nrect, int t) {
+    int k = 0;
+    for (int q = 1; q < nrect; ++q) k += t >= rects[5 * q + 4];
+    const int* R = rects + 5 * k;
+    const int m = t - R[4], w = R[2] - R[0];
+    const int gx = R[0] + m % w, gy = R[1] + m / w;
+    const real eps = a.eps;
+    real Hs[5], ux[5], uy[5];
+    const int ox[5] = {0, -1, 1, 0, 0}, oy[5] = {0, 0, 0, -1, 1};
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            int fx = 0, fy = 0;
-            const int x = mirror(gx + ox[q], a.nx, fx), y = mirror(gy + oy[q], a.ny, fy);
-            const int gi = y * a.nx + x;
-            const real H = a.Hi[gi];
-            real qx = a.Qxi[gi], qy = a.Qyi[gi];
-            if (fx & 1) qx = -qx;
-            if (fy & 1) qy = -qy;
-            const bool wq = H > eps;
-            Hs[q] = H;
-            ux[q] = wq ? Mth<real>::div(qx, H) : real(0);
-            uy[q] = wq ? Mth<real>::div(qy, H) : real(0);
-        }
-        if (Hs[0] > eps) {
-            Nb4<real> nb;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { nb.ux[q] = ux[q + 1]; nb.uy[q] = uy[q + 1]; nb.w[q] = Hs[q + 1] > eps; }
-            real fx, fy;
-            soft_forces(a, Hs[0], ux[0], uy[0], nb, fx, fy);
-            vmax = cfl_speed(a, Hs[0], a.cf[gy * a.nx + gx], ux[0], uy[0], fx, fy);
-        }
+    for (int q = 0; q < 5; ++q) {
+        int fx = 0, fy = 0;
+        const int x = mirror(gx + ox[q], a.nx, fx), y = mirror(gy + oy[q], a.ny, fy);
+        const int gi = y * a.nx + x;
+        const real H = a.Hi[gi];
+        real qx = a.Qxi[gi], qy = a.Qyi[gi];
+        if (fx & 1) qx = -qx;
+        if (fy & 1) qy = -qy;
+        const bool wq = H > eps;
+        Hs[q] = H;
+        ux[q] = wq ? Mth<real>::div(qx, H) : real(0);
+        uy[q] = wq ? Mth<real>::div(qy, H) : real(0);
     }
-    vmax = wave_max(vmax);
-    if ((threadIdx.x & 63) == 0 && vmax > real(0)) atomic_max_prep(a.ctrl, vmax);
+    if (!(Hs[0] > eps)) return real(0);
+    Nb4<real> nb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { nb.ux[q] = ux[q + 1]; nb.uy[q] = uy[q + 1]; nb.w[q] = Hs[q + 1] > eps; }
+    real fx, fy;
+    soft_forces(a, Hs[0], ux[0], uy[0], nb, fx, fy);
+    return cfl_speed(a, Hs[0], a.cf[gy * a.nx + gx], ux[0], uy[0], fx, fy);
 }
 
 // Lengths of the next coarse step (tc, rounded to the stencil type) and of
@@ -286,11 +270,11 @@ __global__ void k_nest_set_dt(Args<real> a, NestArgs<real> n, double tc) {
 
 // Time steps of the next coarse step and its substeps; errors of any grid
 // stop all of them.  `slot` is the coarse list slot of the next step.
+// S_region: a speed maximum gathered besides the control block's.
 template <typename real>
-__global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void nest_tau_rule(const Args<real>& a, const NestArgs<real>& n, int slot, double S_region) {
     Ctrl* c = a.ctrl;
-    const double S = fmax(c->speed, prep_speed(c, real(0)));
+    const double S = fmax(fmax(c->speed, prep_speed(c, real(0))), S_region);
     c->prep_speed = 0ull;
     c->speed = S;
     double tc = cfl_tau_of(a, S);
@@ -304,6 +288,71 @@ __global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
         c->err = e;
         c->err_gate = e;
         for (int k = 0; k < n.np; ++k) n.P[k].ctrl->err_gate = e;
+    }
+}
+
+template <typename real>
+__global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    nest_tau_rule(a, n, slot, 0.0);
+}
+
+// The close of a two-way coarse step, one launch after k_feedback (at most
+// NEST_CLOSE_GRID workgroups of 256 threads, each striding over the work):
+// the CFL speed of the new coarse layer on the cells the feedback can change;
+// the tiles round the covered boxes put on the coarse list of the next step
+// (list `slot`, generation of that list), so that the cells the feedback
+// changed are stepped and both buffers of the pair stay consistent; the taps
+// cleared for the next coarse step.  The last workgroup to finish sets the
+// next steps (k_nest_tau's rule).  Completion uses the coarse grid's group
+// words, which are zero between two of its step launches: each workgroup's
+// speed maximum and arrival go to its group's words by atomics, the arrival
+// issued only once the maximum has returned (so are the workgroup's
+// appends, whose results feed its list writes before the barrier), and the
+// last arrival of the last group reads and clears them.
+constexpr int NEST_CLOSE_GRID = 512;
+template <typename real>
+__global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real> n, const int* rects, int nrect,
+                                                    int ncells, const int* force, int nforce, int ntap, int slot) {
+    constexpr int NT = 256;
+    __shared__ real red[NT / 64];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, G = gridDim.x, grp = blockIdx.x % NSEG;
+    real vmax = real(0);
+    for (int t = blockIdx.x * NT + tid; t < ncells; t += G * NT) vmax = rmax(vmax, region_speed(a, rects, nrect, t));
+    const int gen = (int)a.ctrl->step + 1;
+    // whole workgroups take each round (the append votes per wave)
+    for (int t0 = blockIdx.x * NT; t0 < nforce; t0 += G * NT)
+        append_tiles(t0 + tid < nforce ? force[t0 + tid] : -1, 0, 0, gen, a.stamp, a.lists, a.hot, a.ntiles, slot,
+                     grp);
+    for (int t = blockIdx.x * NT + tid; t < ntap; t += G * NT) n.tap[t] = real(0);
+    vmax = wave_max(vmax);
+    if ((tid & 63) == 0) red[tid >> 6] = vmax;
+    __syncthreads();
+    unsigned long long* const h64 = reinterpret_cast<unsigned long long*>(a.hot);
+    if (tid == 0) {
+        real vm = real(0);
+        for (int q = 0; q < NT / 64; ++q) vm = rmax(vm, red[q]);
+        const unsigned long long sp = atomicMax(&h64[hot_spd(grp) / 2], (unsigned long long)__double_as_longlong((double)vm));
+        const int in_grp = (G - grp + NSEG - 1) / NSEG, ngrp = G < NSEG ? G : NSEG;
+        bool last = false;
+        if (sp != ~0ull) {        // always (no speed has these bits): waits for the maximum
+            const unsigned long long old = atomicAdd(&h64[hot_cnt(grp) / 2], 1ull);
+            if ((int)old == in_grp - 1)
+                last = atomicAdd((unsigned*)&a.hot[hot_done(NSEG)], 1u) == (unsigned)(ngrp - 1);
+        }
+        s_last = last;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid == 0) {
+        double S = 0.0;
+#pragma unroll
+        for (int g = 0; g < NSEG; ++g) S = fmax(S, __longlong_as_double((long long)h64[hot_spd(g) / 2]));
+        for (int g = 0; g < NSEG; ++g) { h64[hot_cnt(g) / 2] = 0ull; h64[hot_spd(g) / 2] = 0ull; }
+        a.hot[hot_done(NSEG)] = 0;
+        nest_tau_rule(a, n, slot, S);
     }
 }
 
