@@ -1634,8 +1634,9 @@ hipError_t nest_step_t(swe_nest_t* n) {
                            n->stream, na, pf, pc ^ 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int nforce = c->p.skip_dry ? n->nforce : 0;
-        const int work = std::max(n->nregion_cells, std::max(n->ntap, nforce));
-        const int grid = std::max(1, std::min(blocks_for(work, 256), swe::NEST_CLOSE_GRID));
+        const int blocks = std::max(blocks_for(n->nregion_cells, 256 * swe::NEST_CLOSE_CELLS),
+                                    std::max(blocks_for(n->ntap, 256), blocks_for(nforce, 256)));
+        const int grid = std::max(1, std::min(blocks, swe::NEST_CLOSE_GRID));
         hipLaunchKernelGGL(swe::k_nest_close<real>, dim3(grid), dim3(256), 0, n->stream, an, na, n->region,
                            n->nregion, n->nregion_cells, n->force_tiles, nforce, n->ntap, pc ^ 1);
         return hipGetLastError();

@@ -205,16 +205,21 @@ __global__ void k_feedback(NestArgs<real> n, int pf, int po) {
     n.Qyc[po][gc] = w ? n.Qyc[po][gc] + wm * dQy : real(0);
 }
 
-// CFL speed of the new coarse layer (buffers of a's input) at cell t of the
-// cells the feedback can change: each covered box widened by 2 cells (rects:
-// x0, y0, x1, y1, cell prefix); 0 for a dry cell.
-template <typename real>
-__device__ real region_speed(const Args<real>& a, const int* rects, int nrect, int t) {
+// Cell t of the cells the feedback can change: each covered box widened by
+// 2 cells (rects: x0, y0, x1, y1, cell prefix).
+__device__ __forceinline__ void region_cell(const int* rects, int nrect, int t, int& gx, int& gy) {
     int k = 0;
     for (int q = 1; q < nrect; ++q) k += t >= rects[5 * q + 4];
     const int* R = rects + 5 * k;
     const int m = t - R[4], w = R[2] - R[0];
-    const int gx = R[0] + m % w, gy = R[1] + m / w;
+    gx = R[0] + m % w;
+    gy = R[1] + m / w;
+}
+
+// CFL speed of the new coarse layer (buffers of a's input) at cell (gx, gy);
+// 0 for a dry cell.
+template <typename real>
+__device__ real region_speed(const Args<real>& a, int gx, int gy) {
     const real eps = a.eps;
     real Hs[5], ux[5], uy[5];
     const int ox[5] = {0, -1, 1, 0, 0}, oy[5] = {0, 0, 0, -1, 1};
@@ -310,7 +315,7 @@ __global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
 // issued only once the maximum has returned (so are the workgroup's
 // appends, whose results feed its list writes before the barrier), and the
 // last arrival of the last group reads and clears them.
-constexpr int NEST_CLOSE_GRID = 512;
+constexpr int NEST_CLOSE_GRID = 512, NEST_CLOSE_CELLS = 4;
 template <typename real>
 __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real> n, const int* rects, int nrect,
                                                     int ncells, const int* force, int nforce, int ntap, int slot) {
@@ -318,8 +323,23 @@ __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real>
     __shared__ real red[NT / 64];
     __shared__ int s_last;
     const int tid = threadIdx.x, G = gridDim.x, grp = blockIdx.x % NSEG;
+    // the region is mostly dry: the depths of U cells per thread are loaded
+    // together, and only a wet cell loads its neighbours
     real vmax = real(0);
-    for (int t = blockIdx.x * NT + tid; t < ncells; t += G * NT) vmax = rmax(vmax, region_speed(a, rects, nrect, t));
+    for (int t0 = blockIdx.x * NT * NEST_CLOSE_CELLS + tid; t0 < ncells; t0 += G * NT * NEST_CLOSE_CELLS) {
+        int gx[NEST_CLOSE_CELLS], gy[NEST_CLOSE_CELLS];
+        real hc[NEST_CLOSE_CELLS];
+#pragma unroll
+        for (int u = 0; u < NEST_CLOSE_CELLS; ++u) {
+            const int t = t0 + u * NT;
+            gx[u] = gy[u] = 0;
+            if (t < ncells) region_cell(rects, nrect, t, gx[u], gy[u]);
+            hc[u] = t < ncells ? a.Hi[gy[u] * a.nx + gx[u]] : real(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NEST_CLOSE_CELLS; ++u)
+            if (hc[u] > a.eps) vmax = rmax(vmax, region_speed(a, gx[u], gy[u]));
+    }
     const int gen = (int)a.ctrl->step + 1;
     // whole workgroups take each round (the append votes per wave)
     for (int t0 = blockIdx.x * NT; t0 < nforce; t0 += G * NT)
