@@ -328,12 +328,13 @@ typedef struct swe_nest_s swe_nest_t;
 
 /* Create a nest: the coarse grid as for swe_create (p: its parameters, the
  * patches inherit the physics; tile_x = tile_y = 0 required), refinement
- * 1 <= r <= 16 and npatch >= 1 patches.  Every box keeps
+ * 1 <= r <= 16 and 1 <= npatch <= 64 patches.  Every box keeps
  * ceil(SWE_NEST_FRAME / r) coarse cells from the domain edge, one uncovered
  * cell from every other box and from the inlet, and holds no closed gate
  * in it or its frame.  The coarse bed under a box should be the mean of the
- * fine bed (it is taken as given).  Patches step every tile (no dry
- * skipping).  NULL on error. */
+ * fine bed (it is taken as given).  Patches skip dry tiles when the coarse
+ * grid does (p->skip_dry), except the tiles holding their frame, which step
+ * every substep.  NULL on error. */
 swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const double* n_M,
                             const swe_params* p, int r, int feedback, int npatch,
                             const swe_patch* patches);

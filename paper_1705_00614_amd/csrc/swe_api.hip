@@ -1715,8 +1715,8 @@ extern "C" {
 swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const double* n_M, const swe_params* p,
                             int r, int feedback, int npatch, const swe_patch* patches) {
     g_err.clear();
-    if (!p || !b || !patches || npatch < 1 || r < 1 || r > 16) {
-        set_err("swe_nest_create: need params, bed, 1 <= r <= 16 and at least one patch"); return nullptr;
+    if (!p || !b || !patches || npatch < 1 || npatch > swe::NEST_MAX_PATCHES || r < 1 || r > 16) {
+        set_err("swe_nest_create: need params, bed, 1 <= r <= 16 and 1 to 64 patches"); return nullptr;
     }
     if (p->tile_x != 0 || p->tile_y != 0) { set_err("swe_nest_create: nests use the default tile shape"); return nullptr; }
     const int G = swe::NEST_FRAME, m = (G + r - 1) / r;

@@ -40,6 +40,8 @@
 namespace swe {
 
 constexpr int NEST_FRAME = 5;   // frame width in fine cells
+// patches of a nest at most (the time-step rule reads one per lane of a wave)
+constexpr int NEST_MAX_PATCHES = 64;
 // ring cells shallower than this [m] after the reflux take its mass but not
 // its momentum, twice as deep all of it, linear between (a film moving with
 // the patch's flow would set the nest's CFL step through the friction term
@@ -274,32 +276,72 @@ __global__ void k_nest_set_dt(Args<real> a, NestArgs<real> n, double tc) {
 }
 
 // Time steps of the next coarse step and its substeps; errors of any grid
-// stop all of them.  `slot` is the coarse list slot of the next step.
-// S_region: a speed maximum gathered besides the control block's.
+// stop all of them.  `slot` is the coarse list slot of the next step.  Run
+// by the first wave of a workgroup (threads 0..63), with every read of the
+// control blocks issued before the first write (two memory round trips, not
+// one per field and patch): lane k < np reads patch k's CFL step and error,
+// lane g < NSEG the coarse list's segment counter g; lane 0 then writes the
+// coarse control block and lane k patch k's steps.  With `region`, s_lane is
+// a speed maximum gathered besides the control block's, per lane (0 where
+// there is none).
 template <typename real>
-__device__ void nest_tau_rule(const Args<real>& a, const NestArgs<real>& n, int slot, double S_region) {
-    Ctrl* c = a.ctrl;
-    const double S = fmax(fmax(c->speed, prep_speed(c, real(0))), S_region);
-    c->prep_speed = 0ull;
-    c->speed = S;
-    double tc = cfl_tau_of(a, S);
-    for (int k = 0; k < n.np; ++k) tc = fmin(tc, (double)n.r * n.P[k].ctrl->tau_cfl);
-    set_nest_steps(a, n, n.hold > 0.0 ? n.hold : tc);
-    int e = c->err;
-    for (int k = 0; k < n.np; ++k)
-        if (!e && n.P[k].ctrl->err) e = n.P[k].ctrl->err;
-    if (a.skip) close_segments(c, a.hot, slot);
-    if (e) {
-        c->err = e;
-        c->err_gate = e;
-        for (int k = 0; k < n.np; ++k) n.P[k].ctrl->err_gate = e;
+__device__ void nest_tau_rule(const Args<real>& a, const NestArgs<real>& n, int slot, bool region, double s_lane) {
+    const int lane = threadIdx.x & 63;
+    Ctrl* const c = a.ctrl;
+    // reads
+    Ctrl* const pc = lane < n.np ? n.P[lane].ctrl : nullptr;
+    const double speed = c->speed, prep = prep_speed(c, real(0)), t = c->t;
+    const int cerr = c->err;
+    const int nseg = a.skip && lane < NSEG ? a.hot[hot_seg(slot, lane)] : 0;
+    const double tcf = pc ? (double)n.r * pc->tau_cfl : __builtin_inf();
+    const int perr = pc ? pc->err : 0;
+    // the rule: tau_c = min(CFL step of the coarse speeds, r * CFL step of
+    // every patch), unless held; min and max are exact in any order
+    double S = s_lane, tp = tcf;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        S = fmax(S, __shfl_xor(S, o, 64));
+        tp = fmin(tp, __shfl_xor(tp, o, 64));
+    }
+    S = region ? fmax(fmax(speed, prep), S) : fmax(speed, prep);
+    const double tc = fmin(cfl_tau_of(a, S), tp);
+    const double tcr = (double)(real)(n.hold > 0.0 ? n.hold : tc);
+    // the coarse step's scalars (set_next_step's rule) and the substeps'
+    const bool bad_step = !(tcr >= a.tau_min) || !(tcr < __builtin_inf());
+    double dV = 0.0;
+    if (a.nin_h2 > 0.0 && tcr < __builtin_inf())
+        dV = hydro_volume(a.q_base, a.q_peak, a.t_peak, a.sigma_t, t, tcr);
+    const double tf = (double)(real)(tcr / (double)n.r);
+    // the coarse grid's error after the step check, else the first patch's
+    int e = bad_step ? -5 : cerr;
+    const unsigned long long pm = __ballot(perr != 0);
+    const int pe = __shfl(perr, pm ? __ffsll((long long)pm) - 1 : 0, 64);
+    if (!e) e = pe;
+    int sg[NSEG];
+#pragma unroll
+    for (int g = 0; g < NSEG; ++g) sg[g] = __shfl(nseg, g, 64);
+    // writes
+    if (lane == 0) {
+        c->prep_speed = 0ull;
+        c->speed = S;
+        c->tau = tcr;
+        c->dV = dV;
+        c->sdepth = a.nin_h2 > 0.0 ? (double)(real)(dV / a.nin_h2) : 0.0;
+        if (a.skip) close_segments_from(c, sg, slot);
+        if (e) { c->err = e; c->err_gate = e; }
+    }
+    if (pc) {
+        pc->tau = tf;
+        pc->dV = 0.0;
+        pc->sdepth = 0.0;
+        if (e) pc->err_gate = e;
     }
 }
 
 template <typename real>
 __global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    nest_tau_rule(a, n, slot, 0.0);
+    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+    nest_tau_rule(a, n, slot, false, 0.0);
 }
 
 // The close of a two-way coarse step, one launch after k_feedback (at most
@@ -315,14 +357,17 @@ __global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
 // issued only once the maximum has returned (so are the workgroup's
 // appends, whose results feed its list writes before the barrier), and the
 // last arrival of the last group reads and clears them.
-constexpr int NEST_CLOSE_GRID = 512, NEST_CLOSE_CELLS = 4;
+constexpr int NEST_CLOSE_GRID = 1024, NEST_CLOSE_CELLS = 4;
 template <typename real>
 __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real> n, const int* rects, int nrect,
                                                     int ncells, const int* force, int nforce, int ntap, int slot) {
     constexpr int NT = 256;
     __shared__ real red[NT / 64];
     __shared__ int s_last;
+    __shared__ int s_rect[5 * NEST_MAX_PATCHES];
     const int tid = threadIdx.x, G = gridDim.x, grp = blockIdx.x % NSEG;
+    for (int i = tid; i < 5 * nrect; i += NT) s_rect[i] = rects[i];
+    __syncthreads();
     // the region is mostly dry: the depths of U cells per thread are loaded
     // together, and only a wet cell loads its neighbours
     real vmax = real(0);
@@ -333,7 +378,7 @@ __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real>
         for (int u = 0; u < NEST_CLOSE_CELLS; ++u) {
             const int t = t0 + u * NT;
             gx[u] = gy[u] = 0;
-            if (t < ncells) region_cell(rects, nrect, t, gx[u], gy[u]);
+            if (t < ncells) region_cell(s_rect, nrect, t, gx[u], gy[u]);
             hc[u] = t < ncells ? a.Hi[gy[u] * a.nx + gx[u]] : real(0);
         }
 #pragma unroll
@@ -366,13 +411,11 @@ __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real>
     __syncthreads();
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (tid == 0) {
-        double S = 0.0;
-#pragma unroll
-        for (int g = 0; g < NSEG; ++g) S = fmax(S, __longlong_as_double((long long)h64[hot_spd(g) / 2]));
-        for (int g = 0; g < NSEG; ++g) { h64[hot_cnt(g) / 2] = 0ull; h64[hot_spd(g) / 2] = 0ull; }
-        a.hot[hot_done(NSEG)] = 0;
-        nest_tau_rule(a, n, slot, S);
+    if (tid < 64) {
+        const double sg = tid < NSEG ? __longlong_as_double((long long)h64[hot_spd(tid) / 2]) : 0.0;
+        nest_tau_rule(a, n, slot, true, sg);
+        if (tid < NSEG) { h64[hot_cnt(tid) / 2] = 0ull; h64[hot_spd(tid) / 2] = 0ull; }
+        if (tid == 0) a.hot[hot_done(NSEG)] = 0;
     }
 }
 

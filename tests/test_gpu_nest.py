@@ -163,6 +163,23 @@ def test_nest_rejects_bad_layouts():
         swe.Nest(two)
 
 
+def test_nest_of_64_patches_matches_oracle_and_65_are_refused():
+    """The time-step rule reads one patch per lane of a wave: 64 patches
+    (every lane) follow the oracle nest; a 65th is refused at creation."""
+    sc = S.random_state(40, 40, seed=23, wet_frac=0.7, precision=64)
+    boxes = [(3 + 4 * (k % 8), 3 + 4 * (k // 8), 2, 2) for k in range(64)]
+    nest = S.nest(sc, boxes, r=2, seed=11, detail=0.3)
+    O = OracleNest(nest["coarse"], nest["patches"], r=2)
+    G = swe.Nest(nest)
+    G.run(10)
+    O.run(10)
+    assert abs(G.query()["time"] - O.time()) <= 1e-12 * O.time()
+    _compare(G, O, 64, label="64 patches")
+    more = S.nest(sc, boxes + [(3, 35, 2, 2)], r=2, seed=11, detail=0.3)
+    with pytest.raises(swe.SweError):
+        swe.Nest(more)
+
+
 @pytest.mark.parametrize("prec,vs_oracle,box", [(64, True, (20, 24, 44, 40)), (32, False, (20, 24, 44, 40)),
                                                  (64, True, (22, 26, 46, 38))])
 def test_patches_skip_dry_tiles_exactly(prec, vs_oracle, box):
