@@ -29,8 +29,9 @@
  *     swe_create returns NULL; the message is in swe_last_error().  After a
  *     device-side error (non-finite state, time-step collapse) the handle
  *     stops advancing until swe_set_state installs a new state.
- *   - Domain edges are reflective walls.  A closed gate (solid cell) is a
- *     permanently dry cell whose bed is far above any water level.
+ *   - Domain edges are reflective walls (periodic in x and y with
+ *     swe_params.periodic).  A closed gate (solid cell) is a permanently
+ *     dry cell whose bed is far above any water level.
  */
 #ifndef SWE_H
 #define SWE_H
@@ -301,11 +302,13 @@ int    swe_batch_autotune(int n, const int* nx, const int* ny, const double* dx,
  * cells.  Per coarse step the coarse grid steps with tau_c, every patch takes
  * r substeps of tau_c / r inside a frame of SWE_NEST_FRAME fine cells filled
  * from the coarse layers n and n+1 (linear in time; fine depth
- * max(0, H_c + b_c - b_fine) where the coarse cell is wet, else dry), and
- * with feedback the covered coarse cells take the mean of their fine cells
- * while the uncovered cells next to a box take the mismatch between the
- * coarse and the summed fine fluxes through their shared face (clamped as in
- * the final update).  tau_c = min(CFL step of the coarse layer as stepped and
+ * max(0, H_c + b_c - b_fine) where the coarse cell is wet, else dry, and
+ * fine discharge the fine depth times the coarse velocity), and with
+ * feedback the covered coarse cells take the mean of their fine cells while
+ * the uncovered cells next to a box take the mismatch between the coarse and
+ * the summed fine fluxes through their shared face (clamped as in the final
+ * update; its momentum part weighted by the cell's depth after it, 0 up to
+ * 5 cm, 1 from 10 cm, linear between).  tau_c = min(CFL step of the coarse layer as stepped and
  * of the cells the feedback changed, r * CFL step of every patch after its
  * last substep).  Without feedback (one-way zoom-in) the coarse grid runs as
  * if alone and drives the patches.  The paper names the method, not the
@@ -361,8 +364,9 @@ int    swe_nest_run_timed(swe_nest_t* n, long coarse_steps, double* kernel_ms);
 int    swe_nest_query(swe_nest_t* n, double* t, double* volume, double* inflow, double* ledger,
                       long* steps, double* dt_coarse, double* dt_fine);
 
-/* Processed cell-steps so far: coarse grid (active tiles) and all patch
- * substeps (every cell of the extended patches).  Either may be NULL. */
+/* Processed cell-steps so far: the in-domain cells of the tiles each step
+ * processed, of the coarse grid and of all patch substeps (extended patches:
+ * listed tiles and the tiles holding the frame).  Either may be NULL. */
 int    swe_nest_work(swe_nest_t* n, long long* coarse_cells, long long* fine_cells);
 
 /* Host FP64 copy of the coarse state (nx*ny each) or of patch k's interior
