@@ -288,7 +288,9 @@ __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsi
 // of the caller, plain locals so that they stay in VGPRs) provides the
 // input windows and the output writers:
 //   src.load(u, q0, q1, q2)    fetch unit u's input window,
-//   src.store(lds, q0, q1, q2) put it into the LDS plane (pixel stride 24),
+//   src.store(lds, q0, q1, q2) put it into the LDS plane (pixel stride 24)
+//                              and return this thread's vote to run the unit,
+//   src.source_near(c, oy0, ox0) whether the unit must run whatever the votes,
 //   src.writer(c, oy0, ox0) the last layer's writer for a block of crop c.
 // The next unit's window is fetched while the current one computes.
 template <int T, int NTH, class Src>
@@ -325,9 +327,14 @@ __device__ __forceinline__ void net_run(const Src& src, NetLds<T>& L, const unsi
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
         const int c = u / (ns * ns), sub = u % (ns * ns);
         const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
-        src.store(L.a, q0, q1, q2);
-        __syncthreads();
+        // a unit whose outputs no face would take is skipped (grid source:
+        // the block's cells and their face neighbours all at most the
+        // correction depth and none of them a source cell); its corrections
+        // keep older values, which the step never applies there
+        const int deep = src.store(L.a, q0, q1, q2);
+        const bool run = __syncthreads_or(deep) || src.source_near(c, oy0, ox0);
         if (u + (int)gridDim.x < units) src.load(u + gridDim.x, q0, q1, q2);
+        if (!run) continue;
         const NoWriter nw;
         net_layer<16, 32, false, W0, NTH>(L.a, N::P16, L.b, N::P32, L.w + wb_off(0), L.bias[0], 32, nw);
         __syncthreads();
@@ -372,10 +379,13 @@ struct CropSource {
             q1 = *reinterpret_cast<const uint4*>(xc + ((size_t)(oy0 + (k1 >> 1) / W0) * Sin + ox0 + (k1 >> 1) % W0) *
                                                           16 + 8 * (k1 & 1));
     }
-    __device__ __forceinline__ void store(unsigned short* a, const uint4& q0, const uint4& q1, const uint4&) const {
+    // returns 1: crops handed in are always run
+    __device__ __forceinline__ int store(unsigned short* a, const uint4& q0, const uint4& q1, const uint4&) const {
         *reinterpret_cast<uint4*>(a + (tid >> 1) * NetLds<T>::P16 + 8 * (tid & 1)) = q0;
         if (tid + NTH < XV) *reinterpret_cast<uint4*>(a + ((tid + NTH) >> 1) * NetLds<T>::P16 + 8 * (tid & 1)) = q1;
+        return 1;
     }
+    __device__ __forceinline__ bool source_near(int, int, int) const { return true; }
     __device__ __forceinline__ CropWriter writer(int c, int oy0, int ox0) const { return CropWriter{y, So, c, oy0, ox0}; }
 };
 
@@ -723,8 +733,13 @@ struct GridSource {
         __builtin_memcpy(q, v, sizeof v);
         q0 = q[0]; q1 = q[1]; q2 = q[2];
     }
-    __device__ __forceinline__ void store(unsigned short* lds, const uint4& q0, const uint4& q1, const uint4& q2) const {
-        if (tid >= W0 * W0) return;
+    // returns 1 if this window pixel is one of the block's output cells or
+    // their face neighbours (pixels HALO-1 .. HALO+T of each axis) and deeper
+    // than the correction depth: the step corrects a face only where its
+    // cells are (the stored depth is the depth after the Lagrangian stage
+    // except on source cells, which source_near covers)
+    __device__ __forceinline__ int store(unsigned short* lds, const uint4& q0, const uint4& q1, const uint4& q2) const {
+        if (tid >= W0 * W0) return 0;
         const uint4 q[3] = {q0, q1, q2};
         real v[6];
         __builtin_memcpy(v, q, sizeof v);
@@ -733,6 +748,17 @@ struct GridSource {
         const uint4 lo = {f[0] | ((unsigned)f[1] << 16), f[2] | ((unsigned)f[3] << 16), f[4] | ((unsigned)f[5] << 16), 0u};
         *reinterpret_cast<uint4*>(lds + tid * NetLds<T>::P16) = lo;
         *reinterpret_cast<uint4*>(lds + tid * NetLds<T>::P16 + 8) = uint4{0u, 0u, 0u, 0u};
+        const int px = tid % W0, py = tid / W0;
+        const bool near = px >= HALO - 1 && px <= HALO + T && py >= HALO - 1 && py <= HALO + T;
+        return near && v[0] > a->corr_hmin;
+    }
+    // whether the block's cells or their face neighbours meet the inlet
+    // rectangle (their depth after the Lagrangian stage includes the source)
+    __device__ __forceinline__ bool source_near(int c, int oy0, int ox0) const {
+        if (a->ni <= 0 || a->nj <= 0) return false;
+        const int tile = crop_tile(*a, slot, c);
+        const int x0 = (tile % a->ntx) * S - 2 + ox0, y0 = (tile / a->ntx) * S - 2 + oy0;   // first neighbour
+        return x0 < a->i0 + a->ni && a->i0 < x0 + T + 2 && y0 < a->j0 + a->nj && a->j0 < y0 + T + 2;
     }
     __device__ __forceinline__ CorrWriter<real> writer(int c, int oy0, int ox0) const {
         const int tile = crop_tile(*a, slot, c);
