@@ -182,6 +182,7 @@ struct swe_s {
     // learned flux corrections (east and north faces, 3 planes each)
     void* corrE = nullptr;
     void* corrN = nullptr;
+    int* claims = nullptr;      // unit claims of an attached network's pre-step, one per step parity
     bool corr = false;
     double corr_hmin = 0.0;
     // line taps (training labels): coarsening factor and buffers
@@ -366,7 +367,7 @@ void free_all(swe_t* s) {
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     void* ptrs[] = {s->Hb[0], s->Hb[1], s->Qxb[0], s->Qxb[1], s->Qyb[0], s->Qyb[1], s->bed, s->cf,
                     s->ctrl, s->hot, s->lists, s->stamp, s->wg_speed, s->wg_cells, s->mass, s->ledger,
-                    s->scalar, s->corrE, s->corrN, s->tapx, s->tapy, s->sigma, s->fmask, s->fvol};
+                    s->scalar, s->corrE, s->corrN, s->claims, s->tapx, s->tapy, s->sigma, s->fmask, s->fvol};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -1048,6 +1049,7 @@ static int ensure_corr_buffers(swe_t* s) {
     const size_t n = 3 * (size_t)s->nx * s->ny;
     HIPCHK(hipMalloc(&s->corrE, n * s->rsize));
     HIPCHK(hipMalloc(&s->corrN, n * s->rsize));
+    HIPCHK(hipMalloc((void**)&s->claims, 2 * sizeof(int)));
     HIPCHK(hipMemsetAsync(s->corrE, 0, n * s->rsize, s->stream));
     HIPCHK(hipMemsetAsync(s->corrN, 0, n * s->rsize, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -2480,7 +2482,7 @@ hipError_t lc_pre_step_t(swe_t* s, int par) {
         const int grid = (int)(units < c->net_blocks ? units : c->net_blocks);
         hipLaunchKernelGGL((L_::k_net_grid<NET_T, NET_NTH, real>), dim3(grid > 0 ? grid : 1), dim3(NET_NTH), 0,
                            s->stream, a, slot, S, c->dscale, c->dscale + 6, (real*)s->corrE, (real*)s->corrN, c->wf,
-                           c->params);
+                           c->params, s->claims);
         return hipGetLastError();
     }
     const int* cnt = s->p.skip_dry ? &s->ctrl->seg_off[slot][swe::NSEG] : nullptr;
@@ -2523,6 +2525,8 @@ int swe_lc_attach(swe_lc_t* c, swe_t* s) {
     HIPCHK(hipStreamSynchronize(c->stream));
     int rc = ensure_corr_buffers(s);
     if (rc) return rc;
+    HIPCHK(hipMemsetAsync(s->claims, 0, 2 * sizeof(int), s->stream));   // outside any captured graph
+    HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(s);
     s->lc = c;
     s->pre_step = lc_pre_step;

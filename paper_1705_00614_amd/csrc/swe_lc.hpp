@@ -291,13 +291,17 @@ __device__ __forceinline__ void net_layer(const unsigned short* in, int PI, unsi
 //   src.store(lds, q0, q1, q2) put it into the LDS plane (pixel stride 24)
 //                              and return this thread's vote to run the unit,
 //   src.source_near(c, oy0, ox0) whether the unit must run whatever the votes,
-//   src.writer(c, oy0, ox0) the last layer's writer for a block of crop c.
-// The next unit's window is fetched while the current one computes.
+//   src.writer(c, oy0, ox0) the last layer's writer for a block of crop c,
+//   src.begin()                once per workgroup, before anything else,
+//   src.claim(u)               (thread 0) the unit after u of this workgroup.
+// A workgroup's first unit is its index; the next unit's window is fetched
+// while the current one computes.
 template <int T, int NTH, class Src>
 __device__ __forceinline__ void net_run(const Src& src, NetLds<T>& L, const unsigned short* __restrict__ wf,
                                         const float* __restrict__ params, int So, int n) {
     using N = NetLds<T>;
     const int ns = (So + T - 1) / T, units = n * ns * ns;
+    src.begin();
     if ((int)blockIdx.x >= units) return;
     const int tid = threadIdx.x;
     constexpr int W0 = T + 2 * HALO;
@@ -324,7 +328,10 @@ __device__ __forceinline__ void net_run(const Src& src, NetLds<T>& L, const unsi
     }
     uint4 q0, q1, q2;
     src.load(blockIdx.x, q0, q1, q2);
-    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+    // the next unit's index, by iteration parity: thread 0 writes one slot
+    // before the vote's barrier while slow threads may still read the other
+    __shared__ int s_next[2];
+    for (int u = blockIdx.x, it = 0; u < units; ++it) {
         const int c = u / (ns * ns), sub = u % (ns * ns);
         const int oy0 = min((sub / ns) * T, So - T), ox0 = min((sub % ns) * T, So - T);
         // a unit whose outputs no face would take is skipped (grid source:
@@ -332,8 +339,11 @@ __device__ __forceinline__ void net_run(const Src& src, NetLds<T>& L, const unsi
         // correction depth and none of them a source cell); its corrections
         // keep older values, which the step never applies there
         const int deep = src.store(L.a, q0, q1, q2);
+        if (tid == 0) s_next[it & 1] = src.claim(u);
         const bool run = __syncthreads_or(deep) || src.source_near(c, oy0, ox0);
-        if (u + (int)gridDim.x < units) src.load(u + gridDim.x, q0, q1, q2);
+        const int next = s_next[it & 1];
+        if (next < units) src.load(next, q0, q1, q2);
+        u = next;
         if (!run) continue;
         const NoWriter nw;
         net_layer<16, 32, false, W0, NTH>(L.a, N::P16, L.b, N::P32, L.w + wb_off(0), L.bias[0], 32, nw);
@@ -386,6 +396,8 @@ struct CropSource {
         return 1;
     }
     __device__ __forceinline__ bool source_near(int, int, int) const { return true; }
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ int claim(int u) const { return u + (int)gridDim.x; }   // a fixed stride
     __device__ __forceinline__ CropWriter writer(int c, int oy0, int ox0) const { return CropWriter{y, So, c, oy0, ox0}; }
 };
 
@@ -715,6 +727,15 @@ struct GridSource {
     real* corrE;
     real* corrN;
     const float* oscale;
+    // units after the first are claimed from claims[slot] (workgroups that
+    // run blocks take fewer); the pre-step of the next step, which uses the
+    // other slot, finds that one cleared by this launch (both are zero when
+    // the network is attached)
+    int* claims;
+    __device__ __forceinline__ void begin() const {
+        if (blockIdx.x == 0 && tid == 0) claims[slot ^ 1] = 0;
+    }
+    __device__ __forceinline__ int claim(int) const { return atomicAdd(&claims[slot], 1) + (int)gridDim.x; }
     __device__ __forceinline__ int origin(int u, int& tile, int& oy0, int& ox0) const {
         const int c = u / (ns * ns), sub = u % (ns * ns);
         oy0 = min((sub / ns) * T, So - T);
@@ -775,11 +796,11 @@ template <int T, int NTH, typename real>
 __global__ __launch_bounds__(NTH) void k_net_grid(Args<real> a, int slot, int S, const float* __restrict__ iscale,
                                                   const float* __restrict__ oscale, real* __restrict__ corrE,
                                                   real* __restrict__ corrN, const unsigned short* __restrict__ wf,
-                                                  const float* __restrict__ params) {
+                                                  const float* __restrict__ params, int* __restrict__ claims) {
     __shared__ NetLds<T> L;
     const int So = S + 1;
     const GridSource<T, NTH, real> src{&a, slot, S, So, (So + T - 1) / T, (int)threadIdx.x, iscale, corrE, corrN,
-                                       oscale};
+                                       oscale, claims};
     const int n = a.skip ? a.ctrl->seg_off[slot][NSEG] : a.ntiles;
     net_run<T, NTH>(src, L, wf, params, So, n);
 }
