@@ -304,27 +304,71 @@ def test_fused_pre_step_equals_gather_forward_scatter(size, hmin):
     net.attach(A)
     for g in (A, B):
         g.set_correction_depth(hmin)
-    ny, nx, ntx = sc["ny"], sc["nx"], -(-sc["nx"] // T)
-    os32 = out_scale.astype(np.float32)
     for step in range(6):
-        x, tiles = net.gather(B)
-        assert len(tiles) > 0
-        out = net.forward(x)
-        dE, dN = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
-        for p, t in enumerate(tiles):
-            gx = (t % ntx) * T - 1 + np.arange(T + 1)
-            gy = (t // ntx) * T - 1 + np.arange(T + 1)
-            ix, iy = (gx >= 0) & (gx < nx), (gy >= 0) & (gy < ny)
-            v = (out[p].astype(np.float32) * os32).astype(np.float64)[np.ix_(iy, ix)]
-            for c in range(3):
-                dE[c][np.ix_(gy[iy], gx[ix])] = v[..., c]
-                dN[c][np.ix_(gy[iy], gx[ix])] = v[..., 3 + c]
-        B.set_correction(dE, dN)
+        _host_corrections(net, B, out_scale)
         A.run(1)
         B.run(1)
         for fa, fb in zip(A.state(), B.state()):
             assert np.array_equal(fa, fb), step
     net.detach(A)
+
+
+def _host_corrections(net, g, out_scale):
+    """Hand grid g the corrections an attached network would use before its
+    next step, computed in separate calls: its crops, the layer-by-layer
+    forward, placed on the host as the scatter places them (FP32 product of
+    output and scale; every gathered tile)."""
+    x, tiles = net.gather(g)
+    assert len(tiles) > 0
+    out = net.forward(x)
+    ny, nx = g.ny, g.nx
+    T = g.work()["tile"][0]
+    ntx = -(-nx // T)
+    os32 = np.asarray(out_scale).astype(np.float32)
+    dE, dN = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
+    for p, t in enumerate(tiles):
+        gx = (t % ntx) * T - 1 + np.arange(T + 1)
+        gy = (t // ntx) * T - 1 + np.arange(T + 1)
+        ix, iy = (gx >= 0) & (gx < nx), (gy >= 0) & (gy < ny)
+        v = (out[p].astype(np.float32) * os32).astype(np.float64)[np.ix_(iy, ix)]
+        for c in range(3):
+            dE[c][np.ix_(gy[iy], gx[ix])] = v[..., c]
+            dN[c][np.ix_(gy[iy], gx[ix])] = v[..., 3 + c]
+    g.set_correction(dE, dN)
+
+
+def test_reattached_network_starts_afresh():
+    """The fused pre-step hands out units from a counter per step parity,
+    each launch clearing the other parity's; attaching clears both, so a
+    network detached after an odd number of steps and attached again still
+    computes every unit it needs: the grid stays bitwise equal to a twin
+    given host-placed corrections while attached and none while detached."""
+    sc = _bench_coarse()
+    W, b = LN.init_params(29)
+    rng = np.random.default_rng(6)
+    b = [rng.normal(scale=0.05, size=v.shape) for v in b]
+    out_scale = OUT_SCALE * 0.1
+    A, B = swe.Solver(sc), swe.Solver(sc)
+    A.run(20)
+    B.run(20)
+    net = swe.Net(A.work()["tile"][0], A.work()["ntiles"], IN_SCALE, out_scale)
+    net.set_params(swe.lc_pack(W, b))
+    for g in (A, B):
+        g.set_correction_depth(1.0)
+    for attached, steps in ((True, 3), (False, 2), (True, 4)):
+        if attached:
+            net.attach(A)
+        for k in range(steps):
+            if attached:
+                _host_corrections(net, B, out_scale)
+            else:
+                B.set_correction(None, None)
+            A.run(1)
+            B.run(1)
+            for fa, fb in zip(A.state(), B.state()):
+                assert np.array_equal(fa, fb), (attached, k)
+        if attached:
+            net.detach(A)
 
 
 # ---------------------------------------------------------------- training data
