@@ -46,9 +46,6 @@ void set_hip_err(const char* where, hipError_t e) {
     } while (0)
 
 constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even)
-// counters of an attached network's unit claims: 2 step parities x 8 groups,
-// one per 256-byte line
-constexpr size_t CLAIM_INTS = 2 * 8 * 64;
 
 struct Launcher {
     int tx, ty, nt, precision, limiter;
@@ -185,7 +182,7 @@ struct swe_s {
     // learned flux corrections (east and north faces, 3 planes each)
     void* corrE = nullptr;
     void* corrN = nullptr;
-    int* claims = nullptr;      // unit claims of an attached network's pre-step (CLAIM_INTS ints)
+    int* claims = nullptr;      // unit claims of an attached network's pre-step, one per step parity
     bool corr = false;
     double corr_hmin = 0.0;
     // line taps (training labels): coarsening factor and buffers
@@ -1052,7 +1049,7 @@ static int ensure_corr_buffers(swe_t* s) {
     const size_t n = 3 * (size_t)s->nx * s->ny;
     HIPCHK(hipMalloc(&s->corrE, n * s->rsize));
     HIPCHK(hipMalloc(&s->corrN, n * s->rsize));
-    HIPCHK(hipMalloc((void**)&s->claims, CLAIM_INTS * sizeof(int)));
+    HIPCHK(hipMalloc((void**)&s->claims, 2 * sizeof(int)));
     HIPCHK(hipMemsetAsync(s->corrE, 0, n * s->rsize, s->stream));
     HIPCHK(hipMemsetAsync(s->corrN, 0, n * s->rsize, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -2081,8 +2078,6 @@ int swe_nest_get_patch(swe_nest_t* n, int k, double* H, double* Qx, double* Qy) 
 // ====================================================================== learned coarse correction
 
 #include "swe_lc.hpp"
-static_assert(CLAIM_INTS == 2 * swe::lc::CLAIM_GROUPS * swe::lc::CLAIM_STRIDE,
-              "claim counters: two step parities of the pre-step's counter groups");
 
 struct swe_lc_s {
     int S = 32, So = 33, max_crops = 0;   // grid tile side; network output side S + 1
@@ -2530,7 +2525,7 @@ int swe_lc_attach(swe_lc_t* c, swe_t* s) {
     HIPCHK(hipStreamSynchronize(c->stream));
     int rc = ensure_corr_buffers(s);
     if (rc) return rc;
-    HIPCHK(hipMemsetAsync(s->claims, 0, CLAIM_INTS * sizeof(int), s->stream));   // outside any captured graph
+    HIPCHK(hipMemsetAsync(s->claims, 0, 2 * sizeof(int), s->stream));   // outside any captured graph
     HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(s);
     s->lc = c;

@@ -31,8 +31,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NL = 4;                         // layers
 constexpr int HALO = NL;                      // crop margin
-// unit claims of the grid pre-step: counter groups, ints between counters
-constexpr int CLAIM_GROUPS = 8, CLAIM_STRIDE = 64;
 constexpr int CIN[NL] = {16, 32, 32, 32};     // padded input channels
 constexpr int COUT[NL] = {32, 32, 32, 16};    // padded output channels
 constexpr int CIN_REAL[NL] = {6, 32, 32, 32};
@@ -729,24 +727,15 @@ struct GridSource {
     real* corrE;
     real* corrN;
     const float* oscale;
-    // Units after the first are claimed (workgroups that run blocks take
-    // fewer).  Units u = g (mod CLAIM_GROUPS) form group g: the workgroups
-    // b = g (mod CLAIM_GROUPS) take its first units, one each, and claim
-    // the rest from the group's counter (one per 256-byte line, so that the
-    // groups' atomics do not queue behind each other), claims[(slot *
-    // CLAIM_GROUPS + g) * CLAIM_STRIDE].  The pre-step of the next step, which
-    // uses the other slot, finds its counters cleared by this launch (all
-    // are zero when the network is attached).
+    // units after the first are claimed from claims[slot] (workgroups that
+    // run blocks take fewer); the pre-step of the next step, which uses the
+    // other slot, finds that one cleared by this launch (both are zero when
+    // the network is attached)
     int* claims;
     __device__ __forceinline__ void begin() const {
-        if (blockIdx.x == 0 && tid < CLAIM_GROUPS) claims[((slot ^ 1) * CLAIM_GROUPS + tid) * CLAIM_STRIDE] = 0;
+        if (blockIdx.x == 0 && tid == 0) claims[slot ^ 1] = 0;
     }
-    __device__ __forceinline__ int claim(int u) const {
-        const int g = u % CLAIM_GROUPS, G = (int)gridDim.x;
-        const int first = (G - g + CLAIM_GROUPS - 1) / CLAIM_GROUPS;   // the group's statically taken units
-        const int k = atomicAdd(&claims[(slot * CLAIM_GROUPS + g) * CLAIM_STRIDE], 1) + first;
-        return g + CLAIM_GROUPS * k;
-    }
+    __device__ __forceinline__ int claim(int) const { return atomicAdd(&claims[slot], 1) + (int)gridDim.x; }
     __device__ __forceinline__ int origin(int u, int& tile, int& oy0, int& ox0) const {
         const int c = u / (ns * ns), sub = u % (ns * ns);
         oy0 = min((sub / ns) * T, So - T);
