@@ -368,8 +368,8 @@ __global__ __launch_bounds__(256) void k_nest_close(Args<real> a, NestArgs<real>
     const int tid = threadIdx.x, G = gridDim.x, grp = blockIdx.x % NSEG;
     for (int i = tid; i < 5 * nrect; i += NT) s_rect[i] = rects[i];
     __syncthreads();
-    // the region is mostly dry: the depths of U cells per thread are loaded
-    // together, and only a wet cell loads its neighbours
+    // the region is mostly dry: the depths of NEST_CLOSE_CELLS cells per
+    // thread are loaded together, and only a wet cell loads its neighbours
     real vmax = real(0);
     for (int t0 = blockIdx.x * NT * NEST_CLOSE_CELLS + tid; t0 < ncells; t0 += G * NT * NEST_CLOSE_CELLS) {
         int gx[NEST_CLOSE_CELLS], gy[NEST_CLOSE_CELLS];
