@@ -1522,10 +1522,12 @@ struct swe_nest_s {
     long long launched = 0;          // coarse steps launched
     hipGraphExec_t graph = nullptr;
     std::vector<unsigned char> nargs;   // NestArgs<real>
-    // patches 1.. step on side streams (default priority), forked from and
-    // joined back into the nest's stream around each substep
+    // one side stream per patch (default priority): the first substep of
+    // every patch runs beside the coarse step, later substeps of patches 1..
+    // beside patch 0; forked from and joined back into the nest's stream
     std::vector<hipStream_t> side;
     hipEvent_t fork = nullptr;
+    hipEvent_t frame0 = nullptr;     // the first substep's frame is written
     std::vector<hipEvent_t> join;
 };
 
@@ -1535,6 +1537,7 @@ void free_nest(swe_nest_t* n) {
     if (n->graph) (void)hipGraphExecDestroy(n->graph);
     for (hipStream_t q : n->side) if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
     if (n->fork) (void)hipEventDestroy(n->fork);
+    if (n->frame0) (void)hipEventDestroy(n->frame0);
     for (hipEvent_t e : n->join) if (e) (void)hipEventDestroy(e);
     for (swe_t* q : n->p) if (q) swe_destroy(q);
     if (n->c) swe_destroy(n->c);
@@ -1604,27 +1607,39 @@ hipError_t nest_step_t(swe_nest_t* n) {
                            n->stream, (real*)n->tap, n->ntap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // Substep 0 takes its frame from layer n alone, so it runs beside the
+    // coarse step: its frame and every patch's first step on side streams
+    // forked before the coarse step and joined back before the next frame.
+    // Later substeps need layer n+1: frame on the nest's stream, patch 0
+    // there too, the others on side streams between a fork and a join.
+    const int np = (int)n->p.size();
+    if ((e = hipEventRecord(n->fork, n->stream)) != hipSuccess) return e;
+    for (int k = 0; k < np; ++k)
+        if ((e = hipStreamWaitEvent(n->side[k], n->fork, 0)) != hipSuccess) return e;
     if ((e = launch_grid_step(c, pc)) != hipSuccess) return e;
     c->launched++;
     for (int s = 0; s < n->r; ++s) {
         const int pf = (int)(n->p[0]->launched & 1);
-        hipLaunchKernelGGL(swe::k_frame<real>, dim3(blocks_for(na.nframe, 256)), dim3(256), 0, n->stream, na, pf, pc,
-                           (real)((double)s / (double)n->r));
+        const bool first = s == 0;
+        hipLaunchKernelGGL(swe::k_frame<real>, dim3(blocks_for(na.nframe, 256)), dim3(256), 0,
+                           first ? n->side[0] : n->stream, na, pf, pc, (real)((double)s / (double)n->r));
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // the patches are independent within a substep: patch 0 on the
-        // nest's stream, the others on side streams between a fork and a join
-        const int np = (int)n->p.size();
-        if (np > 1) {
+        if (first) {   // the other patches' first step waits for the frame
+            if ((e = hipEventRecord(n->frame0, n->side[0])) != hipSuccess) return e;
+            for (int k = 1; k < np; ++k)
+                if ((e = hipStreamWaitEvent(n->side[k], n->frame0, 0)) != hipSuccess) return e;
+        } else if (np > 1) {
             if ((e = hipEventRecord(n->fork, n->stream)) != hipSuccess) return e;
             for (int k = 1; k < np; ++k)
                 if ((e = hipStreamWaitEvent(n->side[k], n->fork, 0)) != hipSuccess) return e;
         }
         for (int k = 0; k < np; ++k) {
             swe_t* q = n->p[k];
-            if ((e = launch_grid_step(q, pf, nullptr, nullptr, k ? n->side[k] : nullptr)) != hipSuccess) return e;
+            hipStream_t st = first || k ? n->side[k] : nullptr;   // nullptr: the nest's stream
+            if ((e = launch_grid_step(q, pf, nullptr, nullptr, st)) != hipSuccess) return e;
             q->launched++;
         }
-        for (int k = 1; k < np; ++k) {
+        for (int k = first ? 0 : 1; k < np; ++k) {
             if ((e = hipEventRecord(n->join[k], n->side[k])) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(n->stream, n->join[k], 0)) != hipSuccess) return e;
         }
@@ -1906,12 +1921,11 @@ swe_nest_t* swe_nest_create(int nx, int ny, double dx, const double* b, const do
     }
     n->side.assign(npatch, nullptr);
     n->join.assign(npatch, nullptr);
-    if (npatch > 1) {
-        NK(hipEventCreateWithFlags(&n->fork, hipEventDisableTiming));
-        for (int k = 1; k < npatch; ++k) {
-            NK(hipStreamCreateWithFlags(&n->side[k], hipStreamNonBlocking));
-            NK(hipEventCreateWithFlags(&n->join[k], hipEventDisableTiming));
-        }
+    NK(hipEventCreateWithFlags(&n->fork, hipEventDisableTiming));
+    NK(hipEventCreateWithFlags(&n->frame0, hipEventDisableTiming));
+    for (int k = 0; k < npatch; ++k) {
+        NK(hipStreamCreateWithFlags(&n->side[k], hipStreamNonBlocking));
+        NK(hipEventCreateWithFlags(&n->join[k], hipEventDisableTiming));
     }
     int rc = 0;
     if (n->precision == 32) {

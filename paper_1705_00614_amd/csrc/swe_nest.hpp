@@ -116,16 +116,19 @@ __global__ void k_frame(NestArgs<real> n, int pf, int pc, real theta) {
     }
     const int ci = d.ci0 + floor_div(fi - G, n.r), cj = d.cj0 + floor_div(fj - G, n.r);
     const int gc = cj * n.nx + ci, gf = fj * nxe + fi;
+    // at theta = 0 the frame is layer n alone (layer n+1 may still be being
+    // computed beside this launch): both terms take layer n's value
+    const int pn = theta > real(0) ? pc ^ 1 : pc;
     const real u = real(1) - theta;
-    const real Hm = u * n.Hc[pc][gc] + theta * n.Hc[pc ^ 1][gc];
+    const real Hm = u * n.Hc[pc][gc] + theta * n.Hc[pn][gc];
     const bool w = Hm > n.eps;
     const real eta = Hm + n.bc[gc];
     const real Hf = w ? rmax(real(0), eta - d.bf[gf]) : real(0);
     d.Hf[pf][gf] = Hf;
     // the coarse velocity carried by the fine depth (not the coarse
     // discharge, which on a high spot of the fine bed would be a fast film)
-    d.Qxf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qxc[pc][gc] + theta * n.Qxc[pc ^ 1][gc], Hm) : real(0);
-    d.Qyf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qyc[pc][gc] + theta * n.Qyc[pc ^ 1][gc], Hm) : real(0);
+    d.Qxf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qxc[pc][gc] + theta * n.Qxc[pn][gc], Hm) : real(0);
+    d.Qyf[pf][gf] = w ? Hf * Mth<real>::div(u * n.Qyc[pc][gc] + theta * n.Qyc[pn][gc], Hm) : real(0);
 }
 
 // Restriction of the fine layer (patch buffers pf) into the covered coarse
