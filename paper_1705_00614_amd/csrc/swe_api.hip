@@ -1600,13 +1600,7 @@ hipError_t nest_step_t(swe_nest_t* n) {
     swe_t* c = n->c;
     const int pc = (int)(c->launched & 1);
     hipError_t e;
-    // with feedback the previous close cleared the taps (and creation did)
-    if (!n->feedback) {
-        hipLaunchKernelGGL(swe::k_nest_zero<real>,
-                           dim3(blocks_for(n->ntap, 256) < 1024 ? blocks_for(n->ntap, 256) : 1024), dim3(256), 0,
-                           n->stream, (real*)n->tap, n->ntap);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    // The previous close cleared the taps (creation did for the first step).
     // Substep 0 takes its frame from layer n alone, so it runs beside the
     // coarse step: its frame and every patch's first step on side streams
     // forked before the coarse step and joined back before the next frame.
@@ -1658,7 +1652,9 @@ hipError_t nest_step_t(swe_nest_t* n) {
                            n->nregion, n->nregion_cells, n->force_tiles, nforce, n->ntap, pc ^ 1);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, an, na, pc ^ 1);
+    const int tb = blocks_for(n->ntap, 256);
+    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(tb < 1 ? 1 : tb > 1024 ? 1024 : tb), dim3(256), 0, n->stream, an,
+                       na, pc ^ 1, n->ntap);
     return hipGetLastError();
 }
 
@@ -1680,7 +1676,7 @@ int nest_init_tau(swe_nest_t* n) {
         if (rc) return rc;
     }
     const Args<real>& a = *(const Args<real>*)n->c->args[pc].data();
-    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, a, na, pc);
+    hipLaunchKernelGGL(swe::k_nest_tau<real>, dim3(1), dim3(64), 0, n->stream, a, na, pc, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(n->stream));
     return 0;

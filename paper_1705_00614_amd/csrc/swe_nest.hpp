@@ -26,7 +26,8 @@
 //            gathers the CFL speed of the changed cells, puts the tiles
 //            round the covered boxes on the coarse tile list and clears the
 //            taps, its last workgroup setting the steps as below
-//   tau      (k_nest_tau without feedback) tau_c = min(CFL step of the
+//   tau      (k_nest_tau without feedback, which also clears the taps)
+//            tau_c = min(CFL step of the
 //            coarse speeds, r * CFL step of every patch after its last
 //            substep), tau_f = tau_c / r, and the coarse hydrograph volume of
 //            the next step.
@@ -87,11 +88,6 @@ __device__ __forceinline__ int find_patch(const NestPatch<real>* P, int np, int 
     return k;
 }
 
-// Zero the taps at the start of a coarse step.
-template <typename real>
-__global__ void k_nest_zero(real* tap, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tap[i] = real(0);
-}
 
 // Frame of every patch at time theta in [0, 1) of the coarse step, written to
 // the patch buffers pf; the coarse layers n and n+1 are in buffers pc, pc^1.
@@ -341,8 +337,12 @@ __device__ void nest_tau_rule(const Args<real>& a, const NestArgs<real>& n, int 
     }
 }
 
+// The close of a coarse step without feedback: the step rule (first wave
+// of block 0) and the taps cleared for the next coarse step (every thread,
+// striding; ntap = 0 leaves them).
 template <typename real>
-__global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot) {
+__global__ void k_nest_tau(Args<real> a, NestArgs<real> n, int slot, int ntap) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntap; i += gridDim.x * blockDim.x) n.tap[i] = real(0);
     if (blockIdx.x != 0 || threadIdx.x >= 64) return;
     nest_tau_rule(a, n, slot, false, 0.0);
 }
